@@ -27,7 +27,7 @@ def build(force=True):
     if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= os.path.getmtime(_SRC):
         return _SO
     tmp = _SO + ".tmp"
-    cmd = ["g++", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c++17", "-o", tmp, _SRC]
+    cmd = ["g++", "-O2", "-mfma", "-ffp-contract=off", "-fPIC", "-shared", "-std=c++17", "-o", tmp, _SRC]
     subprocess.check_call(cmd, cwd=_HERE)
     os.replace(tmp, _SO)
     return _SO
@@ -67,6 +67,8 @@ def lib():
         L.oracle_pivots.argtypes = [vp, i32, i32, vp, vp]
         L.oracle_pivots.restype = i32
         L.oracle_perm.argtypes = [vp, vp]
+        L.oracle_nnca_U.argtypes = [vp, i32, i32, vp]
+        L.oracle_nnca_U.restype = i32
         L.oracle_dense_extended.argtypes = [vp, P(i64), vp, vp]
         L.oracle_dense_extended.restype = i32
         L.oracle_factor.argtypes = [vp]
@@ -75,6 +77,8 @@ def lib():
         L.oracle_solve.restype = i32
         L.oracle_trace.argtypes = [vp, vp, i64]
         L.oracle_trace.restype = i64
+        L.oracle_trace_ranks.argtypes = [vp, vp, vp, i64]
+        L.oracle_trace_ranks.restype = i64
         L.oracle_lists.argtypes = [vp, i32, i32, vp, vp]
         L.oracle_lists.restype = i32
         L.oracle_far_fill_count.argtypes = [vp]
@@ -207,6 +211,12 @@ class System:
         k = lib().oracle_pivots(self.h, level, box, _p(t), _p(s))
         return t[:k].copy(), s[:k].copy()
 
+    def nnca_U(self, level, box):
+        k = int(self.nnca_ranks(level)[box])
+        out = np.zeros(4096 * max(k, 1))
+        m = lib().oracle_nnca_U(self.h, level, box, _p(out))
+        return out[: m * k].reshape(m, k)
+
     def perm(self):
         p = np.zeros(self.N, np.int64)
         lib().oracle_perm(self.h, _p(p))
@@ -240,6 +250,13 @@ class System:
         out = np.zeros((max(n, 1), 4), np.int32)
         lib().oracle_trace(self.h, _p(out), n)
         return out[:n]
+
+    def trace_ranks(self):
+        n = lib().oracle_trace(self.h, None, 0)
+        rk = np.zeros((max(n, 1), 6), np.int32)
+        ra = np.zeros((max(n, 1), 8))
+        lib().oracle_trace_ranks(self.h, _p(rk), _p(ra), n)
+        return rk[:n], ra[:n]
 
     def lists(self, level, box):
         nb = np.zeros(64, np.int32)

@@ -42,7 +42,7 @@ Mat mul(const Mat& A, const Mat& B, int counter = -1) {
     for (int k = 0; k < A.c; ++k) {
       double aik = A.at(i, k);
       if (aik == 0.0) continue;
-      for (int j = 0; j < B.c; ++j) C.at(i, j) += aik * B.at(k, j);
+      for (int j = 0; j < B.c; ++j) C.at(i, j) = std::fma(aik, B.at(k, j), C.at(i, j));
     }
   if (counter >= 0) g_flops[counter] += 2.0 * A.r * A.c * B.c;
   return C;
@@ -87,7 +87,7 @@ int lu_factor(Mat& A, std::vector<int>& perm) {
     for (int i = k + 1; i < n; ++i) {
       double l = A.at(i, k) / piv;
       A.at(i, k) = l;
-      for (int j = k + 1; j < n; ++j) A.at(i, j) -= l * A.at(k, j);
+      for (int j = k + 1; j < n; ++j) A.at(i, j) = std::fma(-l, A.at(k, j), A.at(i, j));
     }
   }
   g_flops[0] += 2.0 * n * n * n / 3.0;
@@ -103,13 +103,13 @@ Mat lu_solve(const Mat& LU, const std::vector<int>& perm, const Mat& B, int coun
     for (int k = 0; k < i; ++k) {
       double l = LU.at(i, k);
       if (l == 0.0) continue;
-      for (int j = 0; j < m; ++j) X.at(i, j) -= l * X.at(k, j);
+      for (int j = 0; j < m; ++j) X.at(i, j) = std::fma(-l, X.at(k, j), X.at(i, j));
     }
   for (int i = n - 1; i >= 0; --i) {
     for (int k = i + 1; k < n; ++k) {
       double u = LU.at(i, k);
       if (u == 0.0) continue;
-      for (int j = 0; j < m; ++j) X.at(i, j) -= u * X.at(k, j);
+      for (int j = 0; j < m; ++j) X.at(i, j) = std::fma(-u, X.at(k, j), X.at(i, j));
     }
     double d = LU.at(i, i);
     for (int j = 0; j < m; ++j) X.at(i, j) /= d;
@@ -119,8 +119,8 @@ Mat lu_solve(const Mat& LU, const std::vector<int>& perm, const Mat& B, int coun
 }
 
 // Householder QR with column pivoting (Q10 reading of the RRQR with threshold eps_A,
-// Sec. 3.2.1): trailing column norms recomputed exactly every step, ties to the lowest
-// column, stop at the smallest k with |R_{k+1,k+1}| <= tol |R_11|.
+// Sec. 3.2.1): trailing column norms recomputed exactly every step, ties (within a relative
+// 1e-11) to the lowest column, stop at the smallest k with |R_{k+1,k+1}| <= tol |R_11|.
 struct Cpqr {
   int rank = 0;
   int m = 0;
@@ -131,6 +131,8 @@ struct Cpqr {
   double kept = 0.0;   // |R_kk| / (tol |R_11|) of the last kept pivot
   double next = 0.0;   // |R_{k+1,k+1}| / (tol |R_11|) of the first rejected pivot (0 if none)
 };
+
+const double kTieTol = 1e-11;
 
 Cpqr cpqr(const Mat& M, double tol) {
   Cpqr out;
@@ -143,14 +145,21 @@ Cpqr cpqr(const Mat& M, double tol) {
   int s = 0;
   int smax = std::min(m, n);
   for (; s < smax; ++s) {
-    int p = -1;
-    double best = -1.0;
+    // pivot: the lowest-index column whose trailing norm is within a relative 1e-11 of the
+    // largest (norms that equal in exact arithmetic, as the columns of an orthonormal basis
+    // block, count as ties whatever their rounding)
+    std::vector<double> nrm(n, 0.0);
+    double mx = -1.0;
     for (int j = s; j < n; ++j) {
       double t = 0.0;
-      for (int i = s; i < m; ++i) t += A.at(i, j) * A.at(i, j);
-      double nrm = std::sqrt(t);
-      if (nrm > best) { best = nrm; p = j; }
+      for (int i = s; i < m; ++i) t = std::fma(A.at(i, j), A.at(i, j), t);
+      nrm[j] = std::sqrt(t);
+      mx = std::max(mx, nrm[j]);
     }
+    int p = s;
+    for (int j = s; j < n; ++j)
+      if (nrm[j] >= mx * (1.0 - kTieTol)) { p = j; break; }
+    double best = nrm[p];
     if (s == 0) {
       r11 = best;
       if (r11 == 0.0) break;
@@ -177,9 +186,9 @@ Cpqr cpqr(const Mat& M, double tol) {
     }
     for (int j = s + 1; j < n; ++j) {
       double w = 0.0;
-      for (int i = s; i < m; ++i) w += v[i] * A.at(i, j);
+      for (int i = s; i < m; ++i) w = std::fma(v[i], A.at(i, j), w);
       w *= tau;
-      for (int i = s; i < m; ++i) A.at(i, j) -= w * v[i];
+      for (int i = s; i < m; ++i) A.at(i, j) = std::fma(-w, v[i], A.at(i, j));
     }
     A.at(s, s) = beta;
     for (int i = s + 1; i < m; ++i) A.at(i, s) = 0.0;
@@ -204,13 +213,38 @@ Mat cpqr_q(const Cpqr& f, int q) {
     double tau = f.tau[s];
     for (int j = 0; j < q; ++j) {
       double w = 0.0;
-      for (int i = s; i < m; ++i) w += v[i] * Q.at(i, j);
+      for (int i = s; i < m; ++i) w = std::fma(v[i], Q.at(i, j), w);
       w *= tau;
-      for (int i = s; i < m; ++i) Q.at(i, j) -= w * v[i];
+      for (int i = s; i < m; ++i) Q.at(i, j) = std::fma(-w, v[i], Q.at(i, j));
     }
   }
   g_flops[3] += 4.0 * m * q * f.rank;
   return Q;
+}
+
+// e^x by Cody-Waite reduction x = k ln2 + r, |r| <= ln2/2 (ln2 split in a high part with
+// trailing zero bits and a low correction), the Taylor series of e^r to degree 13 in Horner
+// form (truncation below 4e-18 relative on the reduced range) and an exact scaling by 2^k.
+double kexp(double x) {
+  if (x < -745.0) return 0.0;
+  double kd = std::rint(x * 1.4426950408889634);
+  double r = std::fma(-kd, 6.93147180369123816490e-01, x);
+  r = std::fma(-kd, 1.90821492927058770002e-10, r);
+  double p = 1.6059043836821613e-10;
+  p = std::fma(p, r, 2.08767569878681e-09);
+  p = std::fma(p, r, 2.505210838544172e-08);
+  p = std::fma(p, r, 2.755731922398589e-07);
+  p = std::fma(p, r, 2.7557319223985893e-06);
+  p = std::fma(p, r, 2.48015873015873e-05);
+  p = std::fma(p, r, 0.0001984126984126984);
+  p = std::fma(p, r, 0.001388888888888889);
+  p = std::fma(p, r, 0.008333333333333333);
+  p = std::fma(p, r, 0.041666666666666664);
+  p = std::fma(p, r, 0.16666666666666666);
+  p = std::fma(p, r, 0.5);
+  p = std::fma(p, r, 1.0);
+  p = std::fma(p, r, 1.0);
+  return std::ldexp(p, (int)kd);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -227,7 +261,7 @@ struct Kern {
       r2 += z * z;
     }
     double v;
-    if (kind == 0) v = std::exp(-std::sqrt(r2) / scale);
+    if (kind == 0) v = kexp(-std::sqrt(r2) / scale);
     else v = 1.0 / std::sqrt(r2 + scale * scale);
     if (i == j) v += shift;
     return v;
@@ -255,7 +289,7 @@ AcaOut aca_pp(int m, int n, const F& M, double tol) {
     int k = (int)o.I.size();
     for (int j = 0; j < n; ++j) {
       double a = M(i, j);
-      for (int l = 0; l < k; ++l) a -= o.U[l][i] * o.V[l][j];
+      for (int l = 0; l < k; ++l) a = std::fma(-o.U[l][i], o.V[l][j], a);
       r[j] = a;
     }
     rused[i] = 1;
@@ -282,7 +316,7 @@ AcaOut aca_pp(int m, int n, const F& M, double tol) {
     for (int j = 0; j < n; ++j) v[j] = r[j] / delta;
     for (int t = 0; t < m; ++t) {
       double a = M(t, jb);
-      for (int l = 0; l < k; ++l) a -= o.V[l][jb] * o.U[l][t];
+      for (int l = 0; l < k; ++l) a = std::fma(-o.V[l][jb], o.U[l][t], a);
       u[t] = a;
     }
     cused[jb] = 1;
@@ -411,6 +445,8 @@ struct oracle_sys {
   bool factored = false;
   std::string err;
   std::vector<std::array<int, 4>> trace;
+  std::vector<std::array<int, 6>> trace_ranks;     // r1..r4 (P2P) or r5, r6, then k_i', k_j'
+  std::vector<std::array<double, 8>> trace_ratio;  // per RRQR: kept, next ratio
   int64_t far_fill = 0;
   double cpqr_margin = 1e300, aca_stop = 1e300, aca_gap = 1e300;
   double flops[5] = {0, 0, 0, 0, 0};
@@ -478,8 +514,16 @@ void build_tree(oracle_sys& s) {
       c[t] = (int)q;
     }
     int64_t leaf = morton(c, d, L);
-    for (int l = L; l >= 0; --l) s.lev[l].pts[leaf >> (d * (L - l))].push_back(i);
+    s.lev[L].pts[leaf].push_back(i);
   }
+  // a coarser box lists its points in tree order: children in Morton order, each child's
+  // points in its own order (ascending original index at the leaf)
+  for (int l = L - 1; l >= 0; --l)
+    for (int b = 0; b < s.lev[l].nb; ++b)
+      for (int ch = 0; ch < (1 << d); ++ch) {
+        const std::vector<int64_t>& t = s.lev[l + 1].pts[(b << d) | ch];
+        s.lev[l].pts[b].insert(s.lev[l].pts[b].end(), t.begin(), t.end());
+      }
 }
 
 // Sec. 2.2, neighbour / interaction-list table (Q4: i in N(i); admissible iff integer
@@ -755,11 +799,21 @@ void col_update(oracle_sys& s, int l, int b, const Mat& Rb, int64_t skip_row) {
   }
 }
 
+// Result of one compression: new bases, the coefficient matrices L, R of the boxes whose
+// bases change and the new values of the two pair blocks.
+struct Comp {
+  int kind = 0, i = 0, j = 0;  // P2P: pair (i, j); P2L: box i and eliminated box r = j
+  Mat Uin, Vin, Ujn, Vjn, Li, Ri, Lj, Rj;
+  Mat A1, A2;  // P2P: (Z_i, y_j), (Z_j, y_i); P2L: (Z_i, y_r), (Z_r, y_i)
+};
+
 // Sec. 3.2.1: compression and redirection of the P2P fill-in pair (P2P_ij, P2P_ji), with the
 // Q10-Q13 readings (four RRQRs, per-box rank = max of its U-side and V-side ranks,
 // coefficients by projection onto the final orthonormal bases).
-void compress_p2p(oracle_sys& s, int l, int i, int j) {
+Comp compress_p2p(oracle_sys& s, int l, int i, int j) {
   Store& S = s.S;
+  Comp c;
+  c.kind = 0; c.i = i; c.j = j;
   int64_t Xi = var(VX, l, i), Xj = var(VX, l, j), xi = var(Vx, l, i), xj = var(Vx, l, j);
   Mat Ui = S.get(Xi, var(Vz, l, i)), Uj = S.get(Xj, var(Vz, l, j));
   Mat Vi = tr(S.get(var(VY, l, i), xi)), Vj = tr(S.get(var(VY, l, j), xj));
@@ -772,38 +826,32 @@ void compress_p2p(oracle_sys& s, int l, int i, int j) {
   Cpqr f4 = cpqr(hcat(Vi, mul(tr(Fji), Q2r, 4)), tol);  // [V_i | L~_ji^*] = V~_i R_ji
   note_cpqr(s, f1); note_cpqr(s, f2); note_cpqr(s, f3); note_cpqr(s, f4);
   int ki = std::max(f1.rank, f4.rank), kj = std::max(f2.rank, f3.rank);
-  Mat Uin = cpqr_q(f1, ki), Vin = cpqr_q(f4, ki), Ujn = cpqr_q(f2, kj), Vjn = cpqr_q(f3, kj);
-  Mat Li = mul(tr(Uin), Ui, 4), Ri = mul(tr(Vin), Vi, 4);   // U_i = U~_i L_i, V_i = V~_i R_i
-  Mat Lj = mul(tr(Ujn), Uj, 4), Rj = mul(tr(Vjn), Vj, 4);
-  Mat Ltij = mul(tr(Uin), Fij, 4);        // P2P_ij = U~_i L~_ij
-  Mat Rtij = mul(tr(Vjn), tr(Ltij), 4);   // L~_ij^* = V~_j R~_ij
-  Mat Ltji = mul(tr(Ujn), Fji, 4);
-  Mat Rtji = mul(tr(Vin), tr(Ltji), 4);
+  s.trace_ranks.push_back({f1.rank, f2.rank, f3.rank, f4.rank, ki, kj});
+  s.trace_ratio.push_back({f1.kept, f1.next, f2.kept, f2.next, f3.kept, f3.next, f4.kept, f4.next});
+  c.Uin = cpqr_q(f1, ki); c.Vin = cpqr_q(f4, ki); c.Ujn = cpqr_q(f2, kj); c.Vjn = cpqr_q(f3, kj);
+  c.Li = mul(tr(c.Uin), Ui, 4); c.Ri = mul(tr(c.Vin), Vi, 4);   // U_i = U~_i L_i, V_i = V~_i R_i
+  c.Lj = mul(tr(c.Ujn), Uj, 4); c.Rj = mul(tr(c.Vjn), Vj, 4);
+  Mat Ltij = mul(tr(c.Uin), Fij, 4);        // P2P_ij = U~_i L~_ij
+  Mat Rtij = mul(tr(c.Vjn), tr(Ltij), 4);   // L~_ij^* = V~_j R~_ij
+  Mat Ltji = mul(tr(c.Ujn), Fji, 4);
+  Mat Rtji = mul(tr(c.Vin), tr(Ltji), 4);
   int64_t Zi = var(VZ, l, i), Zj = var(VZ, l, j), yi = var(Vy, l, i), yj = var(Vy, l, j);
   // A_ij := L_i A_ij R_j^* + R~_ij^*
-  Mat Aij = mul(mul(Li, S.get(Zi, yj), 4), tr(Rj), 4);
+  c.A1 = mul(mul(c.Li, S.get(Zi, yj), 4), tr(c.Rj), 4);
   Mat Rt1 = tr(Rtij);
-  for (size_t q = 0; q < Aij.a.size(); ++q) Aij.a[q] += Rt1.a[q];
-  Mat Aji = mul(mul(Lj, S.get(Zj, yi), 4), tr(Ri), 4);
+  for (size_t q = 0; q < c.A1.a.size(); ++q) c.A1.a[q] += Rt1.a[q];
+  c.A2 = mul(mul(c.Lj, S.get(Zj, yi), 4), tr(c.Ri), 4);
   Mat Rt2 = tr(Rtji);
-  for (size_t q = 0; q < Aji.a.size(); ++q) Aji.a[q] += Rt2.a[q];
-  // other M2L, L2L and M2M blocks of rows Z_i, Z_j and columns y_i, y_j
-  row_update(s, l, i, Li, yj);
-  row_update(s, l, j, Lj, yi);
-  col_update(s, l, i, Ri, Zj);
-  col_update(s, l, j, Rj, Zi);
-  S.erase(Xi, xj);
-  S.erase(Xj, xi);
-  set_basis(s, l, i, Uin, Vin);
-  set_basis(s, l, j, Ujn, Vjn);
-  S.set(Zi, yj, Aij);
-  S.set(Zj, yi, Aji);
+  for (size_t q = 0; q < c.A2.a.size(); ++q) c.A2.a[q] += Rt2.a[q];
+  return c;
 }
 
 // Sec. 3.2.2 and 3.2.3: compression of P2L_ri (row Z_r, column x_i) and M2P_ir (row X_i,
 // column y_r), r eliminated, i about to be eliminated.  Box r's bases are frozen (Q15).
-void compress_p2l(oracle_sys& s, int l, int r, int i) {
+Comp compress_p2l(oracle_sys& s, int l, int r, int i) {
   Store& S = s.S;
+  Comp c;
+  c.kind = 1; c.i = i; c.j = r;
   int64_t Xi = var(VX, l, i), xi = var(Vx, l, i), Zr = var(VZ, l, r), yr = var(Vy, l, r);
   int64_t Zi = var(VZ, l, i), yi = var(Vy, l, i);
   Mat Ui = S.get(Xi, var(Vz, l, i));
@@ -814,23 +862,48 @@ void compress_p2l(oracle_sys& s, int l, int r, int i) {
   Cpqr f6 = cpqr(hcat(Ui, M2P), tol);       // [U_i | M2P_ir]  = U~_i L_ir
   note_cpqr(s, f5); note_cpqr(s, f6);
   int ki = std::max(f5.rank, f6.rank);
-  Mat Vin = cpqr_q(f5, ki), Uin = cpqr_q(f6, ki);
-  Mat Ri = mul(tr(Vin), Vi, 4), Li = mul(tr(Uin), Ui, 4);
-  // A_ri := A_ri R_i^* + R~_ri^*  with R~_ri^* = (V~_i^* P2L_ri^*)^* = P2L_ri V~_i
-  Mat Ari = mul(S.get(Zr, yi), tr(Ri), 4);
-  Mat add1 = mul(P2L, Vin, 4);
-  for (size_t q = 0; q < Ari.a.size(); ++q) Ari.a[q] += add1.a[q];
+  s.trace_ranks.push_back({f5.rank, f6.rank, 0, 0, ki, 0});
+  s.trace_ratio.push_back({f5.kept, f5.next, f6.kept, f6.next, 0, 0, 0, 0});
+  c.Vin = cpqr_q(f5, ki); c.Uin = cpqr_q(f6, ki);
+  c.Ri = mul(tr(c.Vin), Vi, 4); c.Li = mul(tr(c.Uin), Ui, 4);
   // A_ir := L_i A_ir + L~_ir  with L~_ir = U~_i^* M2P_ir
-  Mat Air = mul(Li, S.get(Zi, yr), 4);
-  Mat add2 = mul(tr(Uin), M2P, 4);
-  for (size_t q = 0; q < Air.a.size(); ++q) Air.a[q] += add2.a[q];
-  row_update(s, l, i, Li, yr);
-  col_update(s, l, i, Ri, Zr);
-  S.erase(Zr, xi);
-  S.erase(Xi, yr);
-  set_basis(s, l, i, Uin, Vin);
-  S.set(Zr, yi, Ari);
-  S.set(Zi, yr, Air);
+  c.A1 = mul(c.Li, S.get(Zi, yr), 4);
+  Mat add2 = mul(tr(c.Uin), M2P, 4);
+  for (size_t q = 0; q < c.A1.a.size(); ++q) c.A1.a[q] += add2.a[q];
+  // A_ri := A_ri R_i^* + R~_ri^*  with R~_ri^* = (V~_i^* P2L_ri^*)^* = P2L_ri V~_i
+  c.A2 = mul(S.get(Zr, yi), tr(c.Ri), 4);
+  Mat add1 = mul(P2L, c.Vin, 4);
+  for (size_t q = 0; q < c.A2.a.size(); ++q) c.A2.a[q] += add1.a[q];
+  return c;
+}
+
+// The other M2L, L2L and M2M blocks of the rows Z and columns y whose bases changed
+// ("Other M2L updates", M2M and L2L updates): left factors first, for every compression of
+// the round, then the right factors.
+void comp_rows(oracle_sys& s, int l, const Comp& c) {
+  row_update(s, l, c.i, c.Li, var(Vy, l, c.j));
+  if (c.kind == 0) row_update(s, l, c.j, c.Lj, var(Vy, l, c.i));
+}
+void comp_cols(oracle_sys& s, int l, const Comp& c) {
+  col_update(s, l, c.i, c.Ri, var(VZ, l, c.j));
+  if (c.kind == 0) col_update(s, l, c.j, c.Rj, var(VZ, l, c.i));
+}
+// New bases, the redirected pair blocks, and the compressed fill-ins removed.
+void comp_commit(oracle_sys& s, int l, const Comp& c) {
+  Store& S = s.S;
+  int i = c.i, j = c.j;
+  if (c.kind == 0) {
+    S.erase(var(VX, l, i), var(Vx, l, j));
+    S.erase(var(VX, l, j), var(Vx, l, i));
+    set_basis(s, l, i, c.Uin, c.Vin);
+    set_basis(s, l, j, c.Ujn, c.Vjn);
+  } else {
+    S.erase(var(VZ, l, j), var(Vx, l, i));
+    S.erase(var(VX, l, i), var(Vy, l, j));
+    set_basis(s, l, i, c.Uin, c.Vin);
+  }
+  S.set(var(VZ, l, i), var(Vy, l, j), c.A1);
+  S.set(var(VZ, l, j), var(Vy, l, i), c.A2);
 }
 
 // Algorithm "Efficient Elimination", the elimination step: pivot rows (X_i, Y_i) and columns
@@ -951,44 +1024,75 @@ bool factor(oracle_sys& s) {
     for (int q = 0; q < lv.nb; ++q) pos[lv.order[q]] = q;
     std::set<std::pair<int, int>> vP2P;   // unordered (min, max)
     std::set<std::pair<int, int>> vP2L;   // ordered (eliminated, not eliminated)
-    for (int q = 0; q < lv.nb; ++q) {
-      int i = lv.order[q];
-      // compress pending P2P pairs containing i, by increasing partner position (Q14)
-      std::vector<std::pair<int, int>> todo;
-      for (auto& pr : vP2P)
-        if (pr.first == i || pr.second == i) {
-          int j = pr.first == i ? pr.second : pr.first;
-          todo.push_back({pos[j], j});
+    // colour batches of the order (Q3): the compressions of one batch touch disjoint rows and
+    // columns except for commuting left/right factors on shared M2L blocks, and an
+    // elimination never touches another box of its batch, so every batch runs as: the
+    // r-th compression of each of its boxes for r = 0, 1, ... (left factors of the round,
+    // then right factors), then the eliminations
+    for (int q0 = 0; q0 < lv.nb;) {
+      auto colour = [&](int b) {
+        int64_t c = 0;
+        for (int t = 0; t < d; ++t) c = c * 5 + (lv.coord[b][t] % 5);
+        return c;
+      };
+      int q1 = q0;
+      while (q1 < lv.nb && colour(lv.order[q1]) == colour(lv.order[q0])) ++q1;
+      std::vector<std::vector<std::pair<int, int>>> ops(q1 - q0);  // (kind, partner)
+      size_t rounds = 0;
+      for (int q = q0; q < q1; ++q) {
+        int i = lv.order[q];
+        // pending P2P pairs containing i, by increasing partner position (Q14)
+        std::vector<std::pair<int, int>> todo;
+        for (auto& pr : vP2P)
+          if (pr.first == i || pr.second == i) {
+            int j = pr.first == i ? pr.second : pr.first;
+            todo.push_back({pos[j], j});
+          }
+        std::sort(todo.begin(), todo.end());
+        for (auto& t : todo) {
+          ops[q - q0].push_back({0, t.second});
+          vP2P.erase({std::min(i, t.second), std::max(i, t.second)});
         }
-      std::sort(todo.begin(), todo.end());
-      for (auto& t : todo) {
-        int j = t.second;
-        compress_p2p(s, l, i, j);
-        s.trace.push_back({l, i, 0, j});
-        vP2P.erase({std::min(i, j), std::max(i, j)});
-      }
-      todo.clear();
-      for (auto& pr : vP2L)
-        if (pr.second == i) todo.push_back({pos[pr.first], pr.first});
-      std::sort(todo.begin(), todo.end());
-      for (auto& t : todo) {
-        int r = t.second;
-        compress_p2l(s, l, r, i);
-        s.trace.push_back({l, i, 1, r});
-        vP2L.erase({r, i});
-      }
-      if (!eliminate(s, l, i)) return false;
-      elim[i] = 1;
-      // record the well-separated fill-ins created among N(i) (Algorithm, push steps)
-      for (int p : lv.nbr[i])
-        for (int r : lv.nbr[i]) {
-          if (p == r || p == i || r == i) continue;
-          if (cheb(lv.coord[p], lv.coord[r], d) < 2) continue;
-          if (elim[p] && elim[r]) continue;
-          if (elim[p]) vP2L.insert({p, r});
-          else if (elim[r]) vP2L.insert({r, p});
-          else vP2P.insert({std::min(p, r), std::max(p, r)});
+        todo.clear();
+        for (auto& pr : vP2L)
+          if (pr.second == i) todo.push_back({pos[pr.first], pr.first});
+        std::sort(todo.begin(), todo.end());
+        for (auto& t : todo) {
+          ops[q - q0].push_back({1, t.second});
+          vP2L.erase({t.second, i});
         }
+        rounds = std::max(rounds, ops[q - q0].size());
+      }
+      for (size_t r = 0; r < rounds; ++r) {
+        std::vector<Comp> res;
+        for (int q = q0; q < q1; ++q) {
+          if (r >= ops[q - q0].size()) continue;
+          int i = lv.order[q];
+          auto op = ops[q - q0][r];
+          if (op.first == 0) res.push_back(compress_p2p(s, l, i, op.second));
+          else res.push_back(compress_p2l(s, l, op.second, i));
+          s.trace.push_back({l, i, op.first, op.second});
+        }
+        for (auto& c : res) comp_rows(s, l, c);
+        for (auto& c : res) comp_cols(s, l, c);
+        for (auto& c : res) comp_commit(s, l, c);
+      }
+      for (int q = q0; q < q1; ++q) {
+        int i = lv.order[q];
+        if (!eliminate(s, l, i)) return false;
+        elim[i] = 1;
+        // record the well-separated fill-ins created among N(i) (Algorithm, push steps)
+        for (int p : lv.nbr[i])
+          for (int r : lv.nbr[i]) {
+            if (p == r || p == i || r == i) continue;
+            if (cheb(lv.coord[p], lv.coord[r], d) < 2) continue;
+            if (elim[p] && elim[r]) continue;
+            if (elim[p]) vP2L.insert({p, r});
+            else if (elim[r]) vP2L.insert({r, p});
+            else vP2P.insert({std::min(p, r), std::max(p, r)});
+          }
+      }
+      q0 = q1;
     }
     if (!vP2P.empty() || !vP2L.empty()) {
       s.err = "pending fill-ins left at the end of level " + std::to_string(l);
@@ -1318,6 +1422,26 @@ int oracle_pivots(oracle_sys* s, int level, int box, int64_t* t_i, int64_t* s_i)
   }
   return k;
 }
+int oracle_nnca_U(oracle_sys* s, int level, int box, double* out) {
+  // U_B = A[T_B, s^{B,i}] (A[t^{B,i}, s^{B,i}])^{-1}: L2P at the leaf, stacked children's L2L above
+  if (level < 2 || level > s->L) return -1;
+  Level& lv = s->lev[level];
+  int k = lv.knn[box];
+  if (level == s->L) {
+    const Mat& U = lv.U[box];
+    for (size_t q = 0; q < U.a.size(); ++q) out[q] = U.a[q];
+    return U.r;
+  }
+  Level& dn = s->lev[level + 1];
+  int o = 0;
+  for (int ch = 0; ch < (1 << s->d); ++ch) {
+    const Mat& U = dn.Ud[(box << s->d) | ch];
+    for (int i = 0; i < U.r; ++i)
+      for (int j = 0; j < k; ++j) out[(size_t)(o + i) * k + j] = U.at(i, j);
+    o += U.r;
+  }
+  return o;
+}
 int oracle_perm(oracle_sys* s, int64_t* perm) {
   int64_t o = 0;
   Level& lv = s->lev[s->L];
@@ -1389,6 +1513,14 @@ int64_t oracle_trace(oracle_sys* s, int* out, int64_t cap) {
   if (out)
     for (int64_t q = 0; q < n && q < cap; ++q)
       for (int t = 0; t < 4; ++t) out[q * 4 + t] = s->trace[q][t];
+  return n;
+}
+int64_t oracle_trace_ranks(oracle_sys* s, int* ranks, double* ratio, int64_t cap) {
+  int64_t n = (int64_t)s->trace_ranks.size();
+  for (int64_t q = 0; q < n && q < cap; ++q) {
+    for (int t = 0; t < 6; ++t) ranks[q * 6 + t] = s->trace_ranks[q][t];
+    for (int t = 0; t < 8; ++t) ratio[q * 8 + t] = s->trace_ratio[q][t];
+  }
   return n;
 }
 int64_t oracle_far_fill_count(oracle_sys* s) { return s->far_fill; }

@@ -59,7 +59,9 @@ int    oracle_nnca_ranks(oracle_sys* s, int level, int* k);                   /*
 int    oracle_final_ranks(oracle_sys* s, int level, int* k);                  /* k_b at elimination */
 int    oracle_xsize(oracle_sys* s, int level, int* n);                         /* n_b at elimination */
 int    oracle_pivots(oracle_sys* s, int level, int box, int64_t* t_i, int64_t* s_i); /* returns k */
-int    oracle_perm(oracle_sys* s, int64_t* perm);   /* tree order -> original index */
+int    oracle_perm(oracle_sys* s, int64_t* perm);
+/* NNCA interpolation operator of a box, |T_B| x k_B row-major; returns |T_B| */
+int    oracle_nnca_U(oracle_sys* s, int level, int box, double* out);   /* tree order -> original index */
 int    oracle_elim_order(oracle_sys* s, int level, int* order);
 /* dense extended matrix before elimination (small problems only). Writes dim into *dim;
    if out != NULL fills the dim x dim matrix and xcols[N] = column of x_m for original point m */
@@ -68,6 +70,9 @@ int    oracle_factor(oracle_sys* s);
 int    oracle_solve(oracle_sys* s, const double* b, int64_t nrhs, double* x);
 /* compression trace: rows of 4 ints (level, box being eliminated, kind 0=P2P 1=P2L, partner) */
 int64_t oracle_trace(oracle_sys* s, int* out, int64_t cap);
+/* per compression of the trace: 6 ranks (r1,r2,r3,r4,k_i',k_j' for P2P; r5,r6,0,0,k_i',0 for
+   P2L) and 8 decision ratios |R_kk|/(tol |R_11|) (last kept, first rejected) per RRQR */
+int64_t oracle_trace_ranks(oracle_sys* s, int* ranks, double* ratio, int64_t cap);
 /* number of blocks ever created outside dist_inf <= 2 (must be 0) */
 int64_t oracle_far_fill_count(oracle_sys* s);
 /* N(box) and IL(box) at a level; returns 1000*|N| + |IL| */
