@@ -1,0 +1,129 @@
+/*
+ * aifmm.h — C ABI of the MI355X (gfx950) AIFMM factor/solve library.
+ *
+ * The library builds, factors and solves the N-body system A x = b of Sec. 2 of
+ * Gujjula & Ambikasaran, "Algebraic Inverse Fast Multipole Method" (arXiv 2301.12704):
+ * targets u and sources v coincide (the setting of the paper's experiments, Sec. 4), and
+ * A_ij = kappa(|p_i - p_j|) + shift * delta_ij for a real, symmetric kernel kappa.
+ *
+ *   aifmm_build   Sec. 2.1-2.3 and 3.1: tree, lists, NNCA operators, extended sparse system.
+ *   aifmm_factor  Sec. 3.2-3.3: level-by-level elimination with one-shot compression and
+ *                 redirection of the accumulated well-separated fill-ins (Algorithm
+ *                 "Efficient Elimination").
+ *   aifmm_solve   Sec. 3.4: RHS Schur operations, level-2 multipole solve, back substitution
+ *                 (Algorithm "Back Substitution"); the factor is RHS-independent (remark after
+ *                 that algorithm), so solve may be called many times.
+ *
+ * Every entry point runs its numerical work in hand-written HIP kernels on the device
+ * selected in the options; there is no CPU fallback.  All functions return an
+ * aifmm_status; no exception crosses the ABI.  aifmm_last_error() gives a message.
+ *
+ * Layouts
+ *   points  N x d, row-major (point-major), FP64, host or device memory.
+ *   b, x    N x nrhs, column-major with leading dimension ldb/ldx >= N, FP64, in the caller's
+ *           original point order; host or device memory (detected per call).
+ * Ownership
+ *   aifmm_build copies the points; the system owns all device memory it allocates and
+ *   aifmm_destroy frees it.  b and x stay owned by the caller.
+ * Threading
+ *   One thread per system at a time.  Calls are stream-ordered on opt.stream (NULL = the
+ *   default stream) and return after the work has completed.
+ */
+#ifndef AIFMM_H
+#define AIFMM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AIFMM_OK = 0,
+  AIFMM_ERR_ARG = 1,       /* invalid argument (null pointer, bad size, bad kernel) */
+  AIFMM_ERR_NOMEM = 2,     /* device allocation failed */
+  AIFMM_ERR_SINGULAR = 3,  /* exactly singular self-block or top-level system */
+  AIFMM_ERR_STATE = 4,     /* call out of order (e.g. solve before factor) */
+  AIFMM_ERR_DEVICE = 5,    /* HIP runtime error */
+  AIFMM_ERR_NOCONV = 6,    /* iterative refinement did not reach the requested residual */
+  AIFMM_ERR_CAPACITY = 7,  /* a rank exceeded its preallocated capacity */
+  AIFMM_ERR_BUSY = 8       /* serving: no slot or memory for the request right now */
+} aifmm_status;
+
+typedef enum {
+  AIFMM_K_EXP = 0,   /* kappa(r) = exp(-r / scale)            */
+  AIFMM_K_INVMQ = 1  /* kappa(r) = 1 / sqrt(r^2 + scale^2)    */
+} aifmm_kernel_kind;
+
+typedef struct {
+  aifmm_kernel_kind kind;
+  double scale;  /* > 0 */
+  double shift;  /* added on the diagonal */
+} aifmm_kernel;
+
+typedef struct {
+  int32_t dim;         /* 2 or 3 */
+  int32_t leaf_size;   /* n_max: mean points per leaf used by the depth rule (default 64) */
+  int32_t depth;       /* 0: L = max(2, ceil(log_{2^d}(N / leaf_size))), else the tree depth */
+  int32_t device;      /* HIP device ordinal */
+  void* stream;        /* hipStream_t, NULL = default stream */
+} aifmm_options;
+
+typedef struct aifmm_system aifmm_system;
+
+/* Fill *opt with defaults (dim 2, leaf 64, depth auto, device 0, default stream). */
+aifmm_status aifmm_options_default(aifmm_options* opt);
+
+/* Build the tree (Sec. 2.1), neighbour and interaction lists (Sec. 2.2, eta = sqrt(d)), the
+ * NNCA operators with tolerance tol (Sec. 2.3) and the extended system (Sec. 3.1).
+ * points: N x opt->dim row-major.  On success *out owns a new system. */
+aifmm_status aifmm_build(const double* points, int64_t n, aifmm_kernel kernel, double tol,
+                         const aifmm_options* opt, aifmm_system** out);
+
+/* Eliminate levels L..2 with compression of the pending well-separated fill-ins before each
+ * box elimination (Algorithm "Efficient Elimination", Sec. 3.3), then factor the level-2
+ * multipole system densely.  AIFMM_ERR_SINGULAR names the level and box in the message. */
+aifmm_status aifmm_factor(aifmm_system* s);
+
+/* x = (factored A)^{-1} b for nrhs right-hand sides (Sec. 3.4). */
+aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx);
+
+/* Tree depth L. */
+aifmm_status aifmm_get_depth(const aifmm_system* s, int32_t* L);
+/* Ranks of the 2^(d*level) boxes of a level (2 <= level <= L): the NNCA ranks before
+ * factor, the ranks at elimination time after it. */
+aifmm_status aifmm_get_ranks(const aifmm_system* s, int32_t level, int32_t* ranks);
+/* Statistics, filled into an array of doubles (see AIFMM_STAT_* for the slots). */
+enum {
+  AIFMM_STAT_BUILD_S = 0, AIFMM_STAT_FACTOR_S = 1, AIFMM_STAT_SOLVE_S = 2,
+  AIFMM_STAT_SCHUR_FLOPS = 3,     /* counted Schur-update GEMM flops of the last factor */
+  AIFMM_STAT_SCHUR_BYTES = 4,     /* minimum HBM bytes of those GEMMs                 */
+  AIFMM_STAT_TRSM_FLOPS = 5, AIFMM_STAT_LU_FLOPS = 6,
+  AIFMM_STAT_DEVICE_BYTES = 7,    /* device bytes held by the system                  */
+  AIFMM_STAT_COUNT = 16
+};
+aifmm_status aifmm_get_stats(const aifmm_system* s, double* stats /* AIFMM_STAT_COUNT */);
+/* Decision log of the last factorization (the decision-margin record of the compressions):
+ * one record per compression of the static schedule, in launch order.  rec gets 10 ints per
+ * compression: level, box i being eliminated, kind (0 = P2P pair (i, j), 1 = P2L pair (r, i)),
+ * partner, then the RRQR ranks r1 r2 r3 r4 and the new ranks k_i' k_j' (P2L: r5 r6 0 0 k_i' 0);
+ * ratio gets 8 doubles: for each RRQR |R_kk| / (tol |R_11|) of the last kept and of the first
+ * rejected pivot (0 when none).  At most cap records are written; *count gets the total.
+ * rec / ratio may be NULL.  AIFMM_ERR_STATE before aifmm_factor. */
+aifmm_status aifmm_get_trace(const aifmm_system* s, int32_t* rec, double* ratio, int64_t cap, int64_t* count);
+/* NNCA output of one box (Sec. 2.3, eq. NCA and the operator table): the k_B incoming pivots
+ * t^{B,i} and s^{B,i} as original point indices (arrays of at least k_B, may be NULL), and
+ * U_B = A[T_B, s^{B,i}] (A[t^{B,i}, s^{B,i}])^{-1} (rows x k_B row-major, may be NULL) where
+ * T_B is the box's points at the leaf and its children's incoming pivots above.  *k and
+ * *rows receive k_B and |T_B|.  Valid after aifmm_build. */
+aifmm_status aifmm_get_nnca(const aifmm_system* s, int32_t level, int32_t box, int64_t* t_i, int64_t* s_i, double* U,
+                            int32_t* k, int32_t* rows);
+/* Message of the last error on this system (s != NULL) or of the calling thread (s == NULL). */
+const char* aifmm_last_error(const aifmm_system* s);
+/* Free every resource of the system; NULL is accepted. */
+void aifmm_destroy(aifmm_system* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AIFMM_H */

@@ -1,0 +1,206 @@
+// C ABI of the library (declarations and contracts in include/aifmm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "system.hpp"
+
+namespace {
+thread_local std::string g_err;
+
+aifmm_status fail(aifmm_system* s, aifmm_status st, const std::string& msg) {
+  g_err = msg;
+  if (s) s->err = msg;
+  return st;
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+template <class F>
+aifmm_status guarded(aifmm_system* s, F&& f) {
+  try {
+    f();
+    return AIFMM_OK;
+  } catch (const aifmm::Error& e) {
+    return fail(s, e.st, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(s, AIFMM_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(s, AIFMM_ERR_DEVICE, "unexpected failure");
+  }
+}
+}  // namespace
+
+extern "C" {
+
+aifmm_status aifmm_options_default(aifmm_options* opt) {
+  if (!opt) return fail(nullptr, AIFMM_ERR_ARG, "opt is NULL");
+  opt->dim = 2;
+  opt->leaf_size = 64;
+  opt->depth = 0;
+  opt->device = 0;
+  opt->stream = nullptr;
+  return AIFMM_OK;
+}
+
+aifmm_status aifmm_build(const double* points, int64_t n, aifmm_kernel kernel, double tol, const aifmm_options* opt,
+                         aifmm_system** out) {
+  if (!out) return fail(nullptr, AIFMM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  aifmm_options o;
+  aifmm_options_default(&o);
+  if (opt) o = *opt;
+  if (!points || n <= 0) return fail(nullptr, AIFMM_ERR_ARG, "points is NULL or n <= 0");
+  if (o.dim != 2 && o.dim != 3) return fail(nullptr, AIFMM_ERR_ARG, "dim must be 2 or 3");
+  if (o.leaf_size <= 0 || o.depth < 0 || o.depth > (o.dim == 2 ? 10 : 7))
+    return fail(nullptr, AIFMM_ERR_ARG, "bad leaf_size or depth");
+  if (kernel.kind != AIFMM_K_EXP && kernel.kind != AIFMM_K_INVMQ) return fail(nullptr, AIFMM_ERR_ARG, "bad kernel kind");
+  if (!(kernel.scale > 0.0) || !std::isfinite(kernel.shift)) return fail(nullptr, AIFMM_ERR_ARG, "bad kernel scale/shift");
+  if (!(tol > 0.0) || !(tol < 1.0)) return fail(nullptr, AIFMM_ERR_ARG, "tol must be in (0, 1)");
+  if (n > (int64_t)1 << 30) return fail(nullptr, AIFMM_ERR_ARG, "n too large");
+  aifmm_system* s = new (std::nothrow) aifmm_system();
+  if (!s) return fail(nullptr, AIFMM_ERR_NOMEM, "host allocation failed");
+  s->d = o.dim;
+  s->N = n;
+  s->leaf = o.leaf_size;
+  s->device = o.device;
+  s->stream = (hipStream_t)o.stream;
+  s->tol = tol;
+  s->K = aifmm::KernelDesc{(int)kernel.kind, kernel.scale, kernel.shift};
+  if (o.depth > 0) {
+    s->L = o.depth;
+  } else {
+    int L = 0;
+    double cap = (double)o.leaf_size;
+    while ((double)n > cap) { cap *= (double)(1 << o.dim); ++L; }
+    s->L = L < 2 ? 2 : L;
+  }
+  if (s->L > (o.dim == 2 ? 10 : 7)) { delete s; return fail(nullptr, AIFMM_ERR_ARG, "tree too deep"); }
+  aifmm_status st = guarded(s, [&] {
+    AIFMM_HIP(hipSetDevice(s->device));
+    aifmm::build_system(*s, points, is_device_ptr(points));
+  });
+  if (st != AIFMM_OK) {
+    g_err = s->err;
+    delete s;
+    return st;
+  }
+  *out = s;
+  return AIFMM_OK;
+}
+
+aifmm_status aifmm_factor(aifmm_system* s) {
+  if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  if (s->factored) return fail(s, AIFMM_ERR_STATE, "already factored");
+  aifmm_status st = guarded(s, [&] {
+    AIFMM_HIP(hipSetDevice(s->device));
+    aifmm::factor_system(*s);
+  });
+  if (st == AIFMM_OK) s->factored = true;
+  return st;
+}
+
+aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx) {
+  if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  if (!s->factored) return fail(s, AIFMM_ERR_STATE, "solve before factor");
+  if (!b || !x || nrhs <= 0 || ldb < s->N || ldx < s->N) return fail(s, AIFMM_ERR_ARG, "bad b/x/nrhs/ld");
+  if (nrhs > 4096) return fail(s, AIFMM_ERR_ARG, "nrhs too large");
+  return guarded(s, [&] {
+    AIFMM_HIP(hipSetDevice(s->device));
+    aifmm::solve_system(*s, b, nrhs, ldb, x, ldx, is_device_ptr(b), is_device_ptr(x));
+  });
+}
+
+aifmm_status aifmm_get_depth(const aifmm_system* s, int32_t* L) {
+  if (!s || !L) return fail(nullptr, AIFMM_ERR_ARG, "NULL argument");
+  *L = s->L;
+  return AIFMM_OK;
+}
+
+aifmm_status aifmm_get_ranks(const aifmm_system* s, int32_t level, int32_t* ranks) {
+  if (!s || !ranks) return fail(nullptr, AIFMM_ERR_ARG, "NULL argument");
+  if (level < 2 || level > s->L) return fail(nullptr, AIFMM_ERR_ARG, "level out of range");
+  const aifmm::LevelDev& lv = s->lev[level];
+  const std::vector<int>& k = s->factored ? lv.kfin : lv.knn;
+  for (int b = 0; b < lv.nb; ++b) ranks[b] = k[b];
+  return AIFMM_OK;
+}
+
+aifmm_status aifmm_get_stats(const aifmm_system* s, double* stats) {
+  if (!s || !stats) return fail(nullptr, AIFMM_ERR_ARG, "NULL argument");
+  for (int q = 0; q < AIFMM_STAT_COUNT; ++q) stats[q] = 0.0;
+  stats[AIFMM_STAT_BUILD_S] = s->stats.build_s;
+  stats[AIFMM_STAT_FACTOR_S] = s->stats.factor_s;
+  stats[AIFMM_STAT_SOLVE_S] = s->stats.solve_s;
+  stats[AIFMM_STAT_SCHUR_FLOPS] = s->stats.schur_flops;
+  stats[AIFMM_STAT_SCHUR_BYTES] = s->stats.schur_bytes;
+  stats[AIFMM_STAT_TRSM_FLOPS] = s->stats.trsm_flops;
+  stats[AIFMM_STAT_LU_FLOPS] = s->stats.lu_flops;
+  double bytes = 0;
+  for (const auto& lv : s->lev) bytes += (double)lv.fslab.bytes() + (double)lv.slab.bytes() + (double)lv.d_Unn.bytes();
+  stats[AIFMM_STAT_DEVICE_BYTES] = bytes;
+  return AIFMM_OK;
+}
+
+aifmm_status aifmm_get_trace(const aifmm_system* s, int32_t* rec, double* ratio, int64_t cap, int64_t* count) {
+  if (!s || !count) return fail(nullptr, AIFMM_ERR_ARG, "NULL argument");
+  if (!s->factored) return fail(nullptr, AIFMM_ERR_STATE, "no factorization");
+  *count = (int64_t)s->trace.size();
+  for (int64_t q = 0; q < *count && q < cap; ++q) {
+    const aifmm::TraceRec& t = s->trace[q];
+    if (rec) {
+      int32_t* o = rec + q * 10;
+      o[0] = t.level; o[1] = t.i; o[2] = t.kind; o[3] = t.partner;
+      for (int a = 0; a < 6; ++a) o[4 + a] = t.r[a];
+    }
+    if (ratio)
+      for (int a = 0; a < 8; ++a) ratio[q * 8 + a] = t.ratio[a];
+  }
+  return AIFMM_OK;
+}
+
+aifmm_status aifmm_get_nnca(const aifmm_system* s, int32_t level, int32_t box, int64_t* t_i, int64_t* s_i, double* U,
+                            int32_t* k, int32_t* rows) {
+  if (!s || !k || !rows) return fail(nullptr, AIFMM_ERR_ARG, "NULL argument");
+  if (level < 2 || level > s->L) return fail(nullptr, AIFMM_ERR_ARG, "level out of range");
+  const aifmm::LevelDev& lv = s->lev[level];
+  if (box < 0 || box >= lv.nb) return fail(nullptr, AIFMM_ERR_ARG, "box out of range");
+  return guarded(const_cast<aifmm_system*>(s), [&] {
+    hipStream_t st = s->stream;
+    int kb = lv.knn[box];
+    int t0 = lv.T_off[box], m = lv.T_off[box + 1] - t0;
+    *k = kb;
+    *rows = m;
+    std::vector<int64_t> perm = s->d_perm.download(st);
+    std::vector<int> pr = lv.d_piv_r.download(st), pc = lv.d_piv_c.download(st);
+    for (int q = 0; q < kb; ++q) {
+      if (t_i) t_i[q] = perm[pr[t0 + q]];
+      if (s_i) s_i[q] = perm[pc[t0 + q]];
+    }
+    if (U && kb > 0 && m > 0)
+      AIFMM_HIP(hipMemcpy(U, lv.d_Unn.p + lv.Unn_off[box], sizeof(double) * (size_t)m * kb, hipMemcpyDeviceToHost));
+  });
+}
+
+const char* aifmm_last_error(const aifmm_system* s) {
+  if (s) return s->err.c_str();
+  return g_err.c_str();
+}
+
+void aifmm_destroy(aifmm_system* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  delete s;
+}
+
+}  // extern "C"

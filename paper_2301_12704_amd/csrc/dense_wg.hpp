@@ -1,0 +1,272 @@
+// Workgroup-cooperative dense building blocks for gfx950 (wave64, 256-thread workgroups).
+// Used by the NNCA, compression and elimination kernels.  Every routine is called by all
+// threads of a workgroup and ends with a barrier, so results are visible on return.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "system.hpp"
+
+namespace aifmm {
+
+constexpr int WG = 256;
+constexpr int WAVE = 64;
+
+// e^x: Cody-Waite reduction x = k ln2 + r with |r| <= ln2/2 (ln2 split in a high part with
+// trailing zero bits and a low correction), Taylor series of e^r to degree 13 in Horner form
+// with fused multiply-adds (truncation below 4e-18 relative), exact scaling by 2^k.
+__device__ inline double dexp(double x) {
+  if (x < -745.0) return 0.0;
+  double kd = rint(x * 1.4426950408889634);
+  double r = fma(-kd, 6.93147180369123816490e-01, x);
+  r = fma(-kd, 1.90821492927058770002e-10, r);
+  double p = 1.6059043836821613e-10;
+  p = fma(p, r, 2.08767569878681e-09);
+  p = fma(p, r, 2.505210838544172e-08);
+  p = fma(p, r, 2.755731922398589e-07);
+  p = fma(p, r, 2.7557319223985893e-06);
+  p = fma(p, r, 2.48015873015873e-05);
+  p = fma(p, r, 0.0001984126984126984);
+  p = fma(p, r, 0.001388888888888889);
+  p = fma(p, r, 0.008333333333333333);
+  p = fma(p, r, 0.041666666666666664);
+  p = fma(p, r, 0.16666666666666666);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)kd);
+}
+
+// Kernel entry A_ij = kappa(|p_i - p_j|) + shift * delta_ij on tree positions i, j.  The
+// squared distance is formed without fused multiply-add so the value is the correctly
+// rounded sequence of IEEE operations.
+__device__ inline double kernel_entry(const KernelDesc& K, const double* __restrict__ pts, int d, int i, int j) {
+  double r2 = 0.0;
+  for (int t = 0; t < d; ++t) {
+    double z = __dsub_rn(pts[i * d + t], pts[j * d + t]);
+    r2 = __dadd_rn(r2, __dmul_rn(z, z));
+  }
+  double v;
+  if (K.kind == 0) v = dexp(-sqrt(r2) / K.scale);
+  else v = 1.0 / sqrt(__dadd_rn(r2, __dmul_rn(K.scale, K.scale)));
+  if (i == j) v += K.shift;
+  return v;
+}
+
+struct ValIdx {
+  double v;
+  int i;
+};
+__device__ inline bool vi_better(const ValIdx& a, const ValIdx& b) {
+  return a.v > b.v || (a.v == b.v && a.i < b.i);
+}
+
+// argmax over the workgroup, ties to the lowest index; invalid lanes pass v = -1, i = INT_MAX
+__device__ inline ValIdx wg_argmax(ValIdx x, ValIdx* sh) {
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    ValIdx o;
+    o.v = __shfl_down(x.v, off, WAVE);
+    o.i = __shfl_down(x.i, off, WAVE);
+    if (vi_better(o, x)) x = o;
+  }
+  int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ValIdx b = sh[0];
+    for (int q = 1; q < WG / WAVE; ++q)
+      if (vi_better(sh[q], b)) b = sh[q];
+    sh[WG / WAVE] = b;
+  }
+  __syncthreads();
+  ValIdx r = sh[WG / WAVE];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double wg_sum(double x, double* sh) {
+  for (int off = WAVE / 2; off > 0; off >>= 1) x += __shfl_down(x, off, WAVE);
+  int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < WG / WAVE; ++q) s += sh[q];
+    sh[WG / WAVE] = s;
+  }
+  __syncthreads();
+  double r = sh[WG / WAVE];
+  __syncthreads();
+  return r;
+}
+
+// C = alpha * op(A) op(B) + beta * C  (row-major; op = transpose when the flag is set).
+// C must not alias A or B.  beta == 0 never reads C.
+__device__ inline void wg_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda, bool ta,
+                               const double* __restrict__ B, int ldb, bool tb, double beta, double* C, int ldc) {
+  for (int idx = threadIdx.x; idx < M * N; idx += WG) {
+    int r = idx / N, c = idx - r * N;
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double a = ta ? A[(size_t)k * lda + r] : A[(size_t)r * lda + k];
+      double b = tb ? B[(size_t)c * ldb + k] : B[(size_t)k * ldb + c];
+      acc = fma(a, b, acc);
+    }
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * C[(size_t)r * ldc + c];
+    C[(size_t)r * ldc + c] = v;
+  }
+  __syncthreads();
+}
+
+__device__ inline void wg_copy(int M, int N, const double* __restrict__ A, int lda, double* __restrict__ C, int ldc) {
+  for (int idx = threadIdx.x; idx < M * N; idx += WG) {
+    int r = idx / N, c = idx - r * N;
+    C[(size_t)r * ldc + c] = A[(size_t)r * lda + c];
+  }
+  __syncthreads();
+}
+__device__ inline void wg_zero(int M, int N, double* C, int ldc) {
+  for (int idx = threadIdx.x; idx < M * N; idx += WG) {
+    int r = idx / N, c = idx - r * N;
+    C[(size_t)r * ldc + c] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Householder QR with column pivoting on the m x n row-major matrix M (destroyed), truncated
+// at the first step whose largest trailing column norm is <= tol times the first one
+// (RRQR with threshold eps_A of Sec. 3.2.1).  Reflector s is stored in column s of V
+// (m x n row-major, ldv) with V[s][s] = 1, tau[s] its scale.  nrm is scratch of length n.
+// Returns the rank.
+__device__ inline int wg_cpqr(int m, int n, double* M, int ldm, double tol, double* V, int ldv, double* tau,
+                              double* nrm, ValIdx* shv, double* ratio = nullptr) {
+  double kept = 0.0, next = 0.0;
+  int smax = m < n ? m : n;
+  double r11 = 0.0;
+  int s = 0;
+  for (; s < smax; ++s) {
+    for (int j = s + (int)threadIdx.x; j < n; j += WG) {
+      double t = 0.0;
+      for (int i = s; i < m; ++i) {
+        double a = M[(size_t)i * ldm + j];
+        t = fma(a, a, t);
+      }
+      nrm[j] = sqrt(t);
+    }
+    __syncthreads();
+    // pivot: lowest-index column whose norm is within a relative 1e-11 of the largest, so
+    // norms equal in exact arithmetic (orthonormal basis columns) tie whatever the rounding
+    ValIdx mx{-1.0, INT_MAX};
+    for (int j = s + (int)threadIdx.x; j < n; j += WG) {
+      ValIdx c{nrm[j], j};
+      if (vi_better(c, mx)) mx = c;
+    }
+    mx = wg_argmax(mx, shv);
+    double thr = mx.v * (1.0 - 1e-11);
+    ValIdx best{-1.0, INT_MAX};
+    for (int j = s + (int)threadIdx.x; j < n; j += WG)
+      if (nrm[j] >= thr && j < best.i) best = ValIdx{0.0, j};
+    best = wg_argmax(best, shv);
+    best.v = nrm[best.i];
+    if (s == 0) {
+      r11 = best.v;
+      if (r11 == 0.0) break;
+    } else if (best.v <= tol * r11) {
+      next = best.v / (tol * r11);
+      break;
+    }
+    kept = best.v / (tol * r11);
+    int p = best.i;
+    if (p != s) {
+      for (int i = threadIdx.x; i < m; i += WG) {
+        double a = M[(size_t)i * ldm + s];
+        M[(size_t)i * ldm + s] = M[(size_t)i * ldm + p];
+        M[(size_t)i * ldm + p] = a;
+      }
+      __syncthreads();
+    }
+    double x0 = M[(size_t)s * ldm + s];
+    double alpha = best.v;
+    double beta = x0 >= 0.0 ? -alpha : alpha;
+    double scale = x0 - beta;
+    double tv = (beta - x0) / beta;
+    for (int i = threadIdx.x; i < m; i += WG) {
+      double v = 0.0;
+      if (i == s) v = 1.0;
+      else if (i > s) v = M[(size_t)i * ldm + s] / scale;
+      V[(size_t)i * ldv + s] = v;
+    }
+    if (threadIdx.x == 0) tau[s] = tv;
+    __syncthreads();
+    for (int j = s + 1 + (int)threadIdx.x; j < n; j += WG) {
+      double w = 0.0;
+      for (int i = s; i < m; ++i) w = fma(V[(size_t)i * ldv + s], M[(size_t)i * ldm + j], w);
+      w *= tv;
+      for (int i = s; i < m; ++i) M[(size_t)i * ldm + j] = fma(-w, V[(size_t)i * ldv + s], M[(size_t)i * ldm + j]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += WG) M[(size_t)i * ldm + s] = (i == s) ? beta : (i > s ? 0.0 : M[(size_t)i * ldm + s]);
+    __syncthreads();
+  }
+  if (ratio && threadIdx.x == 0) { ratio[0] = kept; ratio[1] = next; }
+  return s;
+}
+
+// Q[:, 0:q] = H_0 H_1 ... H_{rank-1} [I; 0]  (m x q row-major, ldq)
+__device__ inline void wg_formq(int m, int rank, int q, const double* V, int ldv, const double* tau, double* Q, int ldq) {
+  for (int idx = threadIdx.x; idx < m * q; idx += WG) {
+    int r = idx / q, c = idx - r * q;
+    Q[(size_t)r * ldq + c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int s = rank - 1; s >= 0; --s) {
+    double tv = tau[s];
+    for (int j = threadIdx.x; j < q; j += WG) {
+      double w = 0.0;
+      for (int i = s; i < m; ++i) w = fma(V[(size_t)i * ldv + s], Q[(size_t)i * ldq + j], w);
+      w *= tv;
+      for (int i = s; i < m; ++i) Q[(size_t)i * ldq + j] = fma(-w, V[(size_t)i * ldv + s], Q[(size_t)i * ldq + j]);
+    }
+    __syncthreads();
+  }
+}
+
+// In-place LU with row partial pivoting (ties to the lowest row) of the m x m row-major A;
+// ipiv[k] is the row swapped with k at step k.  Returns 0 or 1+k for an exactly zero pivot.
+__device__ inline int wg_lu(int m, double* A, int lda, int* ipiv, ValIdx* shv) {
+  for (int k = 0; k < m; ++k) {
+    ValIdx best{-1.0, INT_MAX};
+    for (int i = k + (int)threadIdx.x; i < m; i += WG) {
+      ValIdx c{fabs(A[(size_t)i * lda + k]), i};
+      if (vi_better(c, best)) best = c;
+    }
+    best = wg_argmax(best, shv);
+    if (best.v == 0.0) return 1 + k;
+    int p = best.i;
+    if (threadIdx.x == 0) ipiv[k] = p;
+    if (p != k) {
+      for (int j = threadIdx.x; j < m; j += WG) {
+        double a = A[(size_t)k * lda + j];
+        A[(size_t)k * lda + j] = A[(size_t)p * lda + j];
+        A[(size_t)p * lda + j] = a;
+      }
+    }
+    __syncthreads();
+    double piv = A[(size_t)k * lda + k];
+    int rem = m - k - 1;
+    for (int i = threadIdx.x; i < rem; i += WG) A[(size_t)(k + 1 + i) * lda + k] /= piv;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rem * rem; idx += WG) {
+      int i = k + 1 + idx / rem, j = k + 1 + idx % rem;
+      A[(size_t)i * lda + j] = fma(-A[(size_t)i * lda + k], A[(size_t)k * lda + j], A[(size_t)i * lda + j]);
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+}  // namespace aifmm

@@ -1,0 +1,1051 @@
+// Factorization (Sec. 3.2-3.3, Algorithm "Efficient Elimination") on the device.
+//
+// Per level l = L..2 and per colour batch of the colour-major order:
+//   1. compression rounds: round r compresses the r-th pending pair of every box of the
+//      colour (P2P pairs by four RRQRs, P2L/M2P pairs by two, Sec. 3.2.1-3.2.3), then the
+//      basis changes of the other blocks of the touched rows Z and columns y are applied
+//      (left factor L in one kernel, right factor R^* in the next, so no block is written
+//      by two workgroups at once);
+//   2. elimination of every box of the colour: gather of the pivot block
+//      [[K_ii, U_i], [V_i^*, 0]] and of the coupled blocks, pivoted LU, triangular solves
+//      W = Piv^{-1} A[(X_i,Y_i), O_c], Schur update A[O_r, O_c] -= A[O_r, x_i] W_x and the
+//      new rows Z_i = W_z.
+// Between levels the remaining Z^{(l)} x y^{(l)} blocks become the next level's particle
+// blocks (eq. particleAtNonLeafLevel), and after level 2 the level-2 multipole system is
+// factored densely (Algorithm "Back Substitution", first line).
+#include <algorithm>
+#include <chrono>
+
+#include "dense_wg.hpp"
+#include "system.hpp"
+
+namespace aifmm {
+
+struct RoundEntry {
+  int i, kind, partner;
+  int e_ij, e_ji;  // M2L slot entries: (i, partner) and (partner, i)
+  int f_ij, f_ji;  // fill slot entries: (i, partner) and (partner, i)
+};
+struct XformEntry {
+  int x, skip, pair, side;
+};
+
+struct LevelPtrs {
+  int l, nb, d;
+  const int* n;
+  int* k;
+  int* kn;
+  const int* nbr_off;
+  const int* nbr;
+  const int* il_off;
+  const int* il;
+  const int* il_tr;
+  const int* p2_off;
+  const int* p2;
+  const int* grp_off;
+  const int* grp_box;
+  const int* grp_elim;
+  double* slab;
+  const int64_t* near_slot;
+  const int64_t* p2_slot;
+  const int64_t* il_slot;
+  const int64_t* U_off;
+  const int64_t* V_off;
+  const int64_t* l2l_off;
+  const int64_t* m2m_off;
+  const int* kP;
+  const int64_t* tslot;
+  int Gmax;
+  double* fslab;
+  const int64_t* fLU;
+  const int64_t* fC;
+  const int64_t* fW;
+  int* fpiv;
+  const int64_t* fpiv_off;
+  int* trace;        // per compression: r1 r2 r3 r4 k_i' k_j'
+  double* trace_ratio;  // per compression: 4 x (kept, next) decision ratios
+};
+
+// ------------------------------------------------------------------------------------------
+// compression of one pending pair per workgroup
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) k_compress(LevelPtrs P, const RoundEntry* __restrict__ ent, int nent, double* ws,
+                                                 int64_t wsz, int cap, double tol, int64_t tbase) {
+  int e = blockIdx.x;
+  if (e >= nent) return;
+  RoundEntry R = ent[e];
+  int* tr = P.trace + (tbase + e) * 6;
+  double* trr = P.trace_ratio + (tbase + e) * 8;
+  __shared__ ValIdx shv[WG / WAVE + 1];
+  double* w = ws + (size_t)e * wsz;
+  size_t c2 = (size_t)cap * cap;
+  double* Lb_i = w;
+  double* Rb_i = w + c2;
+  double* Lb_j = w + 2 * c2;
+  double* Rb_j = w + 3 * c2;
+  double* M = w + 4 * c2;        // cap x 2cap
+  double* V1 = w + 6 * c2;
+  double* V2 = w + 7 * c2;
+  double* V3 = w + 8 * c2;
+  double* V4 = w + 9 * c2;
+  double* nU = w + 10 * c2;
+  double* nV = w + 11 * c2;
+  double* nUj = w + 12 * c2;
+  double* nVj = w + 13 * c2;
+  double* t1 = w + 14 * c2;      // cap x 2cap
+  double* t2 = w + 16 * c2;
+  double* tau = w + 17 * c2;     // 4 * cap
+  double* nrm = tau + 4 * cap;   // 2 * cap
+  const double* U_i = P.slab + P.U_off[R.i];
+  const double* V_i = P.slab + P.V_off[R.i];
+  int i = R.i, ni = P.n[i], ki = P.k[i];
+  if (R.kind == 0) {
+    int j = R.partner, nj = P.n[j], kj = P.k[j];
+    const double* U_j = P.slab + P.U_off[j];
+    const double* V_j = P.slab + P.V_off[j];
+    double* Fij = P.slab + P.p2_slot[R.f_ij];  // (X_i, x_j): ni x nj, ld nj
+    double* Fji = P.slab + P.p2_slot[R.f_ji];  // (X_j, x_i): nj x ni, ld ni
+    double* Aij = P.slab + P.il_slot[R.e_ij];  // (Z_i, y_j): ki x kj, ld nj
+    double* Aji = P.slab + P.il_slot[R.e_ji];  // (Z_j, y_i): kj x ki, ld ni
+    // RRQR1: [U_i | P2P_ij] = U~_i L_ij
+    int ld = ki + nj;
+    wg_copy(ni, ki, U_i, ni, M, ld);
+    wg_copy(ni, nj, Fij, nj, M + ki, ld);
+    int r1 = wg_cpqr(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, trr);
+    // RRQR2: [U_j | P2P_ji] = U~_j L_ji
+    ld = kj + ni;
+    wg_copy(nj, kj, U_j, nj, M, ld);
+    wg_copy(nj, ni, Fji, ni, M + kj, ld);
+    int r2 = wg_cpqr(nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, trr + 2);
+    // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij
+    wg_formq(ni, r1, r1, V1, cap, tau, t1, r1 > 0 ? r1 : 1);
+    ld = kj + r1;
+    wg_copy(nj, kj, V_j, nj, M, ld);
+    wg_gemm(nj, r1, ni, 1.0, Fij, nj, true, t1, r1 > 0 ? r1 : 1, false, 0.0, M + kj, ld);
+    int r3 = wg_cpqr(nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, trr + 4);
+    // RRQR4: [V_i | L~_ji^*]
+    wg_formq(nj, r2, r2, V2, cap, tau + cap, t1, r2 > 0 ? r2 : 1);
+    ld = ki + r2;
+    wg_copy(ni, ki, V_i, ni, M, ld);
+    wg_gemm(ni, r2, nj, 1.0, Fji, ni, true, t1, r2 > 0 ? r2 : 1, false, 0.0, M + ki, ld);
+    int r4 = wg_cpqr(ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, trr + 6);
+    int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
+    int kin1 = kin > 0 ? kin : 1, kjn1 = kjn > 0 ? kjn : 1;
+    // new orthonormal bases (columns beyond a tolerance rank are further columns of the
+    // same Householder Q)
+    wg_formq(ni, r1, kin, V1, cap, tau, nU, kin1);
+    wg_formq(ni, r4, kin, V4, cap, tau + 3 * cap, nV, kin1);
+    wg_formq(nj, r2, kjn, V2, cap, tau + cap, nUj, kjn1);
+    wg_formq(nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, kjn1);
+    // coefficients by projection: U_i = U~_i L_i, V_i = V~_i R_i, ...
+    int ki1 = ki > 0 ? ki : 1, kj1 = kj > 0 ? kj : 1;
+    wg_gemm(kin, ki, ni, 1.0, nU, kin1, true, U_i, ni, false, 0.0, Lb_i, ki1);
+    wg_gemm(kin, ki, ni, 1.0, nV, kin1, true, V_i, ni, false, 0.0, Rb_i, ki1);
+    wg_gemm(kjn, kj, nj, 1.0, nUj, kjn1, true, U_j, nj, false, 0.0, Lb_j, kj1);
+    wg_gemm(kjn, kj, nj, 1.0, nVj, kjn1, true, V_j, nj, false, 0.0, Rb_j, kj1);
+    // A_ij := L_i A_ij R_j^* + R~_ij^*,  L~_ij = U~_i^* P2P_ij (kin x nj), R~_ij = V~_j^* L~_ij^*
+    wg_gemm(kin, nj, ni, 1.0, nU, kin1, true, Fij, nj, false, 0.0, t1, nj > 0 ? nj : 1);
+    wg_gemm(kjn, kin, nj, 1.0, nVj, kjn1, true, t1, nj > 0 ? nj : 1, true, 0.0, t2, kin1);  // R~_ij
+    wg_gemm(kin, kj, ki, 1.0, Lb_i, ki1, false, Aij, nj, false, 0.0, t1, kj1);             // L_i A_ij
+    for (int idx = threadIdx.x; idx < kin * kjn; idx += WG) {
+      int r = idx / kjn, c = idx - r * kjn;
+      Aij[(size_t)r * nj + c] = t2[(size_t)c * kin1 + r];
+    }
+    __syncthreads();
+    wg_gemm(kin, kjn, kj, 1.0, t1, kj1, false, Rb_j, kj1, true, 1.0, Aij, nj);
+    // A_ji := L_j A_ji R_i^* + R~_ji^*
+    wg_gemm(kjn, ni, nj, 1.0, nUj, kjn1, true, Fji, ni, false, 0.0, t1, ni > 0 ? ni : 1);
+    wg_gemm(kin, kjn, ni, 1.0, nV, kin1, true, t1, ni > 0 ? ni : 1, true, 0.0, t2, kjn1);  // R~_ji
+    wg_gemm(kjn, ki, kj, 1.0, Lb_j, kj1, false, Aji, ni, false, 0.0, t1, ki1);
+    for (int idx = threadIdx.x; idx < kjn * kin; idx += WG) {
+      int r = idx / kin, c = idx - r * kin;
+      Aji[(size_t)r * ni + c] = t2[(size_t)c * kjn1 + r];
+    }
+    __syncthreads();
+    wg_gemm(kjn, kin, ki, 1.0, t1, ki1, false, Rb_i, ki1, true, 1.0, Aji, ni);
+    // bases, fill-ins, ranks
+    wg_copy(ni, kin, nU, kin1, (double*)U_i, ni);
+    wg_copy(ni, kin, nV, kin1, (double*)V_i, ni);
+    wg_copy(nj, kjn, nUj, kjn1, (double*)U_j, nj);
+    wg_copy(nj, kjn, nVj, kjn1, (double*)V_j, nj);
+    wg_zero(ni, nj, Fij, nj);
+    wg_zero(nj, ni, Fji, ni);
+    if (threadIdx.x == 0) {
+      P.kn[i] = kin;
+      P.kn[j] = kjn;
+      tr[0] = r1; tr[1] = r2; tr[2] = r3; tr[3] = r4; tr[4] = kin; tr[5] = kjn;
+    }
+  } else {
+    int r = R.partner, nr = P.n[r], kr = P.k[r];
+    double* M2P = P.slab + P.p2_slot[R.f_ij];  // (X_i, y_r): ni x kr, ld nr
+    double* P2L = P.slab + P.p2_slot[R.f_ji];  // (Z_r, x_i): kr x ni, ld ni
+    double* Air = P.slab + P.il_slot[R.e_ij];  // (Z_i, y_r): ki x kr, ld nr
+    double* Ari = P.slab + P.il_slot[R.e_ji];  // (Z_r, y_i): kr x ki, ld ni
+    int ld = ki + kr;
+    // RRQR: [V_i | P2L_ri^*] = V~_i R_ri
+    wg_copy(ni, ki, V_i, ni, M, ld);
+    for (int idx = threadIdx.x; idx < ni * kr; idx += WG) {
+      int a = idx / kr, c = idx - a * kr;
+      M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
+    }
+    __syncthreads();
+    int r5 = wg_cpqr(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, trr);
+    // RRQR: [U_i | M2P_ir] = U~_i L_ir
+    wg_copy(ni, ki, U_i, ni, M, ld);
+    wg_copy(ni, kr, M2P, nr, M + ki, ld);
+    int r6 = wg_cpqr(ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, trr + 2);
+    int kin = r5 > r6 ? r5 : r6;
+    int kin1 = kin > 0 ? kin : 1, ki1 = ki > 0 ? ki : 1, kr1 = kr > 0 ? kr : 1;
+    wg_formq(ni, r5, kin, V1, cap, tau, nV, kin1);
+    wg_formq(ni, r6, kin, V2, cap, tau + cap, nU, kin1);
+    wg_gemm(kin, ki, ni, 1.0, nV, kin1, true, V_i, ni, false, 0.0, Rb_i, ki1);
+    wg_gemm(kin, ki, ni, 1.0, nU, kin1, true, U_i, ni, false, 0.0, Lb_i, ki1);
+    // A_ri := A_ri R_i^* + P2L_ri V~_i
+    wg_gemm(kr, kin, ki, 1.0, Ari, ni, false, Rb_i, ki1, true, 0.0, t1, kin1);
+    wg_gemm(kr, kin, ni, 1.0, P2L, ni, false, nV, kin1, false, 1.0, t1, kin1);
+    // A_ir := L_i A_ir + U~_i^* M2P_ir
+    wg_gemm(kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
+    wg_gemm(kin, kr, ni, 1.0, nU, kin1, true, M2P, nr, false, 1.0, t2, kr1);
+    wg_copy(kr, kin, t1, kin1, Ari, ni);
+    wg_copy(kin, kr, t2, kr1, Air, nr);
+    wg_copy(ni, kin, nU, kin1, (double*)U_i, ni);
+    wg_copy(ni, kin, nV, kin1, (double*)V_i, ni);
+    wg_zero(nr, ni, P2L, ni);
+    wg_zero(ni, nr, M2P, nr);
+    if (threadIdx.x == 0) {
+      P.kn[i] = kin;
+      tr[0] = r5; tr[1] = r6; tr[2] = 0; tr[3] = 0; tr[4] = kin; tr[5] = 0;
+      trr[4] = trr[5] = trr[6] = trr[7] = 0.0;
+    }
+  }
+}
+
+// Left factor on the rows Z_x: every M2L block (x, c), c in IL(x), except the pair block,
+// and the L2L block become L_x * block.
+__global__ void __launch_bounds__(WG) k_row_xform(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
+                                                  int64_t wsz, int cap, int maxblk, double* scratch, int64_t sstride) {
+  double* tmp = scratch + (size_t)blockIdx.x * sstride;
+  size_t c2 = (size_t)cap * cap;
+  int total = nx * maxblk;
+  for (int task = blockIdx.x; task < total; task += gridDim.x) {
+    int t = task / maxblk, q = task - t * maxblk;
+    XformEntry X = xe[t];
+    int x = X.x;
+    int nil = P.il_off[x + 1] - P.il_off[x];
+    if (q > nil || (q == nil && P.l == 2)) continue;
+    int kold = P.k[x], knew = P.kn[x];
+    const double* Lm = ws + (size_t)X.pair * wsz + (X.side ? 2 * c2 : 0);
+    double* B;
+    int cols, ld;
+    if (q < nil) {
+      int c = P.il[P.il_off[x] + q];
+      if (c == X.skip) continue;
+      B = P.slab + P.il_slot[P.il_off[x] + q];
+      cols = P.k[c];
+      ld = P.n[c];
+    } else {
+      B = P.slab + P.l2l_off[x];
+      cols = P.kP[x];
+      ld = cols;
+    }
+    int kold1 = kold > 0 ? kold : 1;
+    wg_gemm(knew, cols, kold, 1.0, Lm, kold1, false, B, ld, false, 0.0, tmp, cols > 0 ? cols : 1);
+    wg_copy(knew, cols, tmp, cols > 0 ? cols : 1, B, ld);
+  }
+}
+
+// Right factor on the columns y_x: every M2L block (d, x), d in IL(x), except the pair
+// block, becomes block * R_x^*; the M2M block (stored transposed) becomes R_x * block.
+__global__ void __launch_bounds__(WG) k_col_xform(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
+                                                  int64_t wsz, int cap, int maxblk, double* scratch, int64_t sstride) {
+  double* tmp = scratch + (size_t)blockIdx.x * sstride;
+  size_t c2 = (size_t)cap * cap;
+  int total = nx * maxblk;
+  for (int task = blockIdx.x; task < total; task += gridDim.x) {
+    int t = task / maxblk, q = task - t * maxblk;
+    XformEntry X = xe[t];
+    int x = X.x;
+    int nil = P.il_off[x + 1] - P.il_off[x];
+    if (q > nil || (q == nil && P.l == 2)) continue;
+    int kold = P.k[x], knew = P.kn[x];
+    int kold1 = kold > 0 ? kold : 1;
+    const double* Rm = ws + (size_t)X.pair * wsz + (X.side ? 3 * c2 : c2);
+    if (q < nil) {
+      int dbox = P.il[P.il_off[x] + q];
+      if (dbox == X.skip) continue;
+      double* B = P.slab + P.il_slot[P.il_tr[P.il_off[x] + q]];
+      int rows = P.kn[dbox], ld = P.n[x];
+      wg_gemm(rows, knew, kold, 1.0, B, ld, false, Rm, kold1, true, 0.0, tmp, knew > 0 ? knew : 1);
+      wg_copy(rows, knew, tmp, knew > 0 ? knew : 1, B, ld);
+    } else {
+      double* B = P.slab + P.m2m_off[x];
+      int cols = P.kP[x];
+      wg_gemm(knew, cols, kold, 1.0, Rm, kold1, false, B, cols > 0 ? cols : 1, false, 0.0, tmp, cols > 0 ? cols : 1);
+      wg_copy(knew, cols, tmp, cols > 0 ? cols : 1, B, cols > 0 ? cols : 1);
+    }
+  }
+}
+
+__global__ void k_commit(LevelPtrs P, const XformEntry* __restrict__ xe, int nx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nx) P.k[xe[t].x] = P.kn[xe[t].x];
+}
+
+// ------------------------------------------------------------------------------------------
+// elimination of the boxes of one colour
+// ------------------------------------------------------------------------------------------
+__device__ inline int grp_rows(const LevelPtrs& P, int g, int G, int b, int gb, int ge) {
+  if (g == G - 1) return P.k[b];
+  return ge ? P.k[gb] : P.n[gb];
+}
+__device__ inline int64_t near_entry(const LevelPtrs& P, int p, int q) {
+  for (int e = P.nbr_off[p]; e < P.nbr_off[p + 1]; ++e)
+    if (P.nbr[e] == q) return P.near_slot[e];
+  return -1;
+}
+
+// Pivot block [[K_bb, U_b],[V_b^*, 0]], right-hand sides [A[X_b, O_c] | E | I] and the
+// coupled column blocks A[O_r, x_b] of box b (one workgroup per box).
+__global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __restrict__ boxes) {
+  int b = boxes[blockIdx.x];
+  int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+  int n = P.n[b], k = P.k[b], m = n + k;
+  double* Piv = P.fslab + P.fLU[b];
+  double* W = P.fslab + P.fW[b];
+  double* Cb = P.fslab + P.fC[b];
+  int C = 0;
+  for (int g = 0; g < G; ++g) C += grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
+  int ldw = C + n;
+  const double* Kbb = P.slab + near_entry(P, b, b);
+  const double* Ub = P.slab + P.U_off[b];
+  const double* Vb = P.slab + P.V_off[b];
+  for (int idx = threadIdx.x; idx < m * m; idx += WG) {
+    int r = idx / m, c = idx - r * m;
+    double v = 0.0;
+    if (r < n) v = c < n ? Kbb[(size_t)r * n + c] : Ub[(size_t)r * n + (c - n)];
+    else if (c < n) v = Vb[(size_t)c * n + (r - n)];
+    Piv[idx] = v;
+  }
+  for (int idx = threadIdx.x; idx < m * ldw; idx += WG) W[idx] = 0.0;
+  __syncthreads();
+  int co = 0, ro = 0;
+  for (int g = 0; g < G; ++g) {
+    int q = P.grp_box[g0 + g], qe = P.grp_elim[g0 + g];
+    int cd = grp_rows(P, g, G, b, q, qe);
+    if (g < G - 1) {
+      const double* Bbq = P.slab + near_entry(P, b, q);  // (X_b, x_q | y_q), ld n_q
+      int ldq = P.n[q];
+      for (int idx = threadIdx.x; idx < n * cd; idx += WG) {
+        int r = idx / cd, c = idx - r * cd;
+        W[(size_t)r * ldw + co + c] = Bbq[(size_t)r * ldq + c];
+      }
+      const double* Bqb = P.slab + near_entry(P, q, b);  // (X_q | Z_q, x_b), ld n_b
+      for (int idx = threadIdx.x; idx < cd * n; idx += WG) {
+        int r = idx / n, c = idx - r * n;
+        Cb[(size_t)(ro + r) * n + c] = Bqb[(size_t)r * n + c];
+      }
+      ro += cd;
+    } else {
+      for (int r = threadIdx.x; r < k; r += WG) W[(size_t)(n + r) * ldw + co + r] = -1.0;  // (Y_b, y_b) = -I
+    }
+    co += cd;
+  }
+  for (int r = threadIdx.x; r < n; r += WG) W[(size_t)r * ldw + C + r] = 1.0;  // extension: Piv^{-1}[:, x_b]
+}
+
+__global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restrict__ boxes, int* flag) {
+  int b = boxes[blockIdx.x];
+  int m = P.n[b] + P.k[b];
+  __shared__ ValIdx shv[WG / WAVE + 1];
+  int st = wg_lu(m, P.fslab + P.fLU[b], m, P.fpiv + P.fpiv_off[b], shv);
+  if (st && threadIdx.x == 0) {
+    flag[0] = 1;
+    flag[1] = b;
+    flag[2] = P.l;
+  }
+}
+
+// W = Piv^{-1} [rhs]: row swaps, unit-lower forward and upper backward substitution, one
+// column per thread.
+__global__ void __launch_bounds__(WG) k_elim_trsm(LevelPtrs P, const int* __restrict__ boxes, const int* flag) {
+  if (flag[0]) return;
+  int b = boxes[blockIdx.y];
+  int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+  int n = P.n[b], k = P.k[b], m = n + k;
+  int C = 0;
+  for (int g = 0; g < G; ++g) C += grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
+  int ldw = C + n;
+  int c = blockIdx.x * WG + threadIdx.x;
+  if (c >= ldw) return;
+  const double* A = P.fslab + P.fLU[b];
+  const int* ipiv = P.fpiv + P.fpiv_off[b];
+  double* W = P.fslab + P.fW[b];
+  for (int r = 0; r < m; ++r) {
+    int p = ipiv[r];
+    if (p != r) {
+      double t = W[(size_t)r * ldw + c];
+      W[(size_t)r * ldw + c] = W[(size_t)p * ldw + c];
+      W[(size_t)p * ldw + c] = t;
+    }
+  }
+  for (int r = 1; r < m; ++r) {
+    double v = W[(size_t)r * ldw + c];
+    for (int t = 0; t < r; ++t) v = fma(-A[(size_t)r * m + t], W[(size_t)t * ldw + c], v);
+    W[(size_t)r * ldw + c] = v;
+  }
+  for (int r = m - 1; r >= 0; --r) {
+    double v = W[(size_t)r * ldw + c];
+    for (int t = r + 1; t < m; ++t) v = fma(-A[(size_t)r * m + t], W[(size_t)t * ldw + c], v);
+    W[(size_t)r * ldw + c] = v / A[(size_t)r * m + r];
+  }
+}
+
+// Schur update of the coupled blocks: T[p, q] -= A[rows(p), x_b] W_x[:, cols(q)], with the
+// column y_b written (not accumulated): 64 x 64 output tile per workgroup, 4 x 4 per thread.
+constexpr int ST = 64, SK = 16;
+__global__ void __launch_bounds__(WG) k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int tiles_c) {
+  if (flag[0]) return;
+  int b = boxes[blockIdx.y];
+  int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+  int n = P.n[b], k = P.k[b];
+  __shared__ int rstart[28], cstart[28];
+  __shared__ double As[ST][SK + 1];
+  __shared__ double Bs[SK][ST + 1];
+  if (threadIdx.x == 0) {
+    int ro = 0, co = 0;
+    for (int g = 0; g < G; ++g) {
+      int cd = grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
+      rstart[g] = ro;
+      cstart[g] = co;
+      if (g < G - 1) ro += cd;
+      co += cd;
+    }
+    rstart[G] = ro;
+    cstart[G] = co;
+  }
+  __syncthreads();
+  int R = rstart[G - 1], C = cstart[G];
+  int tr = blockIdx.x / tiles_c, tc = blockIdx.x - tr * tiles_c;
+  int r0 = tr * ST, c0 = tc * ST;
+  if (r0 >= R || c0 >= C) return;
+  int ldw = C + n;
+  const double* Cb = P.fslab + P.fC[b];
+  const double* W = P.fslab + P.fW[b];
+  int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  double acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  for (int k0 = 0; k0 < n; k0 += SK) {
+    for (int idx = threadIdx.x; idx < ST * SK; idx += WG) {
+      int r = idx / SK, kk = idx - r * SK;
+      int gr = r0 + r, gk = k0 + kk;
+      As[r][kk] = (gr < R && gk < n) ? Cb[(size_t)gr * n + gk] : 0.0;
+    }
+    for (int idx = threadIdx.x; idx < SK * ST; idx += WG) {
+      int kk = idx / ST, c = idx - kk * ST;
+      int gk = k0 + kk, gc = c0 + c;
+      Bs[kk][c] = (gk < n && gc < C) ? W[(size_t)gk * ldw + gc] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < SK; ++kk) {
+      double av[4], bv[4];
+      for (int a = 0; a < 4; ++a) av[a] = As[ty * 4 + a][kk];
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx * 4 + c];
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) acc[a][c] = fma(av[a], bv[c], acc[a][c]);
+    }
+    __syncthreads();
+  }
+  const int64_t* ts = P.tslot + (size_t)b * P.Gmax * P.Gmax;
+  for (int a = 0; a < 4; ++a) {
+    int r = r0 + ty * 4 + a;
+    if (r >= R) continue;
+    int gr = 0;
+    while (rstart[gr + 1] <= r) ++gr;
+    int lr = r - rstart[gr];
+    for (int c4 = 0; c4 < 4; ++c4) {
+      int c = c0 + tx * 4 + c4;
+      if (c >= C) continue;
+      int gc = 0;
+      while (cstart[gc + 1] <= c) ++gc;
+      int lc = c - cstart[gc];
+      int q = P.grp_box[g0 + gc];
+      double* T = P.slab + ts[gr * P.Gmax + gc];
+      size_t addr = (size_t)lr * P.n[q] + lc;
+      if (gc == G - 1) T[addr] = -acc[a][c4];
+      else T[addr] -= acc[a][c4];
+    }
+  }
+  (void)k;
+}
+
+// New rows Z_b: (Z_b, cols(q)) = W_z[:, cols(q)] for every coupled column group.
+__global__ void __launch_bounds__(WG) k_elim_zrow(LevelPtrs P, const int* __restrict__ boxes, const int* flag) {
+  if (flag[0]) return;
+  int b = boxes[blockIdx.x];
+  int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+  int n = P.n[b], k = P.k[b];
+  int C = 0;
+  for (int g = 0; g < G; ++g) C += grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
+  int ldw = C + n;
+  const double* W = P.fslab + P.fW[b];
+  int co = 0;
+  for (int g = 0; g < G; ++g) {
+    int q = P.grp_box[g0 + g];
+    int cd = grp_rows(P, g, G, b, q, P.grp_elim[g0 + g]);
+    double* T = P.slab + near_entry(P, b, q);
+    int ldq = P.n[q];
+    for (int idx = threadIdx.x; idx < k * cd; idx += WG) {
+      int r = idx / cd, c = idx - r * cd;
+      T[(size_t)r * ldq + c] = W[(size_t)(n + r) * ldw + co + c];
+    }
+    co += cd;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Leaf level of the extended system: P2P near blocks, U_b = V_b, L2L / M2M, M2L
+// ------------------------------------------------------------------------------------------
+__global__ void k_fill_near(KernelDesc K, const double* pts, int d, const int* nbr_off, const int* nbr,
+                            const int* box_off, const int* n, const int64_t* slot, double* slab) {
+  int b = blockIdx.y;
+  int e = nbr_off[b] + blockIdx.x;
+  if (e >= nbr_off[b + 1]) return;
+  int q = nbr[e];
+  int np = n[b], nq = n[q];
+  double* o = slab + slot[e];
+  int p0 = box_off[b], q0 = box_off[q];
+  for (int idx = threadIdx.x; idx < np * nq; idx += WG) {
+    int r = idx / nq, c = idx - r * nq;
+    o[idx] = kernel_entry(K, pts, d, p0 + r, q0 + c);
+  }
+}
+
+// copy a compact k_r x k_c block into a slot with leading dimension ld
+__global__ void k_copy_blocks(const double* src, const int64_t* src_off, const int* rows, const int* cols,
+                              const int64_t* dst_off, const int* ld, double* dst) {
+  int e = blockIdx.x;
+  int R = rows[e], C = cols[e], L = ld[e];
+  const double* s = src + src_off[e];
+  double* o = dst + dst_off[e];
+  for (int idx = threadIdx.x; idx < R * C; idx += WG) {
+    int r = idx / C, c = idx - r * C;
+    o[(size_t)r * L + c] = s[idx];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// level activation: near blocks of level l-1 from the Z^{(l)} x y^{(l)} blocks of level l
+// ------------------------------------------------------------------------------------------
+struct RepackArgs {
+  int d;
+  // destination level
+  const int* nbr_off;
+  const int* nbr;
+  const int* n;          // n_P
+  const int64_t* near_slot;
+  double* slab;
+  // source level (children)
+  const int* ck;         // final child ranks
+  const int* cn;
+  const int* cnbr_off;
+  const int* cnbr;
+  const int64_t* cnear_slot;
+  const int* cil_off;
+  const int* cil;
+  const int64_t* cil_slot;
+  const double* cslab;
+};
+
+__global__ void __launch_bounds__(WG) k_repack_near(RepackArgs a) {
+  int Pb = blockIdx.y;
+  int e = a.nbr_off[Pb] + blockIdx.x;
+  if (e >= a.nbr_off[Pb + 1]) return;
+  int Q = a.nbr[e];
+  int nch = 1 << a.d;
+  double* out = a.slab + a.near_slot[e];
+  int ldo = a.n[Q];
+  int ro = 0;
+  for (int ci = 0; ci < nch; ++ci) {
+    int c = Pb * nch + ci;
+    int kc = a.ck[c];
+    int co = 0;
+    for (int ei = 0; ei < nch; ++ei) {
+      int f = Q * nch + ei;
+      int kf = a.ck[f];
+      const double* src = nullptr;
+      int lds = a.cn[f];
+      for (int t = a.cnbr_off[c]; t < a.cnbr_off[c + 1]; ++t)
+        if (a.cnbr[t] == f) { src = a.cslab + a.cnear_slot[t]; break; }
+      if (!src)
+        for (int t = a.cil_off[c]; t < a.cil_off[c + 1]; ++t)
+          if (a.cil[t] == f) { src = a.cslab + a.cil_slot[t]; break; }
+      if (src)
+        for (int idx = threadIdx.x; idx < kc * kf; idx += WG) {
+          int r = idx / kf, cc = idx - r * kf;
+          out[(size_t)(ro + r) * ldo + co + cc] = src[(size_t)r * lds + cc];
+        }
+      co += kf;
+    }
+    ro += kc;
+  }
+}
+
+// stacked U_P / V_P from the children's L2L / M2M blocks
+__global__ void k_stack_basis(int d, const int* ck, const int* kPc /* child's kP */, const int64_t* cl2l, const int64_t* cm2m,
+                              const double* cslab, const int* n, const int64_t* U_off, const int64_t* V_off, double* slab) {
+  int Pb = blockIdx.x;
+  int nch = 1 << d;
+  int nP = n[Pb];
+  int ro = 0;
+  for (int ci = 0; ci < nch; ++ci) {
+    int c = Pb * nch + ci;
+    int kc = ck[c], kp = kPc[c];
+    const double* L2 = cslab + cl2l[c];
+    const double* M2 = cslab + cm2m[c];
+    for (int idx = threadIdx.x; idx < kc * kp; idx += WG) {
+      int r = idx / kp, cc = idx - r * kp;
+      slab[U_off[Pb] + (size_t)(ro + r) * nP + cc] = L2[(size_t)r * kp + cc];
+      slab[V_off[Pb] + (size_t)(ro + r) * nP + cc] = M2[(size_t)r * kp + cc];
+    }
+    ro += kc;
+  }
+}
+
+__global__ void k_gather_top(int nb, const int* k, const int* n, const int* koff, const int* nbr_off, const int* nbr,
+                             const int64_t* near_slot, const int* il_off, const int* il, const int64_t* il_slot,
+                             const double* slab, double* top, int K) {
+  int a = blockIdx.x, bq = blockIdx.y;
+  int ka = k[a], kb = k[bq];
+  const double* src = nullptr;
+  for (int t = nbr_off[a]; t < nbr_off[a + 1]; ++t)
+    if (nbr[t] == bq) { src = slab + near_slot[t]; break; }
+  if (!src)
+    for (int t = il_off[a]; t < il_off[a + 1]; ++t)
+      if (il[t] == bq) { src = slab + il_slot[t]; break; }
+  int ld = n[bq];
+  for (int idx = threadIdx.x; idx < ka * kb; idx += WG) {
+    int r = idx / kb, c = idx - r * kb;
+    top[(size_t)(koff[a] + r) * K + koff[bq] + c] = src ? src[(size_t)r * ld + c] : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(WG) k_top_lu(double* A, int K, int* ipiv, int* flag) {
+  __shared__ ValIdx shv[WG / WAVE + 1];
+  int st = wg_lu(K, A, K, ipiv, shv);
+  if (st && threadIdx.x == 0) { flag[0] = 1; flag[1] = -1; flag[2] = 1; }
+}
+
+// ------------------------------------------------------------------------------------------
+// host orchestration
+// ------------------------------------------------------------------------------------------
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+static void launch_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{AIFMM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+static LevelPtrs ptrs(aifmm_system& s, int l) {
+  LevelDev& v = s.lev[l];
+  LevelPtrs P;
+  P.l = l;
+  P.nb = v.nb;
+  P.d = s.d;
+  P.n = v.d_n.p;
+  P.k = v.d_k.p;
+  P.kn = v.d_kn.p;
+  P.nbr_off = v.d_nbr_off.p;
+  P.nbr = v.d_nbr.p;
+  P.il_off = v.d_il_off.p;
+  P.il = v.d_il.p;
+  P.il_tr = v.d_il_tr.p;
+  P.p2_off = v.d_p2_off.p;
+  P.p2 = v.d_p2.p;
+  P.grp_off = v.d_grp_off.p;
+  P.grp_box = v.d_grp_box.p;
+  P.grp_elim = v.d_grp_elim.p;
+  P.slab = v.slab.p;
+  P.near_slot = v.d_near_slot.p;
+  P.p2_slot = v.d_p2_slot.p;
+  P.il_slot = v.d_il_slot.p;
+  P.U_off = v.d_U_off.p;
+  P.V_off = v.d_V_off.p;
+  P.l2l_off = v.d_l2l_off.p;
+  P.m2m_off = v.d_m2m_off.p;
+  P.kP = v.d_kP.p;
+  P.tslot = v.d_tslot.p;
+  P.Gmax = v.Gmax;
+  P.fslab = v.fslab.p;
+  P.fLU = v.d_fLU.p;
+  P.fC = v.d_fC.p;
+  P.fW = v.d_fW.p;
+  P.fpiv = v.d_fpiv.p;
+  P.fpiv_off = v.d_fpiv_off.p;
+  return P;
+}
+
+static int find_in(const std::vector<int>& off, const std::vector<int>& val, int b, int q) {
+  auto beg = val.begin() + off[b], end = val.begin() + off[b + 1];
+  auto it = std::lower_bound(beg, end, q);
+  if (it == end || *it != q) return -1;
+  return (int)(it - val.begin());
+}
+
+// Allocate and fill the live block store of level l.
+static void activate_level(aifmm_system& s, int l) {
+  hipStream_t st = s.stream;
+  int d = s.d, L = s.L;
+  LevelDev& lv = s.lev[l];
+  LevelPlan& P = s.plan[l];
+  int nb = lv.nb;
+  // sizes
+  lv.n.assign(nb, 0);
+  if (l == L) {
+    for (int b = 0; b < nb; ++b) lv.n[b] = s.leaf_off[b + 1] - s.leaf_off[b];
+  } else {
+    LevelDev& dn = s.lev[l + 1];
+    for (int b = 0; b < nb; ++b)
+      for (int ch = 0; ch < (1 << d); ++ch) lv.n[b] += dn.kfin[(b << d) | ch];
+  }
+  for (int b = 0; b < nb; ++b)
+    if (lv.knn[b] > lv.n[b])
+      throw Error{AIFMM_ERR_CAPACITY, "NNCA rank " + std::to_string(lv.knn[b]) + " above box size " +
+                                          std::to_string(lv.n[b]) + " at level " + std::to_string(l) + " box " +
+                                          std::to_string(b)};
+  lv.d_n.upload(lv.n, st);
+  lv.nmax = 1;
+  for (int b = 0; b < nb; ++b) lv.nmax = std::max(lv.nmax, lv.n[b]);
+  std::vector<int> kP(nb, 0);
+  if (l > 2)
+    for (int b = 0; b < nb; ++b) kP[b] = s.lev[l - 1].knn[b >> d];
+  lv.d_kP.upload(kP, st);
+  // slab layout
+  int64_t off = 0;
+  auto take = [&](int64_t cnt) { int64_t o = off; off += (cnt + 1) & ~int64_t(1); return o; };
+  std::vector<int64_t> near(P.nbr.size()), p2s(P.p2.size()), ils(P.il.size()), Uo(nb), Vo(nb), l2l(nb), m2m(nb);
+  for (int b = 0; b < nb; ++b) {
+    for (int e = P.nbr_off[b]; e < P.nbr_off[b + 1]; ++e) near[e] = take((int64_t)lv.n[b] * lv.n[P.nbr[e]]);
+    for (int e = P.p2_off[b]; e < P.p2_off[b + 1]; ++e) p2s[e] = take((int64_t)lv.n[b] * lv.n[P.p2[e]]);
+    for (int e = P.il_off[b]; e < P.il_off[b + 1]; ++e) ils[e] = take((int64_t)lv.n[b] * lv.n[P.il[e]]);
+    Uo[b] = take((int64_t)lv.n[b] * lv.n[b]);
+    Vo[b] = take((int64_t)lv.n[b] * lv.n[b]);
+    l2l[b] = take((int64_t)lv.n[b] * kP[b]);
+    m2m[b] = take((int64_t)lv.n[b] * kP[b]);
+  }
+  lv.slab.alloc(off);
+  lv.slab.zero(st);
+  lv.d_near_slot.upload(near, st);
+  lv.d_p2_slot.upload(p2s, st);
+  lv.d_il_slot.upload(ils, st);
+  lv.d_U_off.upload(Uo, st);
+  lv.d_V_off.upload(Vo, st);
+  lv.d_l2l_off.upload(l2l, st);
+  lv.d_m2m_off.upload(m2m, st);
+  // Schur target table
+  lv.Gmax = 1;
+  for (int b = 0; b < nb; ++b) lv.Gmax = std::max(lv.Gmax, P.grp_off[b + 1] - P.grp_off[b]);
+  int Gm = lv.Gmax;
+  std::vector<int64_t> ts((size_t)nb * Gm * Gm, -1);
+  for (int b = 0; b < nb; ++b) {
+    int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+    for (int gr = 0; gr < G; ++gr)
+      for (int gc = 0; gc < G; ++gc) {
+        int p = P.grp_box[g0 + gr], q = P.grp_box[g0 + gc];
+        int dist = cheb(&P.coord[p * 3], &P.coord[q * 3], d);
+        int64_t o = -1;
+        int ix;
+        if (dist <= 1) { ix = find_in(P.nbr_off, P.nbr, p, q); if (ix >= 0) o = near[ix]; }
+        else if (P.grp_elim[g0 + gr] && P.grp_elim[g0 + gc]) { ix = find_in(P.il_off, P.il, p, q); if (ix >= 0) o = ils[ix]; }
+        else { ix = find_in(P.p2_off, P.p2, p, q); if (ix >= 0) o = p2s[ix]; }
+        if (o < 0) throw Error{AIFMM_ERR_STATE, "missing Schur target slot"};
+        ts[((size_t)b * Gm + gr) * Gm + gc] = o;
+      }
+  }
+  lv.d_tslot.upload(ts, st);
+  // factor store
+  lv.fLU.assign(nb, 0);
+  lv.fPx.assign(nb, 0);
+  lv.fC.assign(nb, 0);
+  lv.fW.assign(nb, 0);
+  lv.Rcap.assign(nb, 0);
+  lv.Ccap.assign(nb, 0);
+  std::vector<int64_t> fpo(nb);
+  int64_t fo = 0, po = 0;
+  lv.Rmax = lv.Cmax = 0;
+  for (int b = 0; b < nb; ++b) {
+    int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+    int Rc = 0;
+    for (int g = 0; g < G - 1; ++g) Rc += lv.n[P.grp_box[g0 + g]];
+    int Cc = Rc + lv.n[b];
+    int mc = 2 * lv.n[b];
+    lv.Rcap[b] = Rc;
+    lv.Ccap[b] = Cc;
+    lv.Rmax = std::max(lv.Rmax, Rc);
+    lv.Cmax = std::max(lv.Cmax, Cc + lv.n[b]);
+    lv.fLU[b] = fo; fo += ((int64_t)mc * mc + 1) & ~int64_t(1);
+    lv.fC[b] = fo; fo += ((int64_t)Rc * lv.n[b] + 1) & ~int64_t(1);
+    lv.fW[b] = fo; fo += ((int64_t)mc * (Cc + lv.n[b]) + 1) & ~int64_t(1);
+    fpo[b] = po; po += mc;
+  }
+  lv.fslab.alloc(fo);
+  lv.d_fLU.upload(lv.fLU, st);
+  lv.d_fC.upload(lv.fC, st);
+  lv.d_fW.upload(lv.fW, st);
+  lv.d_fpiv_off.upload(fpo, st);
+  lv.d_fpiv.alloc(std::max<int64_t>(1, po));
+  // ranks: the NNCA ranks
+  lv.d_kn.upload(lv.knn, st);
+  lv.d_k.upload(lv.knn, st);
+
+  // contents
+  if (l == L) {
+    std::vector<int> box_off(nb + 1);
+    for (int b = 0; b <= nb; ++b) box_off[b] = s.leaf_off[b];
+    DBuf<int> d_box_off;
+    d_box_off.upload(box_off, st);
+    int maxn = 0;
+    for (int b = 0; b < nb; ++b) maxn = std::max(maxn, P.nbr_off[b + 1] - P.nbr_off[b]);
+    hipLaunchKernelGGL(k_fill_near, dim3(maxn, nb), dim3(WG), 0, st, s.K, s.d_pts.p, d, lv.d_nbr_off.p, lv.d_nbr.p,
+                       d_box_off.p, lv.d_n.p, lv.d_near_slot.p, lv.slab.p);
+    launch_check("fill near");
+    AIFMM_HIP(hipStreamSynchronize(st));
+  } else {
+    LevelDev& dn = s.lev[l + 1];
+    RepackArgs ra{d, lv.d_nbr_off.p, lv.d_nbr.p, lv.d_n.p, lv.d_near_slot.p, lv.slab.p, dn.d_k.p, dn.d_n.p,
+                  dn.d_nbr_off.p, dn.d_nbr.p, dn.d_near_slot.p, dn.d_il_off.p, dn.d_il.p, dn.d_il_slot.p, dn.slab.p};
+    int maxn = 0;
+    for (int b = 0; b < nb; ++b) maxn = std::max(maxn, P.nbr_off[b + 1] - P.nbr_off[b]);
+    hipLaunchKernelGGL(k_repack_near, dim3(maxn, nb), dim3(WG), 0, st, ra);
+    hipLaunchKernelGGL(k_stack_basis, dim3(nb), dim3(WG), 0, st, d, dn.d_k.p, dn.d_kP.p, dn.d_l2l_off.p, dn.d_m2m_off.p,
+                       dn.slab.p, lv.d_n.p, lv.d_U_off.p, lv.d_V_off.p, lv.slab.p);
+    launch_check("repack");
+  }
+  // M2L blocks from NNCA
+  {
+    int ne = (int)P.il.size();
+    if (ne) {
+      std::vector<int> rows(ne), cols(ne), ld(ne);
+      for (int b = 0; b < nb; ++b)
+        for (int e = P.il_off[b]; e < P.il_off[b + 1]; ++e) {
+          rows[e] = lv.knn[b];
+          cols[e] = lv.knn[P.il[e]];
+          ld[e] = lv.n[P.il[e]];
+        }
+      DBuf<int> dr, dc, dl;
+      dr.upload(rows, st);
+      dc.upload(cols, st);
+      dl.upload(ld, st);
+      hipLaunchKernelGGL(k_copy_blocks, dim3(ne), dim3(WG), 0, st, lv.d_m2l_nn.p, lv.d_m2l_nn_off.p, dr.p, dc.p,
+                         lv.d_il_slot.p, dl.p, lv.slab.p);
+      launch_check("m2l copy");
+      AIFMM_HIP(hipStreamSynchronize(st));
+    }
+  }
+  // leaf bases U = V from NNCA; L2L / M2M rows from the parent's NNCA operator
+  {
+    std::vector<int64_t> so, dof;
+    std::vector<int> rows, cols, ld;
+    if (l == L)
+      for (int b = 0; b < nb; ++b) {
+        so.push_back(lv.Unn_off[b]); dof.push_back(Uo[b]); rows.push_back(lv.n[b]); cols.push_back(lv.knn[b]); ld.push_back(lv.n[b]);
+        so.push_back(lv.Unn_off[b]); dof.push_back(Vo[b]); rows.push_back(lv.n[b]); cols.push_back(lv.knn[b]); ld.push_back(lv.n[b]);
+      }
+    if (!so.empty()) {
+      DBuf<int64_t> dso, ddo;
+      DBuf<int> dr, dc, dl;
+      dso.upload(so, st); ddo.upload(dof, st); dr.upload(rows, st); dc.upload(cols, st); dl.upload(ld, st);
+      hipLaunchKernelGGL(k_copy_blocks, dim3((unsigned)so.size()), dim3(WG), 0, st, lv.d_Unn.p, dso.p, dr.p, dc.p, ddo.p,
+                         dl.p, lv.slab.p);
+      launch_check("leaf bases");
+      AIFMM_HIP(hipStreamSynchronize(st));
+    }
+    if (l > 2) {
+      LevelDev& up = s.lev[l - 1];
+      so.clear(); dof.clear(); rows.clear(); cols.clear(); ld.clear();
+      for (int b = 0; b < nb; ++b) {
+        int Pb = b >> d;
+        int ro = 0;
+        for (int ch = 0; ch < (b & ((1 << d) - 1)); ++ch) ro += lv.knn[(Pb << d) | ch];
+        int64_t src = up.Unn_off[Pb] + (int64_t)ro * up.knn[Pb];
+        so.push_back(src); dof.push_back(l2l[b]); rows.push_back(lv.knn[b]); cols.push_back(kP[b]); ld.push_back(kP[b]);
+        so.push_back(src); dof.push_back(m2m[b]); rows.push_back(lv.knn[b]); cols.push_back(kP[b]); ld.push_back(kP[b]);
+      }
+      DBuf<int64_t> dso, ddo;
+      DBuf<int> dr, dc, dl;
+      dso.upload(so, st); ddo.upload(dof, st); dr.upload(rows, st); dc.upload(cols, st); dl.upload(ld, st);
+      hipLaunchKernelGGL(k_copy_blocks, dim3((unsigned)so.size()), dim3(WG), 0, st, up.d_Unn.p, dso.p, dr.p, dc.p, ddo.p,
+                         dl.p, lv.slab.p);
+      launch_check("l2l/m2m");
+      AIFMM_HIP(hipStreamSynchronize(st));
+    }
+  }
+  AIFMM_HIP(hipStreamSynchronize(st));
+}
+
+static void count_flops(aifmm_system& s, int l) {
+  LevelDev& lv = s.lev[l];
+  LevelPlan& P = s.plan[l];
+  for (int b = 0; b < lv.nb; ++b) {
+    int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+    double R = 0, C = 0;
+    for (int g = 0; g < G; ++g) {
+      int q = P.grp_box[g0 + g];
+      double dm = (g == G - 1) ? lv.kfin[b] : (P.grp_elim[g0 + g] ? lv.kfin[q] : lv.n[q]);
+      if (g < G - 1) R += dm;
+      C += dm;
+    }
+    double n = lv.n[b], m = lv.n[b] + lv.kfin[b];
+    s.stats.schur_flops += 2.0 * R * n * C;
+    s.stats.schur_bytes += 8.0 * (R * n + n * C + 2.0 * R * C);
+    s.stats.trsm_flops += 2.0 * m * m * (C + n);
+    s.stats.lu_flops += 2.0 * m * m * m / 3.0;
+  }
+}
+
+void factor_system(aifmm_system& s) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = s.stream;
+  int L = s.L;
+  s.stats.schur_flops = s.stats.schur_bytes = s.stats.trsm_flops = s.stats.lu_flops = 0;
+  s.trace.clear();
+  s.d_flag.zero(st);
+  for (int l = L; l >= 2; --l) {
+    activate_level(s, l);
+    LevelDev& lv = s.lev[l];
+    LevelPlan& Pl = s.plan[l];
+    if (l < L) s.lev[l + 1].slab.release();
+    LevelPtrs P = ptrs(s, l);
+    int cap = lv.nmax;
+    int64_t wsz = 18 * (int64_t)cap * cap + 8 * cap + 16;
+    int maxcol = 0;
+    for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) maxcol = std::max(maxcol, Pl.col_off[c + 1] - Pl.col_off[c]);
+    const int XG = 1024;
+    int kPmax = 1;
+    if (l > 2)
+      for (int b = 0; b < lv.nb; ++b) kPmax = std::max(kPmax, s.lev[l - 1].knn[b >> s.d]);
+    int64_t sstride = (int64_t)cap * std::max(cap, kPmax);
+    DBuf<double> ws, scratch;
+    ws.alloc((size_t)maxcol * wsz);
+    scratch.alloc((size_t)XG * sstride);
+    DBuf<int> d_order;
+    d_order.upload(Pl.order, st);
+    // static round and transform lists of the whole level
+    std::vector<RoundEntry> rent;
+    std::vector<XformEntry> xent;
+    std::vector<int64_t> r_off, x_off;  // per (colour, round)
+    std::vector<int> nrounds;
+    int maxblk = 1;
+    for (int b = 0; b < lv.nb; ++b) maxblk = std::max(maxblk, Pl.il_off[b + 1] - Pl.il_off[b] + 1);
+    for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) {
+      nrounds.push_back((int)Pl.rounds[c].size());
+      for (auto& round : Pl.rounds[c]) {
+        r_off.push_back((int64_t)rent.size());
+        x_off.push_back((int64_t)xent.size());
+        int pi = 0;
+        for (auto& op : round) {
+          RoundEntry E;
+          E.i = op.i;
+          E.kind = op.kind;
+          E.partner = op.partner;
+          E.e_ij = find_in(Pl.il_off, Pl.il, op.i, op.partner);
+          E.e_ji = find_in(Pl.il_off, Pl.il, op.partner, op.i);
+          E.f_ij = find_in(Pl.p2_off, Pl.p2, op.i, op.partner);
+          E.f_ji = find_in(Pl.p2_off, Pl.p2, op.partner, op.i);
+          if (E.e_ij < 0 || E.e_ji < 0 || E.f_ij < 0 || E.f_ji < 0)
+            throw Error{AIFMM_ERR_STATE, "inconsistent compression schedule"};
+          rent.push_back(E);
+          xent.push_back({op.i, op.partner, pi, 0});
+          if (op.kind == 0) xent.push_back({op.partner, op.i, pi, 1});
+          ++pi;
+        }
+      }
+    }
+    r_off.push_back((int64_t)rent.size());
+    x_off.push_back((int64_t)xent.size());
+    DBuf<RoundEntry> d_rent;
+    DBuf<XformEntry> d_xent;
+    d_rent.upload(rent, st);
+    d_xent.upload(xent, st);
+    DBuf<int> d_tr;
+    DBuf<double> d_trr;
+    d_tr.alloc(rent.size() * 6 + 6);
+    d_trr.alloc(rent.size() * 8 + 8);
+    P.trace = d_tr.p;
+    P.trace_ratio = d_trr.p;
+    size_t rix = 0;
+    for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) {
+      for (int r = 0; r < nrounds[c]; ++r, ++rix) {
+        int ne = (int)(r_off[rix + 1] - r_off[rix]);
+        int nx = (int)(x_off[rix + 1] - x_off[rix]);
+        const RoundEntry* er = d_rent.p + r_off[rix];
+        const XformEntry* ex = d_xent.p + x_off[rix];
+        hipLaunchKernelGGL(k_compress, dim3(ne), dim3(WG), 0, st, P, er, ne, ws.p, wsz, cap, s.tol, r_off[rix]);
+        int grid = std::min<int64_t>(XG, (int64_t)nx * maxblk);
+        hipLaunchKernelGGL(k_row_xform, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p, sstride);
+        hipLaunchKernelGGL(k_col_xform, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p, sstride);
+        hipLaunchKernelGGL(k_commit, dim3(cdiv(nx, WG)), dim3(WG), 0, st, P, ex, nx);
+      }
+      int nbox = Pl.col_off[c + 1] - Pl.col_off[c];
+      const int* boxes = d_order.p + Pl.col_off[c];
+      hipLaunchKernelGGL(k_elim_gather, dim3(nbox), dim3(WG), 0, st, P, boxes);
+      hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
+      hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, WG), nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
+      int tiles_c = cdiv(lv.Cmax, ST), tiles_r = cdiv(std::max(1, lv.Rmax), ST);
+      hipLaunchKernelGGL(k_elim_schur, dim3(tiles_r * tiles_c, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
+      hipLaunchKernelGGL(k_elim_zrow, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
+      launch_check("elimination");
+    }
+    lv.kfin = lv.d_k.download(st);
+    {
+      std::vector<int> tr = d_tr.download(st, rent.size() * 6);
+      std::vector<double> trr = d_trr.download(st, rent.size() * 8);
+      for (size_t q = 0; q < rent.size(); ++q) {
+        TraceRec t;
+        t.level = l;
+        t.i = rent[q].i;
+        t.kind = rent[q].kind;
+        t.partner = rent[q].partner;
+        for (int a = 0; a < 6; ++a) t.r[a] = tr[q * 6 + a];
+        for (int a = 0; a < 8; ++a) t.ratio[a] = trr[q * 8 + a];
+        s.trace.push_back(t);
+      }
+    }
+    std::vector<int> flag = s.d_flag.download(st);
+    if (flag[0]) throw Error{AIFMM_ERR_SINGULAR, "singular self-block at level " + std::to_string(flag[2]) + " box " + std::to_string(flag[1])};
+    for (int b = 0; b < lv.nb; ++b)
+      if (lv.kfin[b] > lv.n[b]) throw Error{AIFMM_ERR_CAPACITY, "rank above box size"};
+    count_flops(s, l);
+    lv.xoff.assign(lv.nb + 1, 0);
+    lv.koff.assign(lv.nb + 1, 0);
+    for (int b = 0; b < lv.nb; ++b) {
+      lv.xoff[b + 1] = lv.xoff[b] + lv.n[b];
+      lv.koff[b + 1] = lv.koff[b] + lv.kfin[b];
+    }
+  }
+  // top-level multipole system
+  {
+    LevelDev& l2 = s.lev[2];
+    s.Ktop = (int)l2.koff[l2.nb];
+    int K = std::max(1, s.Ktop);
+    s.d_top.alloc((size_t)K * K);
+    s.d_top_piv.alloc(K);
+    std::vector<int> koff32(l2.nb);
+    for (int b = 0; b < l2.nb; ++b) koff32[b] = (int)l2.koff[b];
+    DBuf<int> d_koff;
+    d_koff.upload(koff32, st);
+    if (s.Ktop > 0) {
+      hipLaunchKernelGGL(k_gather_top, dim3(l2.nb, l2.nb), dim3(WG), 0, st, l2.nb, l2.d_k.p, l2.d_n.p, d_koff.p,
+                         l2.d_nbr_off.p, l2.d_nbr.p, l2.d_near_slot.p, l2.d_il_off.p, l2.d_il.p, l2.d_il_slot.p,
+                         l2.slab.p, s.d_top.p, s.Ktop);
+      hipLaunchKernelGGL(k_top_lu, dim3(1), dim3(WG), 0, st, s.d_top.p, s.Ktop, s.d_top_piv.p, s.d_flag.p);
+      launch_check("top");
+    }
+    std::vector<int> flag = s.d_flag.download(st);
+    if (flag[0]) throw Error{AIFMM_ERR_SINGULAR, "singular level-2 multipole system"};
+    l2.slab.release();
+  }
+  AIFMM_HIP(hipStreamSynchronize(st));
+  s.stats.factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace aifmm

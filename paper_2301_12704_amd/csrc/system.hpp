@@ -1,0 +1,210 @@
+// Internal structures of the MI355X AIFMM library (host planner + device block store).
+//
+// Terminology follows the paper (arXiv 2301.12704): boxes of a uniform 2^d tree, neighbours
+// N(b) and interaction list IL(b) (Sec. 2.2), particles x, locals z and multipoles y of every
+// box at levels 2..L (Sec. 3.1), rows X / Y / Z of the extended system (equations X, Y, Z).
+//
+// Device block store of one level l (the "live" extended system while level l is being
+// eliminated):
+//   near slot  (p,q), dist_inf(p,q) <= 1 : the live block rows(p) x cols(q), where
+//              rows(p) = X_p before p is eliminated and Z_p after; cols(q) = x_q / y_q.
+//   fill slot  (p,q), dist_inf(p,q) == 2 : the accumulated P2P / P2L / M2P fill-in.
+//   M2L slot   (p,q), q in IL(p)         : A_pq = block (Z_p, y_q).
+//   per box    U_b (X_b, z_b), V_b (transpose of (Y_b, x_b)), L2L (Z_b, z_parent) and
+//              M2M (transpose of (Y_parent, y_b)).
+// Every slot (p,q) is row-major with capacity n_p x n_q and leading dimension n_q; a box's
+// rank never exceeds n_b, so every live shape fits.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/aifmm.h"
+
+namespace aifmm {
+
+struct Error {
+  aifmm_status st;
+  std::string msg;
+};
+
+#define AIFMM_HIP(x)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::aifmm::Error{AIFMM_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Device buffer owned by the system (hipMalloc / hipFree).
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw Error{AIFMM_ERR_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    n = count;
+  }
+  void zero(hipStream_t s) { if (p) AIFMM_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s)); }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    alloc(h.size());
+    if (!h.empty()) AIFMM_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  std::vector<T> download(hipStream_t s, size_t count = (size_t)-1) const {
+    if (count == (size_t)-1) count = n;
+    std::vector<T> h(count);
+    if (count) AIFMM_HIP(hipMemcpyAsync(h.data(), p, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    AIFMM_HIP(hipStreamSynchronize(s));
+    return h;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+struct KernelDesc {
+  int kind;      // 0: exp(-r/scale), 1: 1/sqrt(r^2 + scale^2)
+  double scale;  // > 0
+  double shift;  // added when i == j
+};
+
+// One compression of the static schedule (Algorithm "Efficient Elimination", the loops over
+// vP2P / vP2L before eliminating box i).
+struct PairOp {
+  int i;        // box about to be eliminated
+  int kind;     // 0 = P2P pair (i, j), 1 = P2L pair (r eliminated, i)
+  int partner;  // j (P2P) or r (P2L)
+};
+
+// Host plan of one level: lists, elimination order, colours, compression rounds and the
+// coupled-block tables of every box's elimination.
+struct LevelPlan {
+  int l = 0, nb = 0;
+  std::vector<int> coord;                 // nb * 3
+  std::vector<int> nbr_off, nbr;          // N(b), self included, Morton order
+  std::vector<int> il_off, il;            // IL(b), Morton order
+  std::vector<int> il_tr;                 // for entry e of IL(b)=d: entry index of b in IL(d)
+  std::vector<int> p2_off, p2;            // distance-2 partners, Morton order
+  std::vector<int> p2_tr;                 // transpose index inside the p2 CSR
+  std::vector<int> order, pos;            // elimination order and position of every box
+  std::vector<int> col_off;               // colour batches: order[col_off[c] .. col_off[c+1])
+  std::vector<std::vector<std::vector<PairOp>>> rounds;  // [colour][round] -> compressions
+  // coupled groups of each box elimination: G = |N(b)| entries; entries 0..G-2 are the
+  // neighbours other than b (Morton order), entry G-1 is b itself (rows Z_b / column y_b).
+  std::vector<int> grp_off;               // nb+1 (offsets into grp_box / grp_elim)
+  std::vector<int> grp_box, grp_elim;     // elim: 1 if eliminated before b
+};
+
+int cheb(const int* a, const int* b, int d);
+
+// Build the host plan of level l (lists from Sec. 2.2, colour order, compression schedule).
+void plan_level(LevelPlan& P, int d, int l);
+
+// Per-level device data.
+struct LevelDev {
+  int l = 0, nb = 0;
+  std::vector<int> n;          // x sizes n_b (host copy)
+  std::vector<int> knn;        // NNCA ranks
+  std::vector<int> kfin;       // ranks at elimination (host copy after factor)
+  std::vector<int64_t> xoff;   // prefix of n (rhs / solution offsets of x and X)
+  std::vector<int64_t> koff;   // prefix of final k (rhs / solution offsets of y, z, Y, Z)
+  DBuf<int> d_n, d_k, d_kn;    // n_b, current rank, next rank
+  // plan tables on device
+  DBuf<int> d_nbr_off, d_nbr, d_il_off, d_il, d_il_tr, d_p2_off, d_p2, d_grp_off, d_grp_box, d_grp_elim;
+  // NNCA outputs (compact, valid for the whole factorization)
+  std::vector<int> T_off;      // row set sizes prefix: ACA rows of box b
+  DBuf<int> d_T;               // row sets (tree positions), |T_b| per box
+  DBuf<int> d_T_off;
+  DBuf<int> d_piv_r, d_piv_c;  // pivot rows / cols (tree positions), capacity |T_b| per box
+  DBuf<double> d_Unn;          // U_B = A[T_B, s_i] C^{-1}, |T_B| x k_B row-major
+  std::vector<int64_t> Unn_off;
+  DBuf<int64_t> d_Unn_off;
+  DBuf<double> d_m2l_nn;       // A_BD, k_B x k_D, one per IL entry
+  std::vector<int64_t> m2l_nn_off;
+  DBuf<int64_t> d_m2l_nn_off;
+  // live block store (allocated when the level is eliminated)
+  DBuf<double> slab;
+  DBuf<int64_t> d_near_slot, d_p2_slot, d_il_slot;   // per CSR entry
+  DBuf<int64_t> d_U_off, d_V_off, d_l2l_off, d_m2m_off;  // per box
+  DBuf<int> d_kP;              // NNCA rank of the parent (columns of L2L / M2M), 0 at level 2
+  DBuf<int64_t> d_tslot;       // per box: Gmax x Gmax target offsets (Schur scatter)
+  // factor store (kept for the solve)
+  DBuf<double> fslab;
+  DBuf<int64_t> d_fLU, d_fPx, d_fC, d_fW;  // per box offsets into fslab
+  DBuf<int> d_fpiv;            // ipiv, capacity 2 n_b per box
+  DBuf<int64_t> d_fpiv_off;
+  std::vector<int64_t> fLU, fPx, fC, fW;   // host copies of the offsets
+  std::vector<int> Rcap, Ccap;
+  int nmax = 0, Rmax = 0, Cmax = 0, Gmax = 0;
+};
+
+// decision log of one compression (static schedule entry plus the ranks it decided)
+struct TraceRec {
+  int level, i, kind, partner;
+  int r[6];
+  double ratio[8];
+};
+
+struct Stats {
+  double build_s = 0, factor_s = 0, solve_s = 0;
+  double schur_flops = 0, schur_bytes = 0, trsm_flops = 0, lu_flops = 0;
+};
+
+}  // namespace aifmm
+
+struct aifmm_system {
+  int d = 2, L = 2, leaf = 64, device = 0;
+  int64_t N = 0;
+  aifmm::KernelDesc K{};
+  double tol = 1e-10;
+  hipStream_t stream = nullptr;
+  bool factored = false;
+  std::string err;
+  // tree
+  aifmm::DBuf<double> d_pts;      // points in tree order, N x d
+  aifmm::DBuf<int64_t> d_perm;    // tree position -> original index
+  std::vector<int> leaf_off;      // nb_L + 1, point offsets of leaves in tree order
+  std::vector<aifmm::LevelPlan> plan;   // by level, 0..L
+  std::vector<aifmm::LevelDev> lev;     // by level, 0..L (2..L used)
+  // top-level multipole system
+  int Ktop = 0;
+  aifmm::DBuf<double> d_top;
+  aifmm::DBuf<int> d_top_piv;
+  // workspaces
+  aifmm::DBuf<double> ws;         // compression / transform / elimination scratch
+  aifmm::DBuf<int> d_flag;        // [0] singular flag, [1] box, [2] level, [3] capacity flag
+  aifmm::DBuf<int> d_rounds;      // scratch upload area for round lists
+  aifmm::Stats stats;
+  std::vector<aifmm::TraceRec> trace;
+  size_t device_bytes = 0;
+};
+
+namespace aifmm {
+// build.hip
+void build_system(aifmm_system& s, const double* pts_host_or_dev, bool on_device);
+// factor.hip
+void factor_system(aifmm_system& s);
+// solve.hip
+void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx,
+                  bool b_dev, bool x_dev);
+}  // namespace aifmm

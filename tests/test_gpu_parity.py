@@ -1,0 +1,150 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar (from the method's required outputs): per-level box -> rank tables bit-exact (NNCA ranks,
+pivot lists and the ranks chosen by every compression), solution relative error <= 1e-8
+against the oracle's solution, and the brute-force residual of the GPU solution equal to the
+oracle's within 1e-6 relative.  Both sides execute the same IEEE operation sequence on the
+rank-deciding path (explicit fused multiply-adds, no contraction elsewhere), so the decisions
+agree exactly unless a decision ratio lies within rounding of the threshold; the oracle's
+decision-margin log is printed on failure for attribution.
+"""
+import numpy as np
+import pytest
+
+import aifmm_inputs as I
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+A = pytest.importorskip("paper_2301_12704_amd")
+
+CASES = [
+    # (name, n, d, depth, kernel, tol, nrhs, seed)
+    ("exp_L2", 1024, 2, 2, ("exp", 1.0, 0.1), 1e-10, 1, 7),
+    ("c1_config", 4096, 2, 3, ("exp", 1.0, 0.1), 1e-10, 1, 1001),
+    ("invmq_L3", 4096, 2, 3, ("invmq", 1e-2, 1.0), 1e-8, 3, 21),
+    ("ragged_2000", 2000, 2, 3, ("exp", 1.0, 0.1), 1e-8, 2, 22),
+    ("exp_half_L4", 8192, 2, 4, ("exp", 0.5, 0.05), 1e-8, 1, 23),
+    ("3d_L2", 3000, 3, 2, ("invmq", 3000 ** (-1.0 / 3.0), 1.0), 1e-6, 2, 24),
+]
+
+
+def _run(n, d, depth, kernel, tol, nrhs, seed, pts=None):
+    if pts is None:
+        c = I.small_case(n, d=d, depth=depth, tol=tol, kernel=kernel, nrhs=nrhs, seed=seed)
+        pts, b = c["pts"], c["b"]
+    else:
+        b = np.asfortranarray(np.random.default_rng(seed).standard_normal((pts.shape[0], nrhs)))
+    print(f"case n={pts.shape[0]} d={d} depth={depth} kernel={kernel} tol={tol} nrhs={nrhs} seed={seed}", flush=True)
+    g = A.System(pts, kernel, tol, 64, depth)
+    o = oracle.System(pts, kernel, tol, 64, depth)
+    return g, o, pts, b
+
+
+def _compare(g, o, pts, b, kernel):
+    L = g.L
+    assert L == o.L
+    for l in range(2, L + 1):
+        np.testing.assert_array_equal(g.ranks(l), o.nnca_ranks(l), err_msg=f"NNCA ranks level {l}")
+        for box in range(0, 1 << (g.d * l), max(1, (1 << (g.d * l)) // 16)):
+            ti, si, _ = g.nnca(l, box)
+            oti, osi = o.pivots(l, box)
+            np.testing.assert_array_equal(ti, oti, err_msg=f"row pivots level {l} box {box}")
+            np.testing.assert_array_equal(si, osi, err_msg=f"column pivots level {l} box {box}")
+    g.factor()
+    o.factor()
+    grec, _ = g.trace()
+    otr = o.trace()
+    ork, ora = o.trace_ranks()
+    assert len(grec) == len(otr)
+    gmap = {tuple(r[:4]): r[4:] for r in grec}
+    for q in range(len(otr)):
+        key = tuple(otr[q])
+        assert key in gmap, f"compression {key} missing on the device"
+        if not np.array_equal(gmap[key], ork[q]):
+            pytest.fail(f"compression {key}: device ranks {gmap[key]} oracle {ork[q]} "
+                        f"(oracle decision ratios {ora[q]}, min margin {o.margins()[0]:.3e})")
+    for l in range(2, L + 1):
+        np.testing.assert_array_equal(g.ranks(l), o.final_ranks(l), err_msg=f"final ranks level {l}")
+    x = g.solve(b)
+    xo = o.solve(b)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert err <= 1e-8, f"solution error vs oracle {err:.3e}"
+    res_g = np.linalg.norm(oracle.matvec(pts, kernel, x) - b) / np.linalg.norm(b)
+    res_o = np.linalg.norm(oracle.matvec(pts, kernel, xo) - b) / np.linalg.norm(b)
+    assert abs(res_g - res_o) <= 1e-6 * max(res_o, 1e-300) + 1e-14
+    return err, res_g
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_parity(case):
+    _, n, d, depth, kernel, tol, nrhs, seed = case
+    g, o, pts, b = _run(n, d, depth, kernel, tol, nrhs, seed)
+    err, res = _compare(g, o, pts, b, kernel)
+    print(f"solution error vs oracle {err:.3e}, residual {res:.3e}")
+
+
+def test_empty_and_sparse_boxes():
+    """Points clustered in one corner and a thin strip: many empty leaves and boxes with a
+    handful of points (ranks capped by box sizes)."""
+    rng = np.random.default_rng(31)
+    a = rng.uniform(-1, -0.2, (1500, 2))
+    strip = np.c_[rng.uniform(-1, 1, 500), rng.uniform(0.9, 1.0, 500)]
+    pts = np.ascontiguousarray(np.vstack([a, strip]))
+    g, o, pts, b = _run(0, 2, 3, ("exp", 1.0, 0.1), 1e-8, 2, 32, pts=pts)
+    assert (o.counts(3) == 0).sum() > 10
+    _compare(g, o, pts, b, ("exp", 1.0, 0.1))
+
+
+def test_tiny_boxes():
+    """N=200 on a depth-3 tree: ~3 points per leaf, ranks limited by box sizes."""
+    c = I.small_case(200, depth=3, tol=1e-10, kernel=("invmq", 1e-2, 1.0), nrhs=1, seed=33)
+    g, o, pts, b = _run(200, 2, 3, ("invmq", 1e-2, 1.0), 1e-10, 1, 33, pts=c["pts"])
+    _compare(g, o, pts, b, ("invmq", 1e-2, 1.0))
+
+
+def test_solve_repeat_and_multi_rhs_consistency():
+    c = I.small_case(4096, depth=3, tol=1e-8, kernel=("invmq", 1e-2, 1.0), nrhs=5, seed=34)
+    g = A.System(c["pts"], c["kernel"], c["tol"], 64, 3)
+    g.factor()
+    x5 = g.solve(c["b"])
+    x1 = g.solve(np.asfortranarray(c["b"][:, 2:3]))
+    np.testing.assert_allclose(x1[:, 0], x5[:, 2], rtol=0, atol=1e-13 * np.abs(x5).max())
+    x5b = g.solve(c["b"])
+    np.testing.assert_array_equal(x5, x5b)
+
+
+def test_device_pointers():
+    torch = pytest.importorskip("torch")
+    c = I.small_case(2048, depth=3, tol=1e-8, kernel=("exp", 1.0, 0.1), nrhs=2, seed=35)
+    pts_d = torch.from_numpy(c["pts"]).cuda()
+    g = A.System(pts_d, c["kernel"], c["tol"], 64, 3)
+    g.factor()
+    b_d = torch.from_numpy(np.ascontiguousarray(c["b"].T)).cuda()  # (nrhs, N): column-major N x nrhs
+    x_d = g.solve(b_d)
+    x_h = g.solve(c["b"])
+    np.testing.assert_array_equal(x_d.cpu().numpy().T, x_h)
+
+
+def test_state_errors():
+    c = I.small_case(1024, depth=2)
+    g = A.System(c["pts"], c["kernel"], c["tol"], 64, 2)
+    with pytest.raises(A.AifmmError) as e:
+        g.solve(c["b"])
+    assert e.value.status == 4
+    g.factor()
+    with pytest.raises(A.AifmmError) as e:
+        g.factor()
+    assert e.value.status == 4
+
+
+def test_singular_self_block_reports_box():
+    """Duplicated points with zero diagonal shift make a leaf self-block exactly singular."""
+    rng = np.random.default_rng(36)
+    p = rng.uniform(-1, 1, (512, 2))
+    pts = np.ascontiguousarray(np.vstack([p, p]))
+    g = A.System(pts, ("exp", 1.0, 0.0), 1e-8, 64, 2)
+    with pytest.raises(A.AifmmError) as e:
+        g.factor()
+    assert e.value.status == 3
+    assert "box" in str(e.value)
