@@ -41,6 +41,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIBPATH):
             raise ImportError(f"{LIBPATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+        # One HIP runtime per process: when PyTorch is present its runtime is loaded first, and
+        # the library's libamdhip64.so.7 dependency then resolves to that same object.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIBPATH)
         vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.aifmm_options_default.argtypes = [ctypes.POINTER(_Options)]
