@@ -88,6 +88,19 @@ aifmm_status aifmm_factor(aifmm_system* s);
 /* x = (factored A)^{-1} b for nrhs right-hand sides (Sec. 3.4). */
 aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx);
 
+/* y = A x with every kernel entry evaluated in FP64 (exact product, O(N^2) work; used for
+ * residuals and as the operator of aifmm_gmres).  Same layouts as aifmm_solve. */
+aifmm_status aifmm_matvec(aifmm_system* s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy);
+
+/* Solve A x = b to relative residual ||A x - b|| / ||b|| <= rtol for every column with
+ * right-preconditioned flexible GMRES(restart) in FP64: operator aifmm_matvec, preconditioner
+ * the factored system's aifmm_solve (AIFMM as a preconditioner, Sec. 4, Experiment 5).  x is
+ * an output (the iteration starts from 0).  iters[nrhs] and relres[nrhs] (may be NULL) receive
+ * per-column iteration counts and true relative residuals.  AIFMM_ERR_NOCONV if some column
+ * is above rtol after maxit iterations (x then holds the last iterate). */
+aifmm_status aifmm_gmres(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int32_t restart,
+                         int32_t maxit, double* x, int64_t ldx, int32_t* iters, double* relres);
+
 /* Tree depth L. */
 aifmm_status aifmm_get_depth(const aifmm_system* s, int32_t* L);
 /* Ranks of the 2^(d*level) boxes of a level (2 <= level <= L): the NNCA ranks before
@@ -100,6 +113,11 @@ enum {
   AIFMM_STAT_SCHUR_BYTES = 4,     /* minimum HBM bytes of those GEMMs                 */
   AIFMM_STAT_TRSM_FLOPS = 5, AIFMM_STAT_LU_FLOPS = 6,
   AIFMM_STAT_DEVICE_BYTES = 7,    /* device bytes held by the system                  */
+  AIFMM_STAT_SCHUR_KERNEL_S = 8,  /* summed device time of the Schur-update launches (HIP events) */
+  AIFMM_STAT_SCHUR_LAUNCHES = 9,
+  AIFMM_STAT_COMPRESS_KERNEL_S = 10, /* summed device time of the compression launches */
+  AIFMM_STAT_COMPRESS_LAUNCHES = 11,
+  AIFMM_STAT_GMRES_S = 12,        /* wall time of the last aifmm_gmres call */
   AIFMM_STAT_COUNT = 16
 };
 aifmm_status aifmm_get_stats(const aifmm_system* s, double* stats /* AIFMM_STAT_COUNT */);

@@ -15,7 +15,7 @@ KERNELS = {"exp": 0, "invmq": 1}
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_SINGULAR", 4: "ERR_STATE", 5: "ERR_DEVICE",
           6: "ERR_NOCONV", 7: "ERR_CAPACITY", 8: "ERR_BUSY"}
 STAT_NAMES = ["build_s", "factor_s", "solve_s", "schur_flops", "schur_bytes", "trsm_flops", "lu_flops",
-              "device_bytes"]
+              "device_bytes", "schur_kernel_s", "schur_launches", "compress_kernel_s", "compress_launches", "gmres_s"]
 
 
 class AifmmError(RuntimeError):
@@ -58,6 +58,10 @@ def lib():
         L.aifmm_get_stats.argtypes = [vp, vp]
         L.aifmm_get_trace.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.aifmm_get_trace.restype = ctypes.c_int
+        L.aifmm_matvec.argtypes = [vp, vp, i64, i64, vp, i64]
+        L.aifmm_matvec.restype = ctypes.c_int
+        L.aifmm_gmres.argtypes = [vp, vp, i64, i64, d, i32, i32, vp, i64, vp, vp]
+        L.aifmm_gmres.restype = ctypes.c_int
         L.aifmm_get_nnca.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.aifmm_get_nnca.restype = ctypes.c_int
         L.aifmm_last_error.argtypes = [vp]
@@ -134,6 +138,26 @@ class System:
         x = np.zeros_like(b2, order="F")
         _check(lib().aifmm_solve(self._h, _ptr(b2), b2.shape[1], self.N, _ptr(x), self.N), self._h)
         return x.reshape(np.shape(b))
+
+    def matvec(self, x):
+        """y = A x (exact FP64, every kernel entry evaluated on the device)."""
+        x2 = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(self.N, -1))
+        y = np.zeros_like(x2, order="F")
+        _check(lib().aifmm_matvec(self._h, _ptr(x2), x2.shape[1], self.N, _ptr(y), self.N), self._h)
+        return y.reshape(np.shape(x))
+
+    def gmres(self, b, rtol=1e-10, restart=30, maxit=200, raise_on_noconv=True):
+        """FGMRES to ||Ax-b||/||b|| <= rtol, preconditioned by the factorization.
+        Returns (x, iters, relres)."""
+        b2 = np.asfortranarray(np.asarray(b, dtype=np.float64).reshape(self.N, -1))
+        x = np.zeros_like(b2, order="F")
+        it = np.zeros(b2.shape[1], np.int32)
+        rr = np.zeros(b2.shape[1])
+        st = lib().aifmm_gmres(self._h, _ptr(b2), b2.shape[1], self.N, float(rtol), restart, maxit, _ptr(x), self.N,
+                               _ptr(it), _ptr(rr))
+        if st != 0 and (raise_on_noconv or st != 6):
+            _check(st, self._h)
+        return x.reshape(np.shape(b)), it, rr
 
     def ranks(self, level):
         out = np.zeros(1 << (self.d * level), np.int32)

@@ -1,6 +1,7 @@
 // C ABI of the library (declarations and contracts in include/aifmm.h).
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -121,6 +122,30 @@ aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t
   });
 }
 
+aifmm_status aifmm_matvec(aifmm_system* s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy) {
+  if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  if (!x || !y || nrhs <= 0 || ldx < s->N || ldy < s->N || nrhs > 4096) return fail(s, AIFMM_ERR_ARG, "bad x/y/nrhs/ld");
+  return guarded(s, [&] {
+    AIFMM_HIP(hipSetDevice(s->device));
+    aifmm::matvec_system(*s, x, nrhs, ldx, y, ldy, is_device_ptr(x), is_device_ptr(y));
+  });
+}
+
+aifmm_status aifmm_gmres(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int32_t restart,
+                         int32_t maxit, double* x, int64_t ldx, int32_t* iters, double* relres) {
+  if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  if (!s->factored) return fail(s, AIFMM_ERR_STATE, "gmres before factor");
+  if (!b || !x || nrhs <= 0 || ldb < s->N || ldx < s->N || nrhs > 4096 || !(rtol > 0.0) || restart <= 0 || maxit <= 0)
+    return fail(s, AIFMM_ERR_ARG, "bad b/x/nrhs/ld/rtol/restart/maxit");
+  auto t0 = std::chrono::steady_clock::now();
+  aifmm_status st = guarded(s, [&] {
+    AIFMM_HIP(hipSetDevice(s->device));
+    aifmm::gmres_system(*s, b, nrhs, ldb, rtol, restart, maxit, x, ldx, iters, relres, is_device_ptr(b), is_device_ptr(x));
+  });
+  s->stats.gmres_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
 aifmm_status aifmm_get_depth(const aifmm_system* s, int32_t* L) {
   if (!s || !L) return fail(nullptr, AIFMM_ERR_ARG, "NULL argument");
   *L = s->L;
@@ -149,6 +174,11 @@ aifmm_status aifmm_get_stats(const aifmm_system* s, double* stats) {
   double bytes = 0;
   for (const auto& lv : s->lev) bytes += (double)lv.fslab.bytes() + (double)lv.slab.bytes() + (double)lv.d_Unn.bytes();
   stats[AIFMM_STAT_DEVICE_BYTES] = bytes;
+  stats[AIFMM_STAT_SCHUR_KERNEL_S] = s->stats.schur_kernel_s;
+  stats[AIFMM_STAT_SCHUR_LAUNCHES] = s->stats.schur_launches;
+  stats[AIFMM_STAT_COMPRESS_KERNEL_S] = s->stats.compress_kernel_s;
+  stats[AIFMM_STAT_COMPRESS_LAUNCHES] = s->stats.compress_launches;
+  stats[AIFMM_STAT_GMRES_S] = s->stats.gmres_s;
   return AIFMM_OK;
 }
 

@@ -62,7 +62,9 @@ __device__ inline bool vi_better(const ValIdx& a, const ValIdx& b) {
   return a.v > b.v || (a.v == b.v && a.i < b.i);
 }
 
-// argmax over the workgroup, ties to the lowest index; invalid lanes pass v = -1, i = INT_MAX
+// Workgroup-wide reductions for NT threads (NT a multiple of 64).  sh needs NT/64 + 1 slots.
+// argmax: ties to the lowest index; invalid lanes pass v = -1, i = INT_MAX.
+template <int NT = WG>
 __device__ inline ValIdx wg_argmax(ValIdx x, ValIdx* sh) {
   for (int off = WAVE / 2; off > 0; off >>= 1) {
     ValIdx o;
@@ -76,16 +78,17 @@ __device__ inline ValIdx wg_argmax(ValIdx x, ValIdx* sh) {
   __syncthreads();
   if (threadIdx.x == 0) {
     ValIdx b = sh[0];
-    for (int q = 1; q < WG / WAVE; ++q)
+    for (int q = 1; q < NT / WAVE; ++q)
       if (vi_better(sh[q], b)) b = sh[q];
-    sh[WG / WAVE] = b;
+    sh[NT / WAVE] = b;
   }
   __syncthreads();
-  ValIdx r = sh[WG / WAVE];
+  ValIdx r = sh[NT / WAVE];
   __syncthreads();
   return r;
 }
 
+template <int NT = WG>
 __device__ inline double wg_sum(double x, double* sh) {
   for (int off = WAVE / 2; off > 0; off >>= 1) x += __shfl_down(x, off, WAVE);
   int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
@@ -94,22 +97,25 @@ __device__ inline double wg_sum(double x, double* sh) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int q = 0; q < WG / WAVE; ++q) s += sh[q];
-    sh[WG / WAVE] = s;
+    for (int q = 0; q < NT / WAVE; ++q) s += sh[q];
+    sh[NT / WAVE] = s;
   }
   __syncthreads();
-  double r = sh[WG / WAVE];
+  double r = sh[NT / WAVE];
   __syncthreads();
   return r;
 }
 
 // C = alpha * op(A) op(B) + beta * C  (row-major; op = transpose when the flag is set).
+// Every output element accumulates its products in ascending k with fused multiply-adds.
 // C must not alias A or B.  beta == 0 never reads C.
+template <int NT = WG>
 __device__ inline void wg_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda, bool ta,
                                const double* __restrict__ B, int ldb, bool tb, double beta, double* C, int ldc) {
-  for (int idx = threadIdx.x; idx < M * N; idx += WG) {
+  for (int idx = threadIdx.x; idx < M * N; idx += NT) {
     int r = idx / N, c = idx - r * N;
     double acc = 0.0;
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
       double a = ta ? A[(size_t)k * lda + r] : A[(size_t)r * lda + k];
       double b = tb ? B[(size_t)c * ldb + k] : B[(size_t)k * ldb + c];
@@ -122,15 +128,17 @@ __device__ inline void wg_gemm(int M, int N, int K, double alpha, const double* 
   __syncthreads();
 }
 
+template <int NT = WG>
 __device__ inline void wg_copy(int M, int N, const double* __restrict__ A, int lda, double* __restrict__ C, int ldc) {
-  for (int idx = threadIdx.x; idx < M * N; idx += WG) {
+  for (int idx = threadIdx.x; idx < M * N; idx += NT) {
     int r = idx / N, c = idx - r * N;
     C[(size_t)r * ldc + c] = A[(size_t)r * lda + c];
   }
   __syncthreads();
 }
+template <int NT = WG>
 __device__ inline void wg_zero(int M, int N, double* C, int ldc) {
-  for (int idx = threadIdx.x; idx < M * N; idx += WG) {
+  for (int idx = threadIdx.x; idx < M * N; idx += NT) {
     int r = idx / N, c = idx - r * N;
     C[(size_t)r * ldc + c] = 0.0;
   }
@@ -138,39 +146,43 @@ __device__ inline void wg_zero(int M, int N, double* C, int ldc) {
 }
 
 // Householder QR with column pivoting on the m x n row-major matrix M (destroyed), truncated
-// at the first step whose largest trailing column norm is <= tol times the first one
-// (RRQR with threshold eps_A of Sec. 3.2.1).  Reflector s is stored in column s of V
-// (m x n row-major, ldv) with V[s][s] = 1, tau[s] its scale.  nrm is scratch of length n.
-// Returns the rank.
+// at the first step whose pivot column norm is <= tol times the first one (RRQR with
+// threshold eps_A of Sec. 3.2.1).  Pivot: the lowest-index column whose trailing norm is
+// within a relative 1e-11 of the largest, so norms equal in exact arithmetic (orthonormal
+// basis columns) tie whatever the rounding.  Trailing norms are sums over the rows in
+// ascending order; the norms of step s+1 are formed while the reflector of step s is applied
+// (the same sums as recomputing them).  Reflector s is stored in column s of V (ldv) with
+// V[s][s] = 1, tau[s] its scale; nrm is scratch of length n.  Returns the rank; ratio (if
+// given) receives |R_kk|/(tol |R_11|) of the last kept and of the first rejected pivot.
+template <int NT = WG>
 __device__ inline int wg_cpqr(int m, int n, double* M, int ldm, double tol, double* V, int ldv, double* tau,
                               double* nrm, ValIdx* shv, double* ratio = nullptr) {
   double kept = 0.0, next = 0.0;
   int smax = m < n ? m : n;
   double r11 = 0.0;
+  for (int j = threadIdx.x; j < n; j += NT) {
+    double t = 0.0;
+#pragma unroll 8
+    for (int i = 0; i < m; ++i) {
+      double a = M[(size_t)i * ldm + j];
+      t = fma(a, a, t);
+    }
+    nrm[j] = sqrt(t);
+  }
+  __syncthreads();
   int s = 0;
   for (; s < smax; ++s) {
-    for (int j = s + (int)threadIdx.x; j < n; j += WG) {
-      double t = 0.0;
-      for (int i = s; i < m; ++i) {
-        double a = M[(size_t)i * ldm + j];
-        t = fma(a, a, t);
-      }
-      nrm[j] = sqrt(t);
-    }
-    __syncthreads();
-    // pivot: lowest-index column whose norm is within a relative 1e-11 of the largest, so
-    // norms equal in exact arithmetic (orthonormal basis columns) tie whatever the rounding
     ValIdx mx{-1.0, INT_MAX};
-    for (int j = s + (int)threadIdx.x; j < n; j += WG) {
+    for (int j = s + (int)threadIdx.x; j < n; j += NT) {
       ValIdx c{nrm[j], j};
       if (vi_better(c, mx)) mx = c;
     }
-    mx = wg_argmax(mx, shv);
+    mx = wg_argmax<NT>(mx, shv);
     double thr = mx.v * (1.0 - 1e-11);
     ValIdx best{-1.0, INT_MAX};
-    for (int j = s + (int)threadIdx.x; j < n; j += WG)
+    for (int j = s + (int)threadIdx.x; j < n; j += NT)
       if (nrm[j] >= thr && j < best.i) best = ValIdx{0.0, j};
-    best = wg_argmax(best, shv);
+    best = wg_argmax<NT>(best, shv);
     best.v = nrm[best.i];
     if (s == 0) {
       r11 = best.v;
@@ -182,19 +194,24 @@ __device__ inline int wg_cpqr(int m, int n, double* M, int ldm, double tol, doub
     kept = best.v / (tol * r11);
     int p = best.i;
     if (p != s) {
-      for (int i = threadIdx.x; i < m; i += WG) {
+      for (int i = threadIdx.x; i < m; i += NT) {
         double a = M[(size_t)i * ldm + s];
         M[(size_t)i * ldm + s] = M[(size_t)i * ldm + p];
         M[(size_t)i * ldm + p] = a;
       }
       __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = nrm[s];
+        nrm[s] = nrm[p];
+        nrm[p] = t;
+      }
     }
     double x0 = M[(size_t)s * ldm + s];
     double alpha = best.v;
     double beta = x0 >= 0.0 ? -alpha : alpha;
     double scale = x0 - beta;
     double tv = (beta - x0) / beta;
-    for (int i = threadIdx.x; i < m; i += WG) {
+    for (int i = threadIdx.x; i < m; i += NT) {
       double v = 0.0;
       if (i == s) v = 1.0;
       else if (i > s) v = M[(size_t)i * ldm + s] / scale;
@@ -202,33 +219,51 @@ __device__ inline int wg_cpqr(int m, int n, double* M, int ldm, double tol, doub
     }
     if (threadIdx.x == 0) tau[s] = tv;
     __syncthreads();
-    for (int j = s + 1 + (int)threadIdx.x; j < n; j += WG) {
+    for (int j = s + 1 + (int)threadIdx.x; j < n; j += NT) {
       double w = 0.0;
+#pragma unroll 8
       for (int i = s; i < m; ++i) w = fma(V[(size_t)i * ldv + s], M[(size_t)i * ldm + j], w);
       w *= tv;
-      for (int i = s; i < m; ++i) M[(size_t)i * ldm + j] = fma(-w, V[(size_t)i * ldv + s], M[(size_t)i * ldm + j]);
+      double t = 0.0;
+      {
+        double a = fma(-w, V[(size_t)s * ldv + s], M[(size_t)s * ldm + j]);
+        M[(size_t)s * ldm + j] = a;
+      }
+#pragma unroll 8
+      for (int i = s + 1; i < m; ++i) {
+        double a = fma(-w, V[(size_t)i * ldv + s], M[(size_t)i * ldm + j]);
+        M[(size_t)i * ldm + j] = a;
+        t = fma(a, a, t);
+      }
+      nrm[j] = sqrt(t);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += WG) M[(size_t)i * ldm + s] = (i == s) ? beta : (i > s ? 0.0 : M[(size_t)i * ldm + s]);
+    for (int i = threadIdx.x; i < m; i += NT) M[(size_t)i * ldm + s] = (i == s) ? beta : (i > s ? 0.0 : M[(size_t)i * ldm + s]);
     __syncthreads();
   }
   if (ratio && threadIdx.x == 0) { ratio[0] = kept; ratio[1] = next; }
+  __syncthreads();
   return s;
 }
 
-// Q[:, 0:q] = H_0 H_1 ... H_{rank-1} [I; 0]  (m x q row-major, ldq)
-__device__ inline void wg_formq(int m, int rank, int q, const double* V, int ldv, const double* tau, double* Q, int ldq) {
-  for (int idx = threadIdx.x; idx < m * q; idx += WG) {
-    int r = idx / q, c = idx - r * q;
+// Columns c0 .. q-1 of Q = H_0 H_1 ... H_{rank-1} [I; 0]  (m x q row-major, ldq); columns
+// below c0 are left untouched (already formed).
+template <int NT = WG>
+__device__ inline void wg_formq(int m, int rank, int q, const double* V, int ldv, const double* tau, double* Q, int ldq,
+                                int c0 = 0) {
+  for (int idx = threadIdx.x; idx < m * (q - c0); idx += NT) {
+    int r = idx / (q - c0), c = c0 + idx % (q - c0);
     Q[(size_t)r * ldq + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int s = rank - 1; s >= 0; --s) {
     double tv = tau[s];
-    for (int j = threadIdx.x; j < q; j += WG) {
+    for (int j = c0 + threadIdx.x; j < q; j += NT) {
       double w = 0.0;
+#pragma unroll 8
       for (int i = s; i < m; ++i) w = fma(V[(size_t)i * ldv + s], Q[(size_t)i * ldq + j], w);
       w *= tv;
+#pragma unroll 8
       for (int i = s; i < m; ++i) Q[(size_t)i * ldq + j] = fma(-w, V[(size_t)i * ldv + s], Q[(size_t)i * ldq + j]);
     }
     __syncthreads();
@@ -237,19 +272,20 @@ __device__ inline void wg_formq(int m, int rank, int q, const double* V, int ldv
 
 // In-place LU with row partial pivoting (ties to the lowest row) of the m x m row-major A;
 // ipiv[k] is the row swapped with k at step k.  Returns 0 or 1+k for an exactly zero pivot.
+template <int NT = WG>
 __device__ inline int wg_lu(int m, double* A, int lda, int* ipiv, ValIdx* shv) {
   for (int k = 0; k < m; ++k) {
     ValIdx best{-1.0, INT_MAX};
-    for (int i = k + (int)threadIdx.x; i < m; i += WG) {
+    for (int i = k + (int)threadIdx.x; i < m; i += NT) {
       ValIdx c{fabs(A[(size_t)i * lda + k]), i};
       if (vi_better(c, best)) best = c;
     }
-    best = wg_argmax(best, shv);
+    best = wg_argmax<NT>(best, shv);
     if (best.v == 0.0) return 1 + k;
     int p = best.i;
     if (threadIdx.x == 0) ipiv[k] = p;
     if (p != k) {
-      for (int j = threadIdx.x; j < m; j += WG) {
+      for (int j = threadIdx.x; j < m; j += NT) {
         double a = A[(size_t)k * lda + j];
         A[(size_t)k * lda + j] = A[(size_t)p * lda + j];
         A[(size_t)p * lda + j] = a;
@@ -258,9 +294,9 @@ __device__ inline int wg_lu(int m, double* A, int lda, int* ipiv, ValIdx* shv) {
     __syncthreads();
     double piv = A[(size_t)k * lda + k];
     int rem = m - k - 1;
-    for (int i = threadIdx.x; i < rem; i += WG) A[(size_t)(k + 1 + i) * lda + k] /= piv;
+    for (int i = threadIdx.x; i < rem; i += NT) A[(size_t)(k + 1 + i) * lda + k] /= piv;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < rem * rem; idx += WG) {
+    for (int idx = threadIdx.x; idx < rem * rem; idx += NT) {
       int i = k + 1 + idx / rem, j = k + 1 + idx % rem;
       A[(size_t)i * lda + j] = fma(-A[(size_t)i * lda + k], A[(size_t)k * lda + j], A[(size_t)i * lda + j]);
     }

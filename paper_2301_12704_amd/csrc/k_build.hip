@@ -115,6 +115,7 @@ struct AcaArgs {
   const int64_t* ws_off; // per box: start of U/V workspace in doubles
   double* ws;
   unsigned char* cused;  // |F| per box
+  unsigned char* rused;  // |T| per box (at T_off)
   int* piv_r;            // per box at T_off: pivot row positions (tree positions)
   int* piv_c;
   int* rank;             // k_b
@@ -134,15 +135,11 @@ __global__ void __launch_bounds__(WG) k_aca(AcaArgs a) {
   double* V = U + (size_t)kmax * m;        // kmax x n
   double* r = V + (size_t)kmax * n;        // n  (residual row)
   double* du = r + n;                      // kmax
+  double* dvw = du + kmax;                 // kmax
   unsigned char* cused = a.cused + fbase;
+  unsigned char* rused = a.rused + t0;
   __shared__ ValIdx shv[WG / WAVE + 1];
   __shared__ double shd[WG / WAVE + 1];
-  __shared__ unsigned char rused[1024];
-  __shared__ double dvw[256];
-  if (m > 1024 || kmax > 256) {
-    if (threadIdx.x == 0) atomicExch(&a.flag[3], 1);
-    return;
-  }
   for (int t = threadIdx.x; t < m; t += WG) rused[t] = 0;
   for (int j = threadIdx.x; j < n; j += WG) cused[j] = 0;
   __syncthreads();
@@ -434,21 +431,22 @@ void build_system(aifmm_system& s, const double* pts_in, bool on_device) {
       int64_t m = lv.T_off[b + 1] - lv.T_off[b];
       int64_t km = std::min<int64_t>(m, f);
       F_off[b + 1] = F_off[b] + f;
-      ws_off[b + 1] = ws_off[b] + km * m + km * f + f + km + 8;
+      ws_off[b + 1] = ws_off[b] + km * m + km * f + f + 2 * km + 8;
     }
     DBuf<int64_t> d_F_off, d_ws_off;
     d_F_off.upload(F_off, st);
     d_ws_off.upload(ws_off, st);
     DBuf<double> acaws;
     acaws.alloc(ws_off[nb]);
-    DBuf<unsigned char> cused;
+    DBuf<unsigned char> cused, rused;
     cused.alloc(std::max<int64_t>(1, F_off[nb]));
+    rused.alloc(std::max<int64_t>(1, lv.T_off[nb]));
     lv.d_piv_r.alloc(std::max(1, lv.T_off[nb]));
     lv.d_piv_c.alloc(std::max(1, lv.T_off[nb]));
     lv.d_k.alloc(nb);
     lv.d_kn.alloc(nb);
     AcaArgs aa{s.K, s.d_pts.p, d, s.tol, lv.d_T.p, lv.d_T_off.p, lv.d_il_off.p, lv.d_il.p, d_box_off.p,
-               d_F_off.p, d_ws_off.p, acaws.p, cused.p, lv.d_piv_r.p, lv.d_piv_c.p, lv.d_k.p, s.d_flag.p};
+               d_F_off.p, d_ws_off.p, acaws.p, cused.p, rused.p, lv.d_piv_r.p, lv.d_piv_c.p, lv.d_k.p, s.d_flag.p};
     hipLaunchKernelGGL(k_aca, dim3(nb), dim3(WG), 0, st, aa);
     launch_check("aca");
     lv.knn = lv.d_k.download(st);

@@ -15,6 +15,8 @@
 // factored densely (Algorithm "Back Substitution", first line).
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 
 #include "dense_wg.hpp"
 #include "system.hpp"
@@ -67,16 +69,18 @@ struct LevelPtrs {
 };
 
 // ------------------------------------------------------------------------------------------
-// compression of one pending pair per workgroup
+// compression of one pending pair per workgroup (CT threads)
 // ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_compress(LevelPtrs P, const RoundEntry* __restrict__ ent, int nent, double* ws,
+constexpr int CT = 1024;
+
+__global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* __restrict__ ent, int nent, double* ws,
                                                  int64_t wsz, int cap, double tol, int64_t tbase) {
   int e = blockIdx.x;
   if (e >= nent) return;
   RoundEntry R = ent[e];
   int* tr = P.trace + (tbase + e) * 6;
   double* trr = P.trace_ratio + (tbase + e) * 8;
-  __shared__ ValIdx shv[WG / WAVE + 1];
+  __shared__ ValIdx shv[CT / WAVE + 1];
   double* w = ws + (size_t)e * wsz;
   size_t c2 = (size_t)cap * cap;
   double* Lb_i = w;
@@ -88,7 +92,7 @@ __global__ void __launch_bounds__(WG) k_compress(LevelPtrs P, const RoundEntry* 
   double* V2 = w + 7 * c2;
   double* V3 = w + 8 * c2;
   double* V4 = w + 9 * c2;
-  double* nU = w + 10 * c2;
+  double* nU = w + 10 * c2;      // new bases, cap x cap, ld cap
   double* nV = w + 11 * c2;
   double* nUj = w + 12 * c2;
   double* nVj = w + 13 * c2;
@@ -99,8 +103,10 @@ __global__ void __launch_bounds__(WG) k_compress(LevelPtrs P, const RoundEntry* 
   const double* U_i = P.slab + P.U_off[R.i];
   const double* V_i = P.slab + P.V_off[R.i];
   int i = R.i, ni = P.n[i], ki = P.k[i];
+  int ki1 = ki > 0 ? ki : 1;
   if (R.kind == 0) {
     int j = R.partner, nj = P.n[j], kj = P.k[j];
+    int kj1 = kj > 0 ? kj : 1;
     const double* U_j = P.slab + P.U_off[j];
     const double* V_j = P.slab + P.V_off[j];
     double* Fij = P.slab + P.p2_slot[R.f_ij];  // (X_i, x_j): ni x nj, ld nj
@@ -109,67 +115,66 @@ __global__ void __launch_bounds__(WG) k_compress(LevelPtrs P, const RoundEntry* 
     double* Aji = P.slab + P.il_slot[R.e_ji];  // (Z_j, y_i): kj x ki, ld ni
     // RRQR1: [U_i | P2P_ij] = U~_i L_ij
     int ld = ki + nj;
-    wg_copy(ni, ki, U_i, ni, M, ld);
-    wg_copy(ni, nj, Fij, nj, M + ki, ld);
-    int r1 = wg_cpqr(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, trr);
+    wg_copy<CT>(ni, ki, U_i, ni, M, ld);
+    wg_copy<CT>(ni, nj, Fij, nj, M + ki, ld);
+    int r1 = wg_cpqr<CT>(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, trr);
     // RRQR2: [U_j | P2P_ji] = U~_j L_ji
     ld = kj + ni;
-    wg_copy(nj, kj, U_j, nj, M, ld);
-    wg_copy(nj, ni, Fji, ni, M + kj, ld);
-    int r2 = wg_cpqr(nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, trr + 2);
-    // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij
-    wg_formq(ni, r1, r1, V1, cap, tau, t1, r1 > 0 ? r1 : 1);
+    wg_copy<CT>(nj, kj, U_j, nj, M, ld);
+    wg_copy<CT>(nj, ni, Fji, ni, M + kj, ld);
+    int r2 = wg_cpqr<CT>(nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, trr + 2);
+    // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
+    wg_formq<CT>(ni, r1, r1, V1, cap, tau, nU, cap);
     ld = kj + r1;
-    wg_copy(nj, kj, V_j, nj, M, ld);
-    wg_gemm(nj, r1, ni, 1.0, Fij, nj, true, t1, r1 > 0 ? r1 : 1, false, 0.0, M + kj, ld);
-    int r3 = wg_cpqr(nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, trr + 4);
+    wg_copy<CT>(nj, kj, V_j, nj, M, ld);
+    wg_gemm<CT>(nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
+    int r3 = wg_cpqr<CT>(nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, trr + 4);
     // RRQR4: [V_i | L~_ji^*]
-    wg_formq(nj, r2, r2, V2, cap, tau + cap, t1, r2 > 0 ? r2 : 1);
+    wg_formq<CT>(nj, r2, r2, V2, cap, tau + cap, nUj, cap);
     ld = ki + r2;
-    wg_copy(ni, ki, V_i, ni, M, ld);
-    wg_gemm(ni, r2, nj, 1.0, Fji, ni, true, t1, r2 > 0 ? r2 : 1, false, 0.0, M + ki, ld);
-    int r4 = wg_cpqr(ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, trr + 6);
+    wg_copy<CT>(ni, ki, V_i, ni, M, ld);
+    wg_gemm<CT>(ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, M + ki, ld);
+    int r4 = wg_cpqr<CT>(ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, trr + 6);
     int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
-    int kin1 = kin > 0 ? kin : 1, kjn1 = kjn > 0 ? kjn : 1;
-    // new orthonormal bases (columns beyond a tolerance rank are further columns of the
-    // same Householder Q)
-    wg_formq(ni, r1, kin, V1, cap, tau, nU, kin1);
-    wg_formq(ni, r4, kin, V4, cap, tau + 3 * cap, nV, kin1);
-    wg_formq(nj, r2, kjn, V2, cap, tau + cap, nUj, kjn1);
-    wg_formq(nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, kjn1);
+    // new orthonormal bases: columns beyond a tolerance rank are further columns of the same
+    // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed)
+    wg_formq<CT>(ni, r1, kin, V1, cap, tau, nU, cap, r1);
+    wg_formq<CT>(ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap);
+    wg_formq<CT>(nj, r2, kjn, V2, cap, tau + cap, nUj, cap, r2);
+    wg_formq<CT>(nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap);
     // coefficients by projection: U_i = U~_i L_i, V_i = V~_i R_i, ...
-    int ki1 = ki > 0 ? ki : 1, kj1 = kj > 0 ? kj : 1;
-    wg_gemm(kin, ki, ni, 1.0, nU, kin1, true, U_i, ni, false, 0.0, Lb_i, ki1);
-    wg_gemm(kin, ki, ni, 1.0, nV, kin1, true, V_i, ni, false, 0.0, Rb_i, ki1);
-    wg_gemm(kjn, kj, nj, 1.0, nUj, kjn1, true, U_j, nj, false, 0.0, Lb_j, kj1);
-    wg_gemm(kjn, kj, nj, 1.0, nVj, kjn1, true, V_j, nj, false, 0.0, Rb_j, kj1);
+    wg_gemm<CT>(kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
+    wg_gemm<CT>(kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
+    wg_gemm<CT>(kjn, kj, nj, 1.0, nUj, cap, true, U_j, nj, false, 0.0, Lb_j, kj1);
+    wg_gemm<CT>(kjn, kj, nj, 1.0, nVj, cap, true, V_j, nj, false, 0.0, Rb_j, kj1);
     // A_ij := L_i A_ij R_j^* + R~_ij^*,  L~_ij = U~_i^* P2P_ij (kin x nj), R~_ij = V~_j^* L~_ij^*
-    wg_gemm(kin, nj, ni, 1.0, nU, kin1, true, Fij, nj, false, 0.0, t1, nj > 0 ? nj : 1);
-    wg_gemm(kjn, kin, nj, 1.0, nVj, kjn1, true, t1, nj > 0 ? nj : 1, true, 0.0, t2, kin1);  // R~_ij
-    wg_gemm(kin, kj, ki, 1.0, Lb_i, ki1, false, Aij, nj, false, 0.0, t1, kj1);             // L_i A_ij
-    for (int idx = threadIdx.x; idx < kin * kjn; idx += WG) {
+    int nj1 = nj > 0 ? nj : 1, ni1 = ni > 0 ? ni : 1;
+    wg_gemm<CT>(kin, nj, ni, 1.0, nU, cap, true, Fij, nj, false, 0.0, t1, nj1);
+    wg_gemm<CT>(kjn, kin, nj, 1.0, nVj, cap, true, t1, nj1, true, 0.0, t2, cap);   // R~_ij
+    wg_gemm<CT>(kin, kj, ki, 1.0, Lb_i, ki1, false, Aij, nj, false, 0.0, t1, kj1);  // L_i A_ij
+    for (int idx = threadIdx.x; idx < kin * kjn; idx += CT) {
       int r = idx / kjn, c = idx - r * kjn;
-      Aij[(size_t)r * nj + c] = t2[(size_t)c * kin1 + r];
+      Aij[(size_t)r * nj + c] = t2[(size_t)c * cap + r];
     }
     __syncthreads();
-    wg_gemm(kin, kjn, kj, 1.0, t1, kj1, false, Rb_j, kj1, true, 1.0, Aij, nj);
+    wg_gemm<CT>(kin, kjn, kj, 1.0, t1, kj1, false, Rb_j, kj1, true, 1.0, Aij, nj);
     // A_ji := L_j A_ji R_i^* + R~_ji^*
-    wg_gemm(kjn, ni, nj, 1.0, nUj, kjn1, true, Fji, ni, false, 0.0, t1, ni > 0 ? ni : 1);
-    wg_gemm(kin, kjn, ni, 1.0, nV, kin1, true, t1, ni > 0 ? ni : 1, true, 0.0, t2, kjn1);  // R~_ji
-    wg_gemm(kjn, ki, kj, 1.0, Lb_j, kj1, false, Aji, ni, false, 0.0, t1, ki1);
-    for (int idx = threadIdx.x; idx < kjn * kin; idx += WG) {
+    wg_gemm<CT>(kjn, ni, nj, 1.0, nUj, cap, true, Fji, ni, false, 0.0, t1, ni1);
+    wg_gemm<CT>(kin, kjn, ni, 1.0, nV, cap, true, t1, ni1, true, 0.0, t2, cap);    // R~_ji
+    wg_gemm<CT>(kjn, ki, kj, 1.0, Lb_j, kj1, false, Aji, ni, false, 0.0, t1, ki1);
+    for (int idx = threadIdx.x; idx < kjn * kin; idx += CT) {
       int r = idx / kin, c = idx - r * kin;
-      Aji[(size_t)r * ni + c] = t2[(size_t)c * kjn1 + r];
+      Aji[(size_t)r * ni + c] = t2[(size_t)c * cap + r];
     }
     __syncthreads();
-    wg_gemm(kjn, kin, ki, 1.0, t1, ki1, false, Rb_i, ki1, true, 1.0, Aji, ni);
+    wg_gemm<CT>(kjn, kin, ki, 1.0, t1, ki1, false, Rb_i, ki1, true, 1.0, Aji, ni);
     // bases, fill-ins, ranks
-    wg_copy(ni, kin, nU, kin1, (double*)U_i, ni);
-    wg_copy(ni, kin, nV, kin1, (double*)V_i, ni);
-    wg_copy(nj, kjn, nUj, kjn1, (double*)U_j, nj);
-    wg_copy(nj, kjn, nVj, kjn1, (double*)V_j, nj);
-    wg_zero(ni, nj, Fij, nj);
-    wg_zero(nj, ni, Fji, ni);
+    wg_copy<CT>(ni, kin, nU, cap, (double*)U_i, ni);
+    wg_copy<CT>(ni, kin, nV, cap, (double*)V_i, ni);
+    wg_copy<CT>(nj, kjn, nUj, cap, (double*)U_j, nj);
+    wg_copy<CT>(nj, kjn, nVj, cap, (double*)V_j, nj);
+    wg_zero<CT>(ni, nj, Fij, nj);
+    wg_zero<CT>(nj, ni, Fji, ni);
     if (threadIdx.x == 0) {
       P.kn[i] = kin;
       P.kn[j] = kjn;
@@ -177,41 +182,41 @@ __global__ void __launch_bounds__(WG) k_compress(LevelPtrs P, const RoundEntry* 
     }
   } else {
     int r = R.partner, nr = P.n[r], kr = P.k[r];
+    int kr1 = kr > 0 ? kr : 1;
     double* M2P = P.slab + P.p2_slot[R.f_ij];  // (X_i, y_r): ni x kr, ld nr
     double* P2L = P.slab + P.p2_slot[R.f_ji];  // (Z_r, x_i): kr x ni, ld ni
     double* Air = P.slab + P.il_slot[R.e_ij];  // (Z_i, y_r): ki x kr, ld nr
     double* Ari = P.slab + P.il_slot[R.e_ji];  // (Z_r, y_i): kr x ki, ld ni
     int ld = ki + kr;
     // RRQR: [V_i | P2L_ri^*] = V~_i R_ri
-    wg_copy(ni, ki, V_i, ni, M, ld);
-    for (int idx = threadIdx.x; idx < ni * kr; idx += WG) {
+    wg_copy<CT>(ni, ki, V_i, ni, M, ld);
+    for (int idx = threadIdx.x; idx < ni * kr; idx += CT) {
       int a = idx / kr, c = idx - a * kr;
       M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
     }
     __syncthreads();
-    int r5 = wg_cpqr(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, trr);
+    int r5 = wg_cpqr<CT>(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, trr);
     // RRQR: [U_i | M2P_ir] = U~_i L_ir
-    wg_copy(ni, ki, U_i, ni, M, ld);
-    wg_copy(ni, kr, M2P, nr, M + ki, ld);
-    int r6 = wg_cpqr(ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, trr + 2);
+    wg_copy<CT>(ni, ki, U_i, ni, M, ld);
+    wg_copy<CT>(ni, kr, M2P, nr, M + ki, ld);
+    int r6 = wg_cpqr<CT>(ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, trr + 2);
     int kin = r5 > r6 ? r5 : r6;
-    int kin1 = kin > 0 ? kin : 1, ki1 = ki > 0 ? ki : 1, kr1 = kr > 0 ? kr : 1;
-    wg_formq(ni, r5, kin, V1, cap, tau, nV, kin1);
-    wg_formq(ni, r6, kin, V2, cap, tau + cap, nU, kin1);
-    wg_gemm(kin, ki, ni, 1.0, nV, kin1, true, V_i, ni, false, 0.0, Rb_i, ki1);
-    wg_gemm(kin, ki, ni, 1.0, nU, kin1, true, U_i, ni, false, 0.0, Lb_i, ki1);
+    wg_formq<CT>(ni, r5, kin, V1, cap, tau, nV, cap);
+    wg_formq<CT>(ni, r6, kin, V2, cap, tau + cap, nU, cap);
+    wg_gemm<CT>(kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
+    wg_gemm<CT>(kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
     // A_ri := A_ri R_i^* + P2L_ri V~_i
-    wg_gemm(kr, kin, ki, 1.0, Ari, ni, false, Rb_i, ki1, true, 0.0, t1, kin1);
-    wg_gemm(kr, kin, ni, 1.0, P2L, ni, false, nV, kin1, false, 1.0, t1, kin1);
+    wg_gemm<CT>(kr, kin, ki, 1.0, Ari, ni, false, Rb_i, ki1, true, 0.0, t1, cap);
+    wg_gemm<CT>(kr, kin, ni, 1.0, P2L, ni, false, nV, cap, false, 1.0, t1, cap);
     // A_ir := L_i A_ir + U~_i^* M2P_ir
-    wg_gemm(kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
-    wg_gemm(kin, kr, ni, 1.0, nU, kin1, true, M2P, nr, false, 1.0, t2, kr1);
-    wg_copy(kr, kin, t1, kin1, Ari, ni);
-    wg_copy(kin, kr, t2, kr1, Air, nr);
-    wg_copy(ni, kin, nU, kin1, (double*)U_i, ni);
-    wg_copy(ni, kin, nV, kin1, (double*)V_i, ni);
-    wg_zero(nr, ni, P2L, ni);
-    wg_zero(ni, nr, M2P, nr);
+    wg_gemm<CT>(kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
+    wg_gemm<CT>(kin, kr, ni, 1.0, nU, cap, true, M2P, nr, false, 1.0, t2, kr1);
+    wg_copy<CT>(kr, kin, t1, cap, Ari, ni);
+    wg_copy<CT>(kin, kr, t2, kr1, Air, nr);
+    wg_copy<CT>(ni, kin, nU, cap, (double*)U_i, ni);
+    wg_copy<CT>(ni, kin, nV, cap, (double*)V_i, ni);
+    wg_zero<CT>(nr, ni, P2L, ni);
+    wg_zero<CT>(ni, nr, M2P, nr);
     if (threadIdx.x == 0) {
       P.kn[i] = kin;
       tr[0] = r5; tr[1] = r6; tr[2] = 0; tr[3] = 0; tr[4] = kin; tr[5] = 0;
@@ -630,10 +635,110 @@ __global__ void k_gather_top(int nb, const int* k, const int* n, const int* koff
   }
 }
 
-__global__ void __launch_bounds__(WG) k_top_lu(double* A, int K, int* ipiv, int* flag) {
-  __shared__ ValIdx shv[WG / WAVE + 1];
-  int st = wg_lu(K, A, K, ipiv, shv);
-  if (st && threadIdx.x == 0) { flag[0] = 1; flag[1] = -1; flag[2] = 1; }
+// Blocked LU with row partial pivoting of the dense level-2 system.  Every element receives
+// its updates fma(-l_ik, u_kj, a_ij) in ascending k, exactly as in the unblocked algorithm,
+// so the factors equal those of a column-by-column elimination.
+constexpr int PT = 1024, PNB = 64;
+__global__ void __launch_bounds__(PT) k_lu_panel(double* A, int K, int k0, int nb, int* ipiv, int* flag) {
+  __shared__ ValIdx shv[PT / WAVE + 1];
+  if (flag[0]) return;
+  for (int k = k0; k < k0 + nb; ++k) {
+    ValIdx best{-1.0, INT_MAX};
+    for (int i = k + (int)threadIdx.x; i < K; i += PT) {
+      ValIdx c{fabs(A[(size_t)i * K + k]), i};
+      if (vi_better(c, best)) best = c;
+    }
+    best = wg_argmax<PT>(best, shv);
+    if (best.v == 0.0) {
+      if (threadIdx.x == 0) { flag[0] = 1; flag[1] = -1; flag[2] = 1; }
+      return;
+    }
+    int p = best.i;
+    if (threadIdx.x == 0) ipiv[k] = p;
+    if (p != k)
+      for (int j = k0 + (int)threadIdx.x; j < k0 + nb; j += PT) {
+        double a = A[(size_t)k * K + j];
+        A[(size_t)k * K + j] = A[(size_t)p * K + j];
+        A[(size_t)p * K + j] = a;
+      }
+    __syncthreads();
+    double piv = A[(size_t)k * K + k];
+    for (int i = k + 1 + (int)threadIdx.x; i < K; i += PT) A[(size_t)i * K + k] /= piv;
+    __syncthreads();
+    int w = k0 + nb - k - 1;
+    if (w > 0)
+      for (int idx = threadIdx.x; idx < (K - k - 1) * w; idx += PT) {
+        int i = k + 1 + idx / w, j = k + 1 + idx % w;
+        A[(size_t)i * K + j] = fma(-A[(size_t)i * K + k], A[(size_t)k * K + j], A[(size_t)i * K + j]);
+      }
+    __syncthreads();
+  }
+}
+// row swaps of the panel applied to the columns outside it
+__global__ void k_lu_swaps(double* A, int K, int k0, int nb, const int* ipiv, const int* flag) {
+  if (flag[0]) return;
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= K || (j >= k0 && j < k0 + nb)) return;
+  for (int k = k0; k < k0 + nb; ++k) {
+    int p = ipiv[k];
+    if (p != k) {
+      double a = A[(size_t)k * K + j];
+      A[(size_t)k * K + j] = A[(size_t)p * K + j];
+      A[(size_t)p * K + j] = a;
+    }
+  }
+}
+// U12 = L11^{-1} A12 (unit lower), one column per thread
+__global__ void k_lu_u12(double* A, int K, int k0, int nb, const int* flag) {
+  if (flag[0]) return;
+  int j = k0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= K) return;
+  for (int k = k0; k < k0 + nb; ++k) {
+    double u = A[(size_t)k * K + j];
+    for (int i = k + 1; i < k0 + nb; ++i) A[(size_t)i * K + j] = fma(-A[(size_t)i * K + k], u, A[(size_t)i * K + j]);
+  }
+}
+// A22 -= L21 U12, each element accumulating the panel's updates in ascending k
+__global__ void __launch_bounds__(256) k_lu_a22(double* A, int K, int k0, int nb, const int* flag) {
+  if (flag[0]) return;
+  __shared__ double Ls[64][PNB + 1];
+  __shared__ double Us[PNB][64 + 1];
+  int r0 = k0 + nb + blockIdx.y * 64, c0 = k0 + nb + blockIdx.x * 64;
+  int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  for (int idx = threadIdx.x; idx < 64 * nb; idx += 256) {
+    int r = idx / nb, kk = idx % nb;
+    Ls[r][kk] = (r0 + r < K) ? A[(size_t)(r0 + r) * K + k0 + kk] : 0.0;
+  }
+  for (int idx = threadIdx.x; idx < nb * 64; idx += 256) {
+    int kk = idx / 64, c = idx % 64;
+    Us[kk][c] = (c0 + c < K) ? A[(size_t)(k0 + kk) * K + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int a = 0; a < 4; ++a) {
+    int r = r0 + ty * 4 + a;
+    if (r >= K) continue;
+    for (int b = 0; b < 4; ++b) {
+      int c = c0 + tx * 4 + b;
+      if (c >= K) continue;
+      double acc = A[(size_t)r * K + c];
+      for (int kk = 0; kk < nb; ++kk) acc = fma(-Ls[ty * 4 + a][kk], Us[kk][tx * 4 + b], acc);
+      A[(size_t)r * K + c] = acc;
+    }
+  }
+}
+
+static void top_lu(double* A, int K, int* ipiv, int* flag, hipStream_t st) {
+  for (int k0 = 0; k0 < K; k0 += PNB) {
+    int nb = std::min(PNB, K - k0);
+    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(PT), 0, st, A, K, k0, nb, ipiv, flag);
+    hipLaunchKernelGGL(k_lu_swaps, dim3((K + 255) / 256), dim3(256), 0, st, A, K, k0, nb, ipiv, flag);
+    int rest = K - k0 - nb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(k_lu_u12, dim3((rest + 255) / 256), dim3(256), 0, st, A, K, k0, nb, flag);
+      unsigned t = (unsigned)((rest + 63) / 64);
+      hipLaunchKernelGGL(k_lu_a22, dim3(t, t), dim3(256), 0, st, A, K, k0, nb, flag);
+    }
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -902,15 +1007,26 @@ static void count_flops(aifmm_system& s, int l) {
   }
 }
 
+static bool verbose() {
+  const char* v = getenv("AIFMM_VERBOSE");
+  return v && *v && *v != '0';
+}
+
 void factor_system(aifmm_system& s) {
   auto t0 = std::chrono::steady_clock::now();
+  auto since = [&](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+  };
   hipStream_t st = s.stream;
   int L = s.L;
   s.stats.schur_flops = s.stats.schur_bytes = s.stats.trsm_flops = s.stats.lu_flops = 0;
+  s.stats.schur_kernel_s = s.stats.compress_kernel_s = s.stats.schur_launches = s.stats.compress_launches = 0;
   s.trace.clear();
   s.d_flag.zero(st);
   for (int l = L; l >= 2; --l) {
+    auto tl = std::chrono::steady_clock::now();
     activate_level(s, l);
+    if (verbose()) fprintf(stderr, "[aifmm] level %d activated in %.3f s\n", l, since(tl));
     LevelDev& lv = s.lev[l];
     LevelPlan& Pl = s.plan[l];
     if (l < L) s.lev[l + 1].slab.release();
@@ -927,8 +1043,8 @@ void factor_system(aifmm_system& s) {
     DBuf<double> ws, scratch;
     ws.alloc((size_t)maxcol * wsz);
     scratch.alloc((size_t)XG * sstride);
-    DBuf<int> d_order;
-    d_order.upload(Pl.order, st);
+    lv.d_order.upload(Pl.order, st);
+    DBuf<int>& d_order = lv.d_order;
     // static round and transform lists of the whole level
     std::vector<RoundEntry> rent;
     std::vector<XformEntry> xent;
@@ -973,13 +1089,26 @@ void factor_system(aifmm_system& s) {
     P.trace = d_tr.p;
     P.trace_ratio = d_trr.p;
     size_t rix = 0;
+    hipEvent_t ev[4];
+    for (auto& e : ev) AIFMM_HIP(hipEventCreate(&e));
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> sch_ev, cmp_ev;
+    auto ev_pair = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+      hipEvent_t a, b;
+      AIFMM_HIP(hipEventCreate(&a));
+      AIFMM_HIP(hipEventCreate(&b));
+      v.push_back({a, b});
+      return v.back();
+    };
     for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) {
       for (int r = 0; r < nrounds[c]; ++r, ++rix) {
         int ne = (int)(r_off[rix + 1] - r_off[rix]);
         int nx = (int)(x_off[rix + 1] - x_off[rix]);
         const RoundEntry* er = d_rent.p + r_off[rix];
         const XformEntry* ex = d_xent.p + x_off[rix];
-        hipLaunchKernelGGL(k_compress, dim3(ne), dim3(WG), 0, st, P, er, ne, ws.p, wsz, cap, s.tol, r_off[rix]);
+        auto ce = ev_pair(cmp_ev);
+        AIFMM_HIP(hipEventRecord(ce.first, st));
+        hipLaunchKernelGGL(k_compress, dim3(ne), dim3(CT), 0, st, P, er, ne, ws.p, wsz, cap, s.tol, r_off[rix]);
+        AIFMM_HIP(hipEventRecord(ce.second, st));
         int grid = std::min<int64_t>(XG, (int64_t)nx * maxblk);
         hipLaunchKernelGGL(k_row_xform, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p, sstride);
         hipLaunchKernelGGL(k_col_xform, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p, sstride);
@@ -991,11 +1120,33 @@ void factor_system(aifmm_system& s) {
       hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
       hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, WG), nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
       int tiles_c = cdiv(lv.Cmax, ST), tiles_r = cdiv(std::max(1, lv.Rmax), ST);
+      auto se = ev_pair(sch_ev);
+      AIFMM_HIP(hipEventRecord(se.first, st));
       hipLaunchKernelGGL(k_elim_schur, dim3(tiles_r * tiles_c, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
+      AIFMM_HIP(hipEventRecord(se.second, st));
       hipLaunchKernelGGL(k_elim_zrow, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
       launch_check("elimination");
     }
     lv.kfin = lv.d_k.download(st);
+    AIFMM_HIP(hipStreamSynchronize(st));
+    for (auto& pr : sch_ev) {
+      float ms = 0;
+      AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      s.stats.schur_kernel_s += ms * 1e-3;
+      s.stats.schur_launches += 1;
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    for (auto& pr : cmp_ev) {
+      float ms = 0;
+      AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      s.stats.compress_kernel_s += ms * 1e-3;
+      s.stats.compress_launches += 1;
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (verbose()) fprintf(stderr, "[aifmm] level %d factored in %.3f s (%zu compressions)\n", l, since(tl), rent.size());
     {
       std::vector<int> tr = d_tr.download(st, rent.size() * 6);
       std::vector<double> trr = d_trr.download(st, rent.size() * 8);
@@ -1037,10 +1188,11 @@ void factor_system(aifmm_system& s) {
       hipLaunchKernelGGL(k_gather_top, dim3(l2.nb, l2.nb), dim3(WG), 0, st, l2.nb, l2.d_k.p, l2.d_n.p, d_koff.p,
                          l2.d_nbr_off.p, l2.d_nbr.p, l2.d_near_slot.p, l2.d_il_off.p, l2.d_il.p, l2.d_il_slot.p,
                          l2.slab.p, s.d_top.p, s.Ktop);
-      hipLaunchKernelGGL(k_top_lu, dim3(1), dim3(WG), 0, st, s.d_top.p, s.Ktop, s.d_top_piv.p, s.d_flag.p);
+      top_lu(s.d_top.p, s.Ktop, s.d_top_piv.p, s.d_flag.p, st);
       launch_check("top");
     }
     std::vector<int> flag = s.d_flag.download(st);
+    if (verbose()) fprintf(stderr, "[aifmm] top system K=%d factored at %.3f s\n", s.Ktop, since(t0));
     if (flag[0]) throw Error{AIFMM_ERR_SINGULAR, "singular level-2 multipole system"};
     l2.slab.release();
   }

@@ -1,0 +1,281 @@
+// Exact FP64 matrix-vector product with the kernel matrix and right-preconditioned flexible
+// GMRES with the AIFMM factorization as preconditioner (the paper uses AIFMM as a GMRES
+// preconditioner in Sec. 4, Experiment 5, with the relative residual ||A x - b|| / ||b|| as
+// stopping rule, Table of notations).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "dense_wg.hpp"
+#include "system.hpp"
+
+namespace aifmm {
+
+// y[i, c] = sum_j A_ij x[j, c] for the points in tree order; x, y row-major (N x nr).
+// One target per thread; sources staged through LDS in tiles; every entry evaluated.
+constexpr int MV_T = 256, MV_S = 256, MV_R = 16;
+__global__ void __launch_bounds__(MV_T) k_matvec(KernelDesc K, const double* __restrict__ pts, int d, int64_t N,
+                                                 const double* __restrict__ x, int nr, double* __restrict__ y) {
+  __shared__ double sp[MV_S * 3];
+  __shared__ double sx[MV_S * MV_R];
+  int64_t i = (int64_t)blockIdx.x * MV_T + threadIdx.x;
+  int c0 = blockIdx.y * MV_R;
+  int nc = std::min(MV_R, nr - c0);
+  double acc[MV_R];
+  for (int c = 0; c < MV_R; ++c) acc[c] = 0.0;
+  double pi[3] = {0.0, 0.0, 0.0};
+  if (i < N)
+    for (int t = 0; t < d; ++t) pi[t] = pts[i * d + t];
+  double s2 = K.scale * K.scale;
+  for (int64_t j0 = 0; j0 < N; j0 += MV_S) {
+    int cnt = (int)std::min<int64_t>(MV_S, N - j0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < cnt * d; q += MV_T) sp[q] = pts[j0 * d + q];
+    for (int q = threadIdx.x; q < cnt * MV_R; q += MV_T) {
+      int jj = q / MV_R, c = q % MV_R;
+      sx[q] = c < nc ? x[(j0 + jj) * nr + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (i < N) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        double r2 = 0.0;
+        for (int t = 0; t < d; ++t) {
+          double z = pi[t] - sp[jj * d + t];
+          r2 = fma(z, z, r2);
+        }
+        double v = K.kind == 0 ? dexp(-sqrt(r2) / K.scale) : 1.0 / sqrt(r2 + s2);
+        if (j0 + jj == i) v += K.shift;
+#pragma unroll
+        for (int c = 0; c < MV_R; ++c) acc[c] = fma(v, sx[jj * MV_R + c], acc[c]);
+      }
+    }
+  }
+  if (i < N)
+    for (int c = 0; c < nc; ++c) y[i * nr + c0 + c] = acc[c];
+}
+
+// column dot products: out[c] = sum_i a[i, c] b[i, c]  (row-major N x nr), partial sums per block
+__global__ void k_coldot(const double* a, const double* b, int64_t N, int nr, double* part) {
+  __shared__ double sh[WG / WAVE + 1];
+  for (int c = 0; c < nr; ++c) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < N; i += (int64_t)gridDim.x * WG) s = fma(a[i * nr + c], b[i * nr + c], s);
+    s = wg_sum<WG>(s, sh);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * nr + c] = s;
+  }
+}
+// y[:, c] += alpha[c] x[:, c]
+__global__ void k_axpy_cols(int64_t N, int nr, const double* alpha, const double* x, double* y) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * nr) return;
+  int c = (int)(q % nr);
+  y[q] = fma(alpha[c], x[q], y[q]);
+}
+// y[:, c] = x[:, c] * alpha[c]
+__global__ void k_scale_cols(int64_t N, int nr, const double* alpha, const double* x, double* y) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * nr) return;
+  y[q] = x[q] * alpha[q % nr];
+}
+__global__ void k_perm_rows_in(const double* b, int64_t ldb, const int64_t* perm, int64_t N, int nr, double* out) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * nr) return;
+  int64_t i = q / nr;
+  int c = (int)(q - i * nr);
+  out[q] = b[c * ldb + perm[i]];
+}
+__global__ void k_perm_rows_out(const double* xs, const int64_t* perm, int64_t N, int nr, double* x, int64_t ldx) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * nr) return;
+  int64_t i = q / nr;
+  int c = (int)(q - i * nr);
+  x[c * ldx + perm[i]] = xs[q];
+}
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// y = A x for tree-ordered row-major vectors
+void matvec_tree(aifmm_system& s, const double* x, int nr, double* y) {
+  dim3 grid(cdiv(s.N, MV_T), cdiv(nr, MV_R));
+  hipLaunchKernelGGL(k_matvec, grid, dim3(MV_T), 0, s.stream, s.K, s.d_pts.p, s.d, s.N, x, nr, y);
+  AIFMM_HIP(hipGetLastError());
+}
+
+static std::vector<double> coldots(aifmm_system& s, const double* a, const double* b, int nr, DBuf<double>& part) {
+  int nblk = 256;
+  if (part.n < (size_t)nblk * nr) part.alloc((size_t)nblk * nr);
+  hipLaunchKernelGGL(k_coldot, dim3(nblk), dim3(WG), 0, s.stream, a, b, s.N, nr, part.p);
+  std::vector<double> h = part.download(s.stream, (size_t)nblk * nr);
+  std::vector<double> out(nr, 0.0);
+  for (int q = 0; q < nblk; ++q)
+    for (int c = 0; c < nr; ++c) out[c] += h[(size_t)q * nr + c];
+  return out;
+}
+
+void matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy, bool x_dev,
+                   bool y_dev) {
+  hipStream_t st = s.stream;
+  int nr = (int)nrhs;
+  int64_t N = s.N;
+  DBuf<double> xin, xt, yt, yout;
+  const double* xs = x;
+  if (!x_dev) {
+    xin.alloc((size_t)ldx * nr);
+    AIFMM_HIP(hipMemcpyAsync(xin.p, x, sizeof(double) * ldx * nr, hipMemcpyHostToDevice, st));
+    xs = xin.p;
+  }
+  xt.alloc((size_t)N * nr);
+  yt.alloc((size_t)N * nr);
+  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xs, ldx, s.d_perm.p, N, nr, xt.p);
+  matvec_tree(s, xt.p, nr, yt.p);
+  if (y_dev) {
+    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, yt.p, s.d_perm.p, N, nr, y, ldy);
+  } else {
+    yout.alloc((size_t)ldy * nr);
+    yout.zero(st);
+    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, yt.p, s.d_perm.p, N, nr, yout.p, ldy);
+    AIFMM_HIP(hipMemcpyAsync(y, yout.p, sizeof(double) * ldy * nr, hipMemcpyDeviceToHost, st));
+  }
+  AIFMM_HIP(hipStreamSynchronize(st));
+}
+
+// Right-preconditioned flexible GMRES(m) with modified Gram-Schmidt, all right-hand sides
+// advanced together (each with its own Hessenberg matrix); the preconditioner is the AIFMM
+// solve in tree order.  Stops per column on the true relative residual <= rtol.
+void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int restart, int maxit,
+                  double* x, int64_t ldx, int32_t* iters, double* relres, bool b_dev, bool x_dev) {
+  hipStream_t st = s.stream;
+  int nr = (int)nrhs, m = std::max(1, restart);
+  int64_t N = s.N;
+  size_t vec = (size_t)N * nr;
+  DBuf<double> bin, bt, xt, r, w, part, dalpha;
+  const double* bs = b;
+  if (!b_dev) {
+    bin.alloc((size_t)ldb * nr);
+    AIFMM_HIP(hipMemcpyAsync(bin.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
+    bs = bin.p;
+  }
+  bt.alloc(vec);
+  xt.alloc(vec);
+  r.alloc(vec);
+  w.alloc(vec);
+  dalpha.alloc(nr);
+  xt.zero(st);
+  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(vec, WG)), dim3(WG), 0, st, bs, ldb, s.d_perm.p, N, nr, bt.p);
+  std::vector<DBuf<double>> V(m + 1), Z(m);
+  for (auto& v : V) v.alloc(vec);
+  for (auto& z : Z) z.alloc(vec);
+  std::vector<double> bnorm = coldots(s, bt.p, bt.p, nr, part);
+  for (auto& v : bnorm) v = std::sqrt(v);
+  std::vector<int> done(nr, 0), its(nr, 0);
+  std::vector<double> rel(nr, 1.0);
+  auto set_alpha = [&](const std::vector<double>& a) {
+    AIFMM_HIP(hipMemcpyAsync(dalpha.p, a.data(), sizeof(double) * nr, hipMemcpyHostToDevice, st));
+  };
+  auto axpy = [&](const std::vector<double>& a, const double* xx, double* yy) {
+    set_alpha(a);
+    hipLaunchKernelGGL(k_axpy_cols, dim3(cdiv(vec, WG)), dim3(WG), 0, st, N, nr, dalpha.p, xx, yy);
+  };
+  auto scale = [&](const std::vector<double>& a, const double* xx, double* yy) {
+    set_alpha(a);
+    hipLaunchKernelGGL(k_scale_cols, dim3(cdiv(vec, WG)), dim3(WG), 0, st, N, nr, dalpha.p, xx, yy);
+  };
+  int total = 0;
+  while (true) {
+    // true residual r = b - A x
+    matvec_tree(s, xt.p, nr, w.p);
+    AIFMM_HIP(hipMemcpyAsync(r.p, bt.p, sizeof(double) * vec, hipMemcpyDeviceToDevice, st));
+    axpy(std::vector<double>(nr, -1.0), w.p, r.p);
+    std::vector<double> beta = coldots(s, r.p, r.p, nr, part);
+    bool all = true;
+    for (int c = 0; c < nr; ++c) {
+      beta[c] = std::sqrt(beta[c]);
+      rel[c] = bnorm[c] > 0 ? beta[c] / bnorm[c] : 0.0;
+      done[c] = rel[c] <= rtol;
+      all = all && done[c];
+    }
+    if (all || total >= maxit) break;
+    std::vector<double> inv(nr);
+    for (int c = 0; c < nr; ++c) inv[c] = (done[c] || beta[c] == 0.0) ? 0.0 : 1.0 / beta[c];
+    scale(inv, r.p, V[0].p);
+    std::vector<std::vector<double>> H((size_t)(m + 1) * m, std::vector<double>(nr, 0.0));
+    std::vector<std::vector<double>> cs(m, std::vector<double>(nr)), sn(m, std::vector<double>(nr));
+    std::vector<std::vector<double>> g(m + 1, std::vector<double>(nr, 0.0));
+    for (int c = 0; c < nr; ++c) g[0][c] = done[c] ? 0.0 : beta[c];
+    int j = 0;
+    for (; j < m && total < maxit; ++j, ++total) {
+      solve_tree(s, V[j].p, nr, Z[j].p);  // Z_j = M^{-1} V_j
+      matvec_tree(s, Z[j].p, nr, w.p);
+      for (int i = 0; i <= j; ++i) {
+        std::vector<double> h = coldots(s, V[i].p, w.p, nr, part);
+        for (int c = 0; c < nr; ++c) H[(size_t)i * m + j][c] = h[c];
+        std::vector<double> neg(nr);
+        for (int c = 0; c < nr; ++c) neg[c] = -h[c];
+        axpy(neg, V[i].p, w.p);
+      }
+      std::vector<double> hn = coldots(s, w.p, w.p, nr, part);
+      std::vector<double> inv2(nr);
+      for (int c = 0; c < nr; ++c) {
+        hn[c] = std::sqrt(hn[c]);
+        H[(size_t)(j + 1) * m + j][c] = hn[c];
+        inv2[c] = hn[c] > 0 ? 1.0 / hn[c] : 0.0;
+      }
+      scale(inv2, w.p, V[j + 1].p);
+      bool conv = true;
+      for (int c = 0; c < nr; ++c) {
+        for (int i = 0; i < j; ++i) {
+          double a = H[(size_t)i * m + j][c], bb = H[(size_t)(i + 1) * m + j][c];
+          H[(size_t)i * m + j][c] = cs[i][c] * a + sn[i][c] * bb;
+          H[(size_t)(i + 1) * m + j][c] = -sn[i][c] * a + cs[i][c] * bb;
+        }
+        double a = H[(size_t)j * m + j][c], bb = H[(size_t)(j + 1) * m + j][c];
+        double rr = std::hypot(a, bb);
+        cs[j][c] = rr > 0 ? a / rr : 1.0;
+        sn[j][c] = rr > 0 ? bb / rr : 0.0;
+        H[(size_t)j * m + j][c] = rr;
+        H[(size_t)(j + 1) * m + j][c] = 0.0;
+        g[j + 1][c] = -sn[j][c] * g[j][c];
+        g[j][c] = cs[j][c] * g[j][c];
+        if (!done[c]) {
+          ++its[c];
+          if (std::fabs(g[j + 1][c]) > rtol * 0.5 * bnorm[c]) conv = false;
+        }
+      }
+      if (conv) { ++j; ++total; break; }
+    }
+    // x += Z y with H y = g (upper triangular, per column)
+    for (int c = 0; c < nr; ++c) {
+      std::vector<double> y(j, 0.0);
+      for (int i = j - 1; i >= 0; --i) {
+        double v = g[i][c];
+        for (int t = i + 1; t < j; ++t) v -= H[(size_t)i * m + t][c] * y[t];
+        y[i] = H[(size_t)i * m + i][c] != 0.0 ? v / H[(size_t)i * m + i][c] : 0.0;
+      }
+      for (int i = 0; i < j; ++i) H[(size_t)i * m][c] = y[i];  // reuse column 0 as storage
+    }
+    for (int i = 0; i < j; ++i) {
+      std::vector<double> a(nr);
+      for (int c = 0; c < nr; ++c) a[c] = done[c] ? 0.0 : H[(size_t)i * m][c];
+      axpy(a, Z[i].p, xt.p);
+    }
+  }
+  for (int c = 0; c < nr; ++c) {
+    if (iters) iters[c] = its[c];
+    if (relres) relres[c] = rel[c];
+  }
+  if (x_dev) {
+    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(vec, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, x, ldx);
+  } else {
+    DBuf<double> xo;
+    xo.alloc((size_t)ldx * nr);
+    xo.zero(st);
+    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(vec, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, xo.p, ldx);
+    AIFMM_HIP(hipMemcpyAsync(x, xo.p, sizeof(double) * ldx * nr, hipMemcpyDeviceToHost, st));
+  }
+  AIFMM_HIP(hipStreamSynchronize(st));
+  bool ok = true;
+  for (int c = 0; c < nr; ++c) ok = ok && rel[c] <= rtol;
+  if (!ok) throw Error{AIFMM_ERR_NOCONV, "GMRES did not reach the requested residual within maxit"};
+}
+
+}  // namespace aifmm

@@ -151,30 +151,21 @@ static void launch_check(const char* what) {
   if (e != hipSuccess) throw Error{AIFMM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx, bool b_dev,
-                  bool x_dev) {
-  auto t0 = std::chrono::steady_clock::now();
+// Solve with tree-ordered row-major right-hand sides (N x nr) on the device; x may alias nothing.
+void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x) {
   hipStream_t st = s.stream;
-  int L = s.L, nr = (int)nrhs;
+  int L = s.L;
   int64_t N = s.N;
   // buffers: rhs per level (X rows of level l; Z rows of level l == X rows of level l-1)
   std::vector<DBuf<double>> R(L + 2), X(L + 2);  // R[l]: rhs of X rows at level l; X[l]: solution x at level l
   R[L].alloc((size_t)N * nr);
-  X[L].alloc((size_t)N * nr);
+  AIFMM_HIP(hipMemcpyAsync(R[L].p, rhs, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, st));
   for (int l = L; l >= 2; --l) {
     int64_t K = s.lev[l].koff[s.lev[l].nb];
     R[l - 1].alloc((size_t)std::max<int64_t>(1, K) * nr);
     R[l - 1].zero(st);
     X[l - 1].alloc((size_t)std::max<int64_t>(1, K) * nr);
   }
-  DBuf<double> bdev;
-  const double* bsrc = b;
-  if (!b_dev) {
-    bdev.alloc((size_t)ldb * nr);
-    AIFMM_HIP(hipMemcpyAsync(bdev.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
-    bsrc = bdev.p;
-  }
-  hipLaunchKernelGGL(k_perm_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, bsrc, ldb, s.d_perm.p, N, nr, R[L].p);
   // per level device offsets and w storage
   std::vector<DBuf<int64_t>> dx(L + 1), dk(L + 1), dwo(L + 1);
   std::vector<DBuf<double>> wsv(L + 1);
@@ -204,20 +195,18 @@ void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
     S.koff = dk[l].p;
     S.Xr = R[l].p;
     S.Zr = R[l - 1].p;
-    S.xs = X[l].p;
+    S.xs = l == L ? x : X[l].p;
     S.ys = X[l - 1].p;
     S.wsave = wsv[l].p;
     S.woff = dwo[l].p;
     return S;
   };
-  std::vector<DBuf<int>> dorder(L + 1);
-  for (int l = 2; l <= L; ++l) dorder[l].upload(s.plan[l].order, st);
   for (int l = L; l >= 2; --l) {
     SolvePtrs S = sp(l);
     LevelPlan& P = s.plan[l];
     for (size_t c = 0; c + 1 < P.col_off.size(); ++c) {
       int nbox = P.col_off[c + 1] - P.col_off[c];
-      hipLaunchKernelGGL(k_fwd, dim3(nbox), dim3(WG), 0, st, S, dorder[l].p + P.col_off[c]);
+      hipLaunchKernelGGL(k_fwd, dim3(nbox), dim3(WG), 0, st, S, s.lev[l].d_order.p + P.col_off[c]);
     }
   }
   launch_check("forward sweep");
@@ -232,17 +221,37 @@ void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
     for (size_t c = P.col_off.size() - 1; c-- > 0;) {
       int nbox = P.col_off[c + 1] - P.col_off[c];
       // boxes of one colour are independent; reverse order inside the colour is not needed
-      hipLaunchKernelGGL(k_bwd, dim3(nbox), dim3(WG), 0, st, S, dorder[l].p + P.col_off[c]);
+      hipLaunchKernelGGL(k_bwd, dim3(nbox), dim3(WG), 0, st, S, s.lev[l].d_order.p + P.col_off[c]);
     }
   }
   launch_check("backward sweep");
+  AIFMM_HIP(hipStreamSynchronize(st));
+}
+
+void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx, bool b_dev,
+                  bool x_dev) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = s.stream;
+  int nr = (int)nrhs;
+  int64_t N = s.N;
+  DBuf<double> bdev, rt, xt;
+  const double* bsrc = b;
+  if (!b_dev) {
+    bdev.alloc((size_t)ldb * nr);
+    AIFMM_HIP(hipMemcpyAsync(bdev.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
+    bsrc = bdev.p;
+  }
+  rt.alloc((size_t)N * nr);
+  xt.alloc((size_t)N * nr);
+  hipLaunchKernelGGL(k_perm_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, bsrc, ldb, s.d_perm.p, N, nr, rt.p);
+  solve_tree(s, rt.p, nr, xt.p);
   if (x_dev) {
-    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, X[L].p, s.d_perm.p, N, nr, x, ldx);
+    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, x, ldx);
   } else {
     DBuf<double> xd;
     xd.alloc((size_t)ldx * nr);
     xd.zero(st);
-    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, X[L].p, s.d_perm.p, N, nr, xd.p, ldx);
+    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, xd.p, ldx);
     AIFMM_HIP(hipMemcpyAsync(x, xd.p, sizeof(double) * ldx * nr, hipMemcpyDeviceToHost, st));
   }
   AIFMM_HIP(hipStreamSynchronize(st));

@@ -151,6 +151,7 @@ struct LevelDev {
   // factor store (kept for the solve)
   DBuf<double> fslab;
   DBuf<int64_t> d_fLU, d_fPx, d_fC, d_fW;  // per box offsets into fslab
+  DBuf<int> d_order;           // elimination order on the device
   DBuf<int> d_fpiv;            // ipiv, capacity 2 n_b per box
   DBuf<int64_t> d_fpiv_off;
   std::vector<int64_t> fLU, fPx, fC, fW;   // host copies of the offsets
@@ -168,6 +169,9 @@ struct TraceRec {
 struct Stats {
   double build_s = 0, factor_s = 0, solve_s = 0;
   double schur_flops = 0, schur_bytes = 0, trsm_flops = 0, lu_flops = 0;
+  double schur_kernel_s = 0, compress_kernel_s = 0;   // event-timed device time of the last factor
+  double schur_launches = 0, compress_launches = 0;
+  double gmres_s = 0, gmres_iters = 0;
 };
 
 }  // namespace aifmm
@@ -207,4 +211,11 @@ void factor_system(aifmm_system& s);
 // solve.hip
 void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx,
                   bool b_dev, bool x_dev);
+void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x);
+// k_gmres.hip
+void matvec_tree(aifmm_system& s, const double* x, int nr, double* y);
+void matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy, bool x_dev,
+                   bool y_dev);
+void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int restart, int maxit,
+                  double* x, int64_t ldx, int32_t* iters, double* relres, bool b_dev, bool x_dev);
 }  // namespace aifmm
