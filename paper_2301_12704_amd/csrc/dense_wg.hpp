@@ -54,6 +54,25 @@ __device__ inline double kernel_entry(const KernelDesc& K, const double* __restr
   return v;
 }
 
+// acc + sum_{i<n} a(i) b(i), accumulated in ascending i with fused multiply-adds; the loads of
+// every batch of eight terms are issued before its multiply-adds.
+template <class FA, class FB>
+__device__ inline double seq_dot(int n, FA a, FB b, double acc) {
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x[u] = a(i + u);
+      y[u] = b(i + u);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(x[u], y[u], acc);
+  }
+  for (; i < n; ++i) acc = fma(a(i), b(i), acc);
+  return acc;
+}
+
 struct ValIdx {
   double v;
   int i;
@@ -114,13 +133,10 @@ __device__ inline void wg_gemm(int M, int N, int K, double alpha, const double* 
                                const double* __restrict__ B, int ldb, bool tb, double beta, double* C, int ldc) {
   for (int idx = threadIdx.x; idx < M * N; idx += NT) {
     int r = idx / N, c = idx - r * N;
-    double acc = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-      double a = ta ? A[(size_t)k * lda + r] : A[(size_t)r * lda + k];
-      double b = tb ? B[(size_t)c * ldb + k] : B[(size_t)k * ldb + c];
-      acc = fma(a, b, acc);
-    }
+    const double* pa = ta ? A + r : A + (size_t)r * lda;
+    const double* pb = tb ? B + (size_t)c * ldb : B + c;
+    size_t sa = ta ? (size_t)lda : 1, sb = tb ? 1 : (size_t)ldb;
+    double acc = seq_dot(K, [&](int k) { return pa[k * sa]; }, [&](int k) { return pb[k * sb]; }, 0.0);
     double v = alpha * acc;
     if (beta != 0.0) v += beta * C[(size_t)r * ldc + c];
     C[(size_t)r * ldc + c] = v;
@@ -156,17 +172,13 @@ __device__ inline void wg_zero(int M, int N, double* C, int ldc) {
 // given) receives |R_kk|/(tol |R_11|) of the last kept and of the first rejected pivot.
 template <int NT = WG>
 __device__ inline int wg_cpqr(int m, int n, double* M, int ldm, double tol, double* V, int ldv, double* tau,
-                              double* nrm, ValIdx* shv, double* ratio = nullptr) {
+                              double* nrm, ValIdx* shv, double* vsh, double* ratio = nullptr) {
   double kept = 0.0, next = 0.0;
   int smax = m < n ? m : n;
   double r11 = 0.0;
   for (int j = threadIdx.x; j < n; j += NT) {
-    double t = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < m; ++i) {
-      double a = M[(size_t)i * ldm + j];
-      t = fma(a, a, t);
-    }
+    const double* col = M + j;
+    double t = seq_dot(m, [&](int i) { return col[(size_t)i * ldm]; }, [&](int i) { return col[(size_t)i * ldm]; }, 0.0);
     nrm[j] = sqrt(t);
   }
   __syncthreads();
@@ -216,23 +228,33 @@ __device__ inline int wg_cpqr(int m, int n, double* M, int ldm, double tol, doub
       if (i == s) v = 1.0;
       else if (i > s) v = M[(size_t)i * ldm + s] / scale;
       V[(size_t)i * ldv + s] = v;
+      vsh[i] = v;
     }
     if (threadIdx.x == 0) tau[s] = tv;
     __syncthreads();
+    int len = m - s;
     for (int j = s + 1 + (int)threadIdx.x; j < n; j += NT) {
-      double w = 0.0;
-#pragma unroll 8
-      for (int i = s; i < m; ++i) w = fma(V[(size_t)i * ldv + s], M[(size_t)i * ldm + j], w);
+      double* col = M + (size_t)s * ldm + j;
+      const double* vv = vsh + s;
+      double w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldm]; }, 0.0);
       w *= tv;
+      col[0] = fma(-w, vv[0], col[0]);
       double t = 0.0;
-      {
-        double a = fma(-w, V[(size_t)s * ldv + s], M[(size_t)s * ldm + j]);
-        M[(size_t)s * ldm + j] = a;
+      int i = 1;
+      for (; i + 8 <= len; i += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldm];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = fma(-w, vv[i + u], a[u]);
+          col[(size_t)(i + u) * ldm] = a[u];
+          t = fma(a[u], a[u], t);
+        }
       }
-#pragma unroll 8
-      for (int i = s + 1; i < m; ++i) {
-        double a = fma(-w, V[(size_t)i * ldv + s], M[(size_t)i * ldm + j]);
-        M[(size_t)i * ldm + j] = a;
+      for (; i < len; ++i) {
+        double a = fma(-w, vv[i], col[(size_t)i * ldm]);
+        col[(size_t)i * ldm] = a;
         t = fma(a, a, t);
       }
       nrm[j] = sqrt(t);
@@ -250,7 +272,7 @@ __device__ inline int wg_cpqr(int m, int n, double* M, int ldm, double tol, doub
 // below c0 are left untouched (already formed).
 template <int NT = WG>
 __device__ inline void wg_formq(int m, int rank, int q, const double* V, int ldv, const double* tau, double* Q, int ldq,
-                                int c0 = 0) {
+                                double* vsh, int c0 = 0) {
   for (int idx = threadIdx.x; idx < m * (q - c0); idx += NT) {
     int r = idx / (q - c0), c = c0 + idx % (q - c0);
     Q[(size_t)r * ldq + c] = (r == c) ? 1.0 : 0.0;
@@ -258,13 +280,24 @@ __device__ inline void wg_formq(int m, int rank, int q, const double* V, int ldv
   __syncthreads();
   for (int s = rank - 1; s >= 0; --s) {
     double tv = tau[s];
-    for (int j = c0 + threadIdx.x; j < q; j += NT) {
-      double w = 0.0;
-#pragma unroll 8
-      for (int i = s; i < m; ++i) w = fma(V[(size_t)i * ldv + s], Q[(size_t)i * ldq + j], w);
+    for (int i = s + threadIdx.x; i < m; i += NT) vsh[i] = V[(size_t)i * ldv + s];
+    __syncthreads();
+    int len = m - s;
+    const double* vv = vsh + s;
+    // column j is still e_j while s > j, so the reflector leaves it unchanged (w = 0)
+    for (int j = (c0 > s ? c0 : s) + threadIdx.x; j < q; j += NT) {
+      double* col = Q + (size_t)s * ldq + j;
+      double w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldq]; }, 0.0);
       w *= tv;
-#pragma unroll 8
-      for (int i = s; i < m; ++i) Q[(size_t)i * ldq + j] = fma(-w, V[(size_t)i * ldv + s], Q[(size_t)i * ldq + j]);
+      int i = 0;
+      for (; i + 8 <= len; i += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldq];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) col[(size_t)(i + u) * ldq] = fma(-w, vv[i + u], a[u]);
+      }
+      for (; i < len; ++i) col[(size_t)i * ldq] = fma(-w, vv[i], col[(size_t)i * ldq]);
     }
     __syncthreads();
   }

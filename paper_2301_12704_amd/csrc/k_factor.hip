@@ -71,7 +71,7 @@ struct LevelPtrs {
 // ------------------------------------------------------------------------------------------
 // compression of one pending pair per workgroup (CT threads)
 // ------------------------------------------------------------------------------------------
-constexpr int CT = 1024;
+constexpr int CT = 512;
 
 __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* __restrict__ ent, int nent, double* ws,
                                                  int64_t wsz, int cap, double tol, int64_t tbase) {
@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   int* tr = P.trace + (tbase + e) * 6;
   double* trr = P.trace_ratio + (tbase + e) * 8;
   __shared__ ValIdx shv[CT / WAVE + 1];
+  extern __shared__ double vsh[];  // one reflector (cap doubles)
   double* w = ws + (size_t)e * wsz;
   size_t c2 = (size_t)cap * cap;
   double* Lb_i = w;
@@ -117,31 +118,31 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     int ld = ki + nj;
     wg_copy<CT>(ni, ki, U_i, ni, M, ld);
     wg_copy<CT>(ni, nj, Fij, nj, M + ki, ld);
-    int r1 = wg_cpqr<CT>(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, trr);
+    int r1 = wg_cpqr<CT>(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, trr);
     // RRQR2: [U_j | P2P_ji] = U~_j L_ji
     ld = kj + ni;
     wg_copy<CT>(nj, kj, U_j, nj, M, ld);
     wg_copy<CT>(nj, ni, Fji, ni, M + kj, ld);
-    int r2 = wg_cpqr<CT>(nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, trr + 2);
+    int r2 = wg_cpqr<CT>(nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, trr + 2);
     // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
-    wg_formq<CT>(ni, r1, r1, V1, cap, tau, nU, cap);
+    wg_formq<CT>(ni, r1, r1, V1, cap, tau, nU, cap, vsh);
     ld = kj + r1;
     wg_copy<CT>(nj, kj, V_j, nj, M, ld);
     wg_gemm<CT>(nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
-    int r3 = wg_cpqr<CT>(nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, trr + 4);
+    int r3 = wg_cpqr<CT>(nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, vsh, trr + 4);
     // RRQR4: [V_i | L~_ji^*]
-    wg_formq<CT>(nj, r2, r2, V2, cap, tau + cap, nUj, cap);
+    wg_formq<CT>(nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh);
     ld = ki + r2;
     wg_copy<CT>(ni, ki, V_i, ni, M, ld);
     wg_gemm<CT>(ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, M + ki, ld);
-    int r4 = wg_cpqr<CT>(ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, trr + 6);
+    int r4 = wg_cpqr<CT>(ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, vsh, trr + 6);
     int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
     // new orthonormal bases: columns beyond a tolerance rank are further columns of the same
     // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed)
-    wg_formq<CT>(ni, r1, kin, V1, cap, tau, nU, cap, r1);
-    wg_formq<CT>(ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap);
-    wg_formq<CT>(nj, r2, kjn, V2, cap, tau + cap, nUj, cap, r2);
-    wg_formq<CT>(nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap);
+    wg_formq<CT>(ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1);
+    wg_formq<CT>(ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh);
+    wg_formq<CT>(nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2);
+    wg_formq<CT>(nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh);
     // coefficients by projection: U_i = U~_i L_i, V_i = V~_i R_i, ...
     wg_gemm<CT>(kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
     wg_gemm<CT>(kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
@@ -195,14 +196,14 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
     }
     __syncthreads();
-    int r5 = wg_cpqr<CT>(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, trr);
+    int r5 = wg_cpqr<CT>(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, trr);
     // RRQR: [U_i | M2P_ir] = U~_i L_ir
     wg_copy<CT>(ni, ki, U_i, ni, M, ld);
     wg_copy<CT>(ni, kr, M2P, nr, M + ki, ld);
-    int r6 = wg_cpqr<CT>(ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, trr + 2);
+    int r6 = wg_cpqr<CT>(ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, trr + 2);
     int kin = r5 > r6 ? r5 : r6;
-    wg_formq<CT>(ni, r5, kin, V1, cap, tau, nV, cap);
-    wg_formq<CT>(ni, r6, kin, V2, cap, tau + cap, nU, cap);
+    wg_formq<CT>(ni, r5, kin, V1, cap, tau, nV, cap, vsh);
+    wg_formq<CT>(ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh);
     wg_gemm<CT>(kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
     wg_gemm<CT>(kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
     // A_ri := A_ri R_i^* + P2L_ri V~_i
@@ -393,15 +394,18 @@ __global__ void __launch_bounds__(WG) k_elim_trsm(LevelPtrs P, const int* __rest
       W[(size_t)p * ldw + c] = t;
     }
   }
+  double* Wc = W + c;
   for (int r = 1; r < m; ++r) {
-    double v = W[(size_t)r * ldw + c];
-    for (int t = 0; t < r; ++t) v = fma(-A[(size_t)r * m + t], W[(size_t)t * ldw + c], v);
-    W[(size_t)r * ldw + c] = v;
+    const double* Ar = A + (size_t)r * m;
+    double v = seq_dot(r, [&](int t) { return -Ar[t]; }, [&](int t) { return Wc[(size_t)t * ldw]; }, Wc[(size_t)r * ldw]);
+    Wc[(size_t)r * ldw] = v;
   }
   for (int r = m - 1; r >= 0; --r) {
-    double v = W[(size_t)r * ldw + c];
-    for (int t = r + 1; t < m; ++t) v = fma(-A[(size_t)r * m + t], W[(size_t)t * ldw + c], v);
-    W[(size_t)r * ldw + c] = v / A[(size_t)r * m + r];
+    const double* Ar = A + (size_t)r * m + r + 1;
+    const double* Wr = Wc + (size_t)(r + 1) * ldw;
+    double v = seq_dot(m - r - 1, [&](int t) { return -Ar[t]; }, [&](int t) { return Wr[(size_t)t * ldw]; },
+                       Wc[(size_t)r * ldw]);
+    Wc[(size_t)r * ldw] = v / A[(size_t)r * m + r];
   }
 }
 
@@ -1107,7 +1111,7 @@ void factor_system(aifmm_system& s) {
         const XformEntry* ex = d_xent.p + x_off[rix];
         auto ce = ev_pair(cmp_ev);
         AIFMM_HIP(hipEventRecord(ce.first, st));
-        hipLaunchKernelGGL(k_compress, dim3(ne), dim3(CT), 0, st, P, er, ne, ws.p, wsz, cap, s.tol, r_off[rix]);
+        hipLaunchKernelGGL(k_compress, dim3(ne), dim3(CT), (size_t)cap * sizeof(double), st, P, er, ne, ws.p, wsz, cap, s.tol, r_off[rix]);
         AIFMM_HIP(hipEventRecord(ce.second, st));
         int grid = std::min<int64_t>(XG, (int64_t)nx * maxblk);
         hipLaunchKernelGGL(k_row_xform, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p, sstride);
