@@ -49,6 +49,20 @@ def cpu_baseline(cfg, n_sample=8192, depth=4):
                       f"{t:.2f} s on 1 core, x{scale:.0f} (point-count ratio, lower bound)"}
 
 
+def copy_calibration(mib):
+    """A fill then five copies of a buffer of known size, so that the per-dispatch FETCH_SIZE /
+    WRITE_SIZE counters can be scaled to bytes (a copy reads and writes exactly its size)."""
+    import torch
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "copies": 5}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,10 +71,16 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a fill and five plain device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import paper_2301_12704_amd as A
 

@@ -1026,6 +1026,7 @@ void factor_system(aifmm_system& s) {
   s.stats.schur_flops = s.stats.schur_bytes = s.stats.trsm_flops = s.stats.lu_flops = 0;
   s.stats.schur_kernel_s = s.stats.compress_kernel_s = s.stats.schur_launches = s.stats.compress_launches = 0;
   s.trace.clear();
+  s.sc = SolveCache{};
   s.d_flag.zero(st);
   for (int l = L; l >= 2; --l) {
     auto tl = std::chrono::steady_clock::now();

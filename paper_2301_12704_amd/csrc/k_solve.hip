@@ -10,92 +10,83 @@
 
 namespace aifmm {
 
-struct SolvePtrs {
-  int nrhs;
-  const int* n;
-  const int* k;
-  const int* grp_off;
-  const int* grp_box;
-  const int* grp_elim;
-  const double* fslab;
-  const int64_t* fC;
-  const int64_t* fW;
-  const int64_t* xoff;   // per box, rows of x / X at this level
-  const int64_t* koff;   // per box, rows of y / z / Z at this level
-  double* Xr;            // rhs of X rows (level l)
-  double* Zr;            // rhs of Z rows (level l) == rhs of X rows of level l-1
-  double* xs;            // solution x (level l)
-  const double* ys;      // solution y (level l) == solution x of level l-1
-  double* wsave;         // per box m x nrhs
-  const int64_t* woff;
-};
+constexpr int SOLVE_KC = 64;  // rows of B staged per wave and chunk
 
-__device__ inline int grp_dim(const SolvePtrs& S, int g, int G, int b, int q, int e) {
-  if (g == G - 1) return S.k[b];
-  return e ? S.k[q] : S.n[q];
+// Y tile = A tile B over column block [cb, cb + NRB): the four waves of the workgroup split
+// K in quarters (each stages its rows of B in LDS), lane = row; the partial sums are added in
+// wave order, so the result does not depend on scheduling.
+template <int NRB, int MODE>
+__global__ void __launch_bounds__(WG) k_rows_gemm(const STask* __restrict__ tasks, const double* __restrict__ fslab,
+                                                 const double* __restrict__ Bbuf, double* Y0buf, double* Y1buf,
+                                                 const double* __restrict__ Yinit, int nr) {
+  __shared__ double sB[4 * SOLVE_KC * NRB];
+  STask T = tasks[blockIdx.x];
+  int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  int Kq = (T.K + 3) / 4;
+  int k0 = w * Kq, k1 = min(T.K, k0 + Kq);
+  bool rv = lane < T.rows;
+  const double* A = fslab + T.a + (size_t)(rv ? lane : 0) * T.lda;
+  const double* B = Bbuf + (size_t)T.b * nr;
+  double* sw = sB + w * SOLVE_KC * NRB;
+  for (int cb = 0; cb < nr; cb += NRB) {
+    double acc[NRB];
+#pragma unroll
+    for (int c = 0; c < NRB; ++c) acc[c] = 0.0;
+    for (int c0 = 0; c0 < Kq; c0 += SOLVE_KC) {
+      for (int idx = lane; idx < SOLVE_KC * NRB; idx += WAVE) {
+        int kk = idx / NRB, cc = idx - kk * NRB;
+        int k = k0 + c0 + kk, col = cb + cc;
+        sw[idx] = (k < k1 && col < nr) ? B[(size_t)k * nr + col] : 0.0;
+      }
+      __syncthreads();
+      int kn = min(SOLVE_KC, k1 - (k0 + c0));
+      if (rv) {
+        const double* Ar = A + k0 + c0;
+        for (int kk = 0; kk < kn; kk += 8) {
+          double a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = (kk + u < kn) ? Ar[kk + u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int c = 0; c < NRB; ++c) acc[c] = fma(a[u], sw[(kk + u) * NRB + c], acc[c]);
+        }
+      }
+      __syncthreads();
+    }
+    // reduction over the four waves
+#pragma unroll
+    for (int c = 0; c < NRB; ++c) sB[(w * WAVE + lane) * NRB + c] = acc[c];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < T.rows * NRB; idx += WG) {
+      int r = idx / NRB, c = idx - r * NRB;
+      int col = cb + c;
+      if (col >= nr) continue;
+      double s = sB[(0 * WAVE + r) * NRB + c] + sB[(1 * WAVE + r) * NRB + c];
+      s += sB[(2 * WAVE + r) * NRB + c];
+      s += sB[(3 * WAVE + r) * NRB + c];
+      if (MODE == 0) {  // w = Piv^{-1}[rhs(X_b); 0]; rows from sel on are also rhs(Z_b)
+        Y0buf[(size_t)(T.y + r) * nr + col] = s;
+        if (r >= T.sel) Y1buf[(size_t)(T.z + r) * nr + col] = s;
+      } else if (MODE == 1) {  // rhs(rows(p)) -= A[rows(p), x_b] w_x
+        double* Y = T.sel ? Y1buf : Y0buf;
+        Y[(size_t)(T.y + r) * nr + col] -= s;
+      } else {  // sol(x_b) = w_x - W sol(O_c)
+        Y0buf[(size_t)(T.y + r) * nr + col] = Yinit[(size_t)(T.y0 + r) * nr + col] - s;
+      }
+    }
+    __syncthreads();
+  }
 }
 
-// w = Piv^{-1} [rhs(X_b); 0] = Px rhs(X_b); rhs(rows(p)) -= A[rows(p), x_b] w_x; rhs(Z_b) = w_z
-__global__ void __launch_bounds__(WG) k_fwd(SolvePtrs S, const int* __restrict__ boxes) {
-  int b = boxes[blockIdx.x];
-  int g0 = S.grp_off[b], G = S.grp_off[b + 1] - g0;
-  int n = S.n[b], k = S.k[b], m = n + k, nr = S.nrhs;
-  int C = 0;
-  for (int g = 0; g < G; ++g) C += grp_dim(S, g, G, b, S.grp_box[g0 + g], S.grp_elim[g0 + g]);
-  int ldw = C + n;
-  const double* W = S.fslab + S.fW[b];
-  const double* Px = W + C;  // columns C .. C+n of the extended W
-  const double* rx = S.Xr + S.xoff[b] * nr;
-  double* w = S.wsave + S.woff[b];
-  for (int idx = threadIdx.x; idx < m * nr; idx += WG) {
-    int r = idx / nr, c = idx - r * nr;
-    double acc = 0.0;
-    for (int t = 0; t < n; ++t) acc += Px[(size_t)r * ldw + t] * rx[(size_t)t * nr + c];
-    w[idx] = acc;
-  }
-  __syncthreads();
-  const double* Cb = S.fslab + S.fC[b];
-  int ro = 0;
-  for (int g = 0; g < G - 1; ++g) {
-    int p = S.grp_box[g0 + g], e = S.grp_elim[g0 + g];
-    int rd = e ? S.k[p] : S.n[p];
-    double* dst = e ? S.Zr + S.koff[p] * nr : S.Xr + S.xoff[p] * nr;
-    for (int idx = threadIdx.x; idx < rd * nr; idx += WG) {
-      int r = idx / nr, c = idx - r * nr;
-      double acc = 0.0;
-      for (int t = 0; t < n; ++t) acc += Cb[(size_t)(ro + r) * n + t] * w[(size_t)t * nr + c];
-      dst[idx] -= acc;
-    }
-    ro += rd;
-  }
-  double* zb = S.Zr + S.koff[b] * nr;
-  for (int idx = threadIdx.x; idx < k * nr; idx += WG) zb[idx] = w[(size_t)n * nr + idx];
-}
-
-// sol(x_b; z_b) = w - W sol(O_c);  only x_b is needed further (z never couples forward)
-__global__ void __launch_bounds__(WG) k_bwd(SolvePtrs S, const int* __restrict__ boxes) {
-  int b = boxes[blockIdx.x];
-  int g0 = S.grp_off[b], G = S.grp_off[b + 1] - g0;
-  int n = S.n[b], nr = S.nrhs;
-  int C = 0;
-  for (int g = 0; g < G; ++g) C += grp_dim(S, g, G, b, S.grp_box[g0 + g], S.grp_elim[g0 + g]);
-  int ldw = C + n;
-  const double* W = S.fslab + S.fW[b];
-  const double* w = S.wsave + S.woff[b];
-  double* xb = S.xs + S.xoff[b] * nr;
-  for (int idx = threadIdx.x; idx < n * nr; idx += WG) {
-    int r = idx / nr, c = idx - r * nr;
-    double acc = w[idx];
-    int co = 0;
-    for (int g = 0; g < G; ++g) {
-      int q = S.grp_box[g0 + g], e = S.grp_elim[g0 + g];
-      int cd = grp_dim(S, g, G, b, q, e);
-      const double* src = (g == G - 1) ? S.ys + S.koff[b] * nr : (e ? S.ys + S.koff[q] * nr : S.xs + S.xoff[q] * nr);
-      for (int t = 0; t < cd; ++t) acc -= W[(size_t)r * ldw + co + t] * src[(size_t)t * nr + c];
-      co += cd;
-    }
-    xb[idx] = acc;
-  }
+// B of the backward products: the solution segments of the coupled columns, gathered into one
+// contiguous block per box (one workgroup per segment; sel 1 = x of this level, 0 = y).
+__global__ void __launch_bounds__(WG) k_gather_seg(const STask* __restrict__ segs, const double* ys, const double* xs,
+                                                  double* g, int nr) {
+  STask T = segs[blockIdx.x];
+  const double* src = (T.sel ? xs : ys) + (size_t)T.b * nr;
+  double* dst = g + (size_t)T.y * nr;
+  for (int idx = threadIdx.x; idx < T.rows * nr; idx += WG) dst[idx] = src[idx];
 }
 
 // dense LU solve of the level-2 system, columns of the right-hand side in parallel
@@ -151,77 +142,194 @@ static void launch_check(const char* what) {
   if (e != hipSuccess) throw Error{AIFMM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
+// Task lists of the solve sweeps (static after the factorization): per level and colour,
+// the row tiles of the forward products, of the forward updates, of the backward products and
+// the gather segments.
+static void build_solve_plan(aifmm_system& s) {
+  SolveCache& sc = s.sc;
+  int L = s.L;
+  sc.lev.clear();
+  sc.lev.resize(L + 1);
+  hipStream_t st = s.stream;
+  for (int l = 2; l <= L; ++l) {
+    LevelDev& lv = s.lev[l];
+    LevelPlan& P = s.plan[l];
+    SolveLevel& sl = sc.lev[l];
+    std::vector<STask> fw, fu, bw, gs;
+    sl.fw_off = {0};
+    sl.fu_off = {0};
+    sl.bw_off = {0};
+    sl.gs_off = {0};
+    sl.woff.assign(lv.nb + 1, 0);
+    for (int b = 0; b < lv.nb; ++b) sl.woff[b + 1] = sl.woff[b] + lv.n[b] + lv.kfin[b];
+    int64_t gmax = 0;
+    for (size_t c = 0; c + 1 < P.col_off.size(); ++c) {
+      int64_t go = 0;
+      for (int q = P.col_off[c]; q < P.col_off[c + 1]; ++q) {
+        int b = P.order[q];
+        int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+        int n = lv.n[b], k = lv.kfin[b], m = n + k;
+        auto dim = [&](int g) {
+          if (g == G - 1) return k;
+          int p = P.grp_box[g0 + g];
+          return P.grp_elim[g0 + g] ? lv.kfin[p] : lv.n[p];
+        };
+        int C = 0;
+        for (int g = 0; g < G; ++g) C += dim(g);
+        int ldw = C + n;
+        for (int r0 = 0; r0 < m; r0 += WAVE) {
+          STask t{};
+          t.a = lv.fW[b] + C + (int64_t)r0 * ldw;
+          t.lda = ldw;
+          t.K = n;
+          t.rows = std::min(WAVE, m - r0);
+          t.b = lv.xoff[b];
+          t.y = sl.woff[b] + r0;
+          t.sel = n - r0;
+          t.z = lv.koff[b] + r0 - n;
+          fw.push_back(t);
+        }
+        int ro = 0;
+        for (int g = 0; g < G - 1; ++g) {
+          int p = P.grp_box[g0 + g], e = P.grp_elim[g0 + g];
+          int rd = dim(g);
+          for (int r0 = 0; r0 < rd; r0 += WAVE) {
+            STask t{};
+            t.a = lv.fC[b] + (int64_t)(ro + r0) * n;
+            t.lda = n;
+            t.K = n;
+            t.rows = std::min(WAVE, rd - r0);
+            t.b = sl.woff[b];
+            t.y = (e ? lv.koff[p] : lv.xoff[p]) + r0;
+            t.sel = e;
+            fu.push_back(t);
+          }
+          ro += rd;
+        }
+        int co = 0;
+        for (int g = 0; g < G; ++g) {
+          int p = P.grp_box[g0 + g], e = P.grp_elim[g0 + g];
+          int cd = dim(g);
+          if (cd > 0) {
+            STask t{};
+            t.y = go + co;
+            t.rows = cd;
+            if (g == G - 1) { t.b = lv.koff[b]; t.sel = 0; }
+            else if (e) { t.b = lv.koff[p]; t.sel = 0; }
+            else { t.b = lv.xoff[p]; t.sel = 1; }
+            gs.push_back(t);
+          }
+          co += cd;
+        }
+        for (int r0 = 0; r0 < n; r0 += WAVE) {
+          STask t{};
+          t.a = lv.fW[b] + (int64_t)r0 * ldw;
+          t.lda = ldw;
+          t.K = C;
+          t.rows = std::min(WAVE, n - r0);
+          t.b = go;
+          t.y = lv.xoff[b] + r0;
+          t.y0 = sl.woff[b] + r0;
+          bw.push_back(t);
+        }
+        go += C;
+      }
+      gmax = std::max(gmax, go);
+      sl.fw_off.push_back((int)fw.size());
+      sl.fu_off.push_back((int)fu.size());
+      sl.bw_off.push_back((int)bw.size());
+      sl.gs_off.push_back((int)gs.size());
+    }
+    sl.grows = gmax;
+    sl.fw.upload(fw, st);
+    sl.fu.upload(fu, st);
+    sl.bw.upload(bw, st);
+    sl.gs.upload(gs, st);
+  }
+  sc.nr_cap = 0;
+  sc.built = true;
+}
+
+static void ensure_solve_buffers(aifmm_system& s, int nr) {
+  SolveCache& sc = s.sc;
+  if (!sc.built) build_solve_plan(s);
+  if (nr <= sc.nr_cap) return;
+  int L = s.L;
+  sc.R.clear();
+  sc.X.clear();
+  sc.R.resize(L + 1);
+  sc.X.resize(L + 1);
+  sc.W.clear();
+  sc.W.resize(L + 1);
+  for (int l = L; l >= 2; --l) {
+    int64_t K = s.lev[l].koff[s.lev[l].nb];
+    sc.R[l - 1].alloc((size_t)std::max<int64_t>(1, K) * nr);
+    sc.X[l - 1].alloc((size_t)std::max<int64_t>(1, K) * nr);
+    sc.W[l].alloc((size_t)std::max<int64_t>(1, sc.lev[l].woff.back()) * nr);
+  }
+  int64_t gmax = 1;
+  for (int l = 2; l <= L; ++l) gmax = std::max(gmax, sc.lev[l].grows);
+  sc.G.alloc((size_t)gmax * nr);
+  sc.nr_cap = nr;
+}
+
+template <int MODE>
+static void launch_rows(int ntask, const STask* t, const double* fslab, const double* B, double* Y0, double* Y1,
+                        const double* Yi, int nr, hipStream_t st) {
+  if (ntask <= 0) return;
+  dim3 g(ntask), blk(WG);
+  if (nr == 1) hipLaunchKernelGGL((k_rows_gemm<1, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
+  else if (nr == 2) hipLaunchKernelGGL((k_rows_gemm<2, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
+  else if (nr <= 4) hipLaunchKernelGGL((k_rows_gemm<4, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
+  else if (nr <= 8) hipLaunchKernelGGL((k_rows_gemm<8, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
+  else hipLaunchKernelGGL((k_rows_gemm<16, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
+}
+
 // Solve with tree-ordered row-major right-hand sides (N x nr) on the device; x may alias nothing.
 void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x) {
   hipStream_t st = s.stream;
   int L = s.L;
   int64_t N = s.N;
-  // buffers: rhs per level (X rows of level l; Z rows of level l == X rows of level l-1)
-  std::vector<DBuf<double>> R(L + 2), X(L + 2);  // R[l]: rhs of X rows at level l; X[l]: solution x at level l
-  R[L].alloc((size_t)N * nr);
-  AIFMM_HIP(hipMemcpyAsync(R[L].p, rhs, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, st));
+  ensure_solve_buffers(s, nr);
+  SolveCache& sc = s.sc;
+  // rhs of the X rows of level L is the input; rhs of Z rows of level l = X rows of level l-1
+  AIFMM_HIP(hipMemcpyAsync(x, rhs, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, st));
+  auto Xrows = [&](int l) { return l == L ? x : sc.R[l].p; };   // rhs, overwritten in place
   for (int l = L; l >= 2; --l) {
     int64_t K = s.lev[l].koff[s.lev[l].nb];
-    R[l - 1].alloc((size_t)std::max<int64_t>(1, K) * nr);
-    R[l - 1].zero(st);
-    X[l - 1].alloc((size_t)std::max<int64_t>(1, K) * nr);
+    if (K > 0) AIFMM_HIP(hipMemsetAsync(sc.R[l - 1].p, 0, sizeof(double) * K * nr, st));
   }
-  // per level device offsets and w storage
-  std::vector<DBuf<int64_t>> dx(L + 1), dk(L + 1), dwo(L + 1);
-  std::vector<DBuf<double>> wsv(L + 1);
-  for (int l = 2; l <= L; ++l) {
-    LevelDev& lv = s.lev[l];
-    dx[l].upload(lv.xoff, st);
-    dk[l].upload(lv.koff, st);
-    std::vector<int64_t> wo(lv.nb);
-    int64_t o = 0;
-    for (int bx = 0; bx < lv.nb; ++bx) { wo[bx] = o; o += (int64_t)(lv.n[bx] + lv.kfin[bx]) * nr; }
-    dwo[l].upload(wo, st);
-    wsv[l].alloc(std::max<int64_t>(1, o));
-  }
-  auto sp = [&](int l) {
-    LevelDev& lv = s.lev[l];
-    SolvePtrs S;
-    S.nrhs = nr;
-    S.n = lv.d_n.p;
-    S.k = lv.d_k.p;
-    S.grp_off = lv.d_grp_off.p;
-    S.grp_box = lv.d_grp_box.p;
-    S.grp_elim = lv.d_grp_elim.p;
-    S.fslab = lv.fslab.p;
-    S.fC = lv.d_fC.p;
-    S.fW = lv.d_fW.p;
-    S.xoff = dx[l].p;
-    S.koff = dk[l].p;
-    S.Xr = R[l].p;
-    S.Zr = R[l - 1].p;
-    S.xs = l == L ? x : X[l].p;
-    S.ys = X[l - 1].p;
-    S.wsave = wsv[l].p;
-    S.woff = dwo[l].p;
-    return S;
-  };
+  // the forward sweep keeps rhs(X^{(L)}) in x; the backward sweep overwrites x with sol(x^{(L)})
+  // box by box after every read of rhs(X_b) (the forward sweep has finished by then)
   for (int l = L; l >= 2; --l) {
-    SolvePtrs S = sp(l);
-    LevelPlan& P = s.plan[l];
-    for (size_t c = 0; c + 1 < P.col_off.size(); ++c) {
-      int nbox = P.col_off[c + 1] - P.col_off[c];
-      hipLaunchKernelGGL(k_fwd, dim3(nbox), dim3(WG), 0, st, S, s.lev[l].d_order.p + P.col_off[c]);
+    LevelDev& lv = s.lev[l];
+    SolveLevel& sl = sc.lev[l];
+    double* Xr = Xrows(l);
+    double* Zr = sc.R[l - 1].p;
+    for (size_t c = 0; c + 1 < sl.fw_off.size(); ++c) {
+      launch_rows<0>(sl.fw_off[c + 1] - sl.fw_off[c], sl.fw.p + sl.fw_off[c], lv.fslab.p, Xr, sc.W[l].p, Zr, nullptr,
+                     nr, st);
+      launch_rows<1>(sl.fu_off[c + 1] - sl.fu_off[c], sl.fu.p + sl.fu_off[c], lv.fslab.p, sc.W[l].p, Xr, Zr, nullptr,
+                     nr, st);
     }
   }
   launch_check("forward sweep");
   // level-2 multipoles: y^{(2)} = Top^{-1} rhs(Z^{(2)})
   if (s.Ktop > 0) {
-    AIFMM_HIP(hipMemcpyAsync(X[1].p, R[1].p, sizeof(double) * s.Ktop * nr, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_top_solve, dim3(1), dim3(WG), 0, st, s.d_top.p, s.d_top_piv.p, s.Ktop, X[1].p, nr);
+    AIFMM_HIP(hipMemcpyAsync(sc.X[1].p, sc.R[1].p, sizeof(double) * s.Ktop * nr, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_top_solve, dim3(1), dim3(WG), 0, st, s.d_top.p, s.d_top_piv.p, s.Ktop, sc.X[1].p, nr);
   }
   for (int l = 2; l <= L; ++l) {
-    SolvePtrs S = sp(l);
-    LevelPlan& P = s.plan[l];
-    for (size_t c = P.col_off.size() - 1; c-- > 0;) {
-      int nbox = P.col_off[c + 1] - P.col_off[c];
-      // boxes of one colour are independent; reverse order inside the colour is not needed
-      hipLaunchKernelGGL(k_bwd, dim3(nbox), dim3(WG), 0, st, S, s.lev[l].d_order.p + P.col_off[c]);
+    LevelDev& lv = s.lev[l];
+    SolveLevel& sl = sc.lev[l];
+    double* xs = l == L ? x : sc.X[l].p;
+    const double* ys = sc.X[l - 1].p;
+    for (size_t c = sl.bw_off.size() - 1; c-- > 0;) {
+      int ng = sl.gs_off[c + 1] - sl.gs_off[c];
+      if (ng > 0)
+        hipLaunchKernelGGL(k_gather_seg, dim3(ng), dim3(WG), 0, st, sl.gs.p + sl.gs_off[c], ys, xs, sc.G.p, nr);
+      launch_rows<2>(sl.bw_off[c + 1] - sl.bw_off[c], sl.bw.p + sl.bw_off[c], lv.fslab.p, sc.G.p, xs, nullptr,
+                     sc.W[l].p, nr, st);
     }
   }
   launch_check("backward sweep");

@@ -166,6 +166,29 @@ struct TraceRec {
   double ratio[8];
 };
 
+// One tile of at most 64 rows of a solve-sweep product Y (rows x nr) = A (rows x K, row-major
+// lda) B (K x nr, row-major); how Y is written depends on the kernel.  Offsets are in elements
+// of the factor store (a) and in rows of the right-hand-side buffers (b, y, y0, z).
+struct STask {
+  int64_t a, b, y, y0, z;
+  int lda, K, rows, sel;
+};
+
+// Static task lists of the solve sweeps of one level (per colour offsets) and buffers.
+struct SolveLevel {
+  DBuf<STask> fw, fu, bw, gs;
+  std::vector<int> fw_off, fu_off, bw_off, gs_off;
+  std::vector<int64_t> woff;  // rows of w = Piv^{-1} rhs per box
+  int64_t grows = 0;          // rows of the largest gathered colour
+};
+struct SolveCache {
+  bool built = false;
+  int nr_cap = 0;
+  std::vector<SolveLevel> lev;
+  std::vector<DBuf<double>> R, X, W;
+  DBuf<double> G;
+};
+
 struct Stats {
   double build_s = 0, factor_s = 0, solve_s = 0;
   double schur_flops = 0, schur_bytes = 0, trsm_flops = 0, lu_flops = 0;
@@ -199,6 +222,7 @@ struct aifmm_system {
   aifmm::DBuf<int> d_flag;        // [0] singular flag, [1] box, [2] level, [3] capacity flag
   aifmm::DBuf<int> d_rounds;      // scratch upload area for round lists
   aifmm::Stats stats;
+  aifmm::SolveCache sc;           // solve task lists and buffers (rebuilt after every factor)
   std::vector<aifmm::TraceRec> trace;
   size_t device_bytes = 0;
 };
