@@ -338,4 +338,141 @@ __device__ inline int wg_lu(int m, double* A, int lda, int* ipiv, ValIdx* shv) {
   return 0;
 }
 
+
+// The same factorization as wg_lu, blocked in panels of NB columns for a 256-thread workgroup:
+// every element still receives its updates a = fma(-l, u, a) one at a time in ascending step
+// order and every pivot is chosen from the same fully updated column, so the factors are bit
+// for bit those of wg_lu.  Inside a panel only its NB columns are updated (one thread per
+// row, the row's panel entries loaded together); row swaps outside the panel are applied
+// after it in step order; then the U12 rows are solved column by column and the trailing
+// matrix is updated in 64 x 64 tiles staged through LDS.  sh: LDS of at least
+// NB + 64 (NB + 1) + 65 NB doubles; ipv: NB ints of LDS.
+template <int NB>
+__device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx* shv, double* sh, int* ipv) {
+  constexpr int NT = WG;
+  const int tid = threadIdx.x;
+  double* prow = sh;
+  double* Ls = sh + NB;                // [64][NB + 1]
+  double* Us = Ls + 64 * (NB + 1);     // [NB][65]
+  for (int k0 = 0; k0 < m; k0 += NB) {
+    const int nb = min(NB, m - k0);
+    for (int s = 0; s < nb; ++s) {
+      const int k = k0 + s;
+      ValIdx best{-1.0, INT_MAX};
+      for (int i = k + tid; i < m; i += NT) {
+        ValIdx c{fabs(A[(size_t)i * lda + k]), i};
+        if (vi_better(c, best)) best = c;
+      }
+      best = wg_argmax<NT>(best, shv);
+      if (best.v == 0.0) return 1 + k;
+      const int p = best.i;
+      if (tid == 0) { ipiv[k] = p; ipv[s] = p; }
+      if (p != k)
+        for (int j = tid; j < nb; j += NT) {
+          double t = A[(size_t)k * lda + k0 + j];
+          A[(size_t)k * lda + k0 + j] = A[(size_t)p * lda + k0 + j];
+          A[(size_t)p * lda + k0 + j] = t;
+        }
+      __syncthreads();
+      for (int j = tid; j < nb; j += NT) prow[j] = A[(size_t)k * lda + k0 + j];
+      __syncthreads();
+      const double piv = prow[s];
+      for (int i = k + 1 + tid; i < m; i += NT) {
+        double* row = A + (size_t)i * lda + k0;
+        double as = row[s];
+        double v[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) v[j] = (j > s && j < nb) ? row[j] : 0.0;
+        double l = as / piv;
+        row[s] = l;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j > s && j < nb) row[j] = fma(-l, prow[j], v[j]);
+      }
+      __syncthreads();
+    }
+    // the panel's row swaps on every other column, in step order
+    for (int c = tid; c < m; c += NT) {
+      if (c >= k0 && c < k0 + nb) continue;
+      for (int s = 0; s < nb; ++s) {
+        int r = k0 + s, p = ipv[s];
+        if (p != r) {
+          double t = A[(size_t)r * lda + c];
+          A[(size_t)r * lda + c] = A[(size_t)p * lda + c];
+          A[(size_t)p * lda + c] = t;
+        }
+      }
+    }
+    __syncthreads();
+    const int c1 = k0 + nb;
+    if (c1 >= m) break;
+    // U12: rows k0 .. c1-1 of the columns right of the panel (unit-lower L11 from the panel)
+    for (int idx = tid; idx < nb * nb; idx += NT) {
+      int r = idx / nb, t = idx - r * nb;
+      Ls[r * (NB + 1) + t] = A[(size_t)(k0 + r) * lda + k0 + t];
+    }
+    __syncthreads();
+    for (int c = c1 + tid; c < m; c += NT) {
+      double u[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) u[t] = t < nb ? A[(size_t)(k0 + t) * lda + c] : 0.0;
+#pragma unroll
+      for (int r = 1; r < NB; ++r)
+#pragma unroll
+        for (int t = 0; t < r; ++t)
+          if (r < nb) u[r] = fma(-Ls[r * (NB + 1) + t], u[t], u[r]);
+#pragma unroll
+      for (int t = 1; t < NB; ++t)
+        if (t < nb) A[(size_t)(k0 + t) * lda + c] = u[t];
+    }
+    __syncthreads();
+    // A22 -= L21 U12, one fused multiply-add per step in ascending order, 64 x 64 tiles
+    const int rem = m - c1;
+    const int tiles = (rem + 63) / 64;
+    const int ty = tid / 16, tx = tid % 16;
+    for (int tt = 0; tt < tiles * tiles; ++tt) {
+      int r0 = c1 + (tt / tiles) * 64, cc0 = c1 + (tt % tiles) * 64;
+      for (int idx = tid; idx < 64 * NB; idx += NT) {
+        int r = idx / NB, t = idx - r * NB;
+        int gr = r0 + r;
+        Ls[r * (NB + 1) + t] = (gr < m && t < nb) ? A[(size_t)gr * lda + k0 + t] : 0.0;
+      }
+      for (int idx = tid; idx < NB * 64; idx += NT) {
+        int t = idx / 64, c = idx - t * 64;
+        int gc = cc0 + c;
+        Us[t * 65 + c] = (gc < m && t < nb) ? A[(size_t)(k0 + t) * lda + gc] : 0.0;
+      }
+      __syncthreads();
+      double a[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          int gr = r0 + ty * 4 + x, gc = cc0 + tx * 4 + y;
+          a[x][y] = (gr < m && gc < m) ? A[(size_t)gr * lda + gc] : 0.0;
+        }
+      for (int t = 0; t < nb; ++t) {
+        double lv[4], uv[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) lv[x] = -Ls[(ty * 4 + x) * (NB + 1) + t];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) uv[y] = Us[t * 65 + tx * 4 + y];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) a[x][y] = fma(lv[x], uv[y], a[x][y]);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          int gr = r0 + ty * 4 + x, gc = cc0 + tx * 4 + y;
+          if (gr < m && gc < m) A[(size_t)gr * lda + gc] = a[x][y];
+        }
+      __syncthreads();
+    }
+  }
+  return 0;
+}
+
 }  // namespace aifmm

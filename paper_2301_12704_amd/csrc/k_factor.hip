@@ -359,11 +359,14 @@ __global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __re
   for (int r = threadIdx.x; r < n; r += WG) W[(size_t)r * ldw + C + r] = 1.0;  // extension: Piv^{-1}[:, x_b]
 }
 
+constexpr int LU_NB = 16;
 __global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restrict__ boxes, int* flag) {
   int b = boxes[blockIdx.x];
   int m = P.n[b] + P.k[b];
   __shared__ ValIdx shv[WG / WAVE + 1];
-  int st = wg_lu(m, P.fslab + P.fLU[b], m, P.fpiv + P.fpiv_off[b], shv);
+  __shared__ double sh[LU_NB + 64 * (LU_NB + 1) + LU_NB * 65];
+  __shared__ int ipv[LU_NB];
+  int st = wg_lu_blocked<LU_NB>(m, P.fslab + P.fLU[b], m, P.fpiv + P.fpiv_off[b], shv, sh, ipv);
   if (st && threadIdx.x == 0) {
     flag[0] = 1;
     flag[1] = b;
