@@ -19,6 +19,7 @@
 #include <cstdlib>
 
 #include "dense_wg.hpp"
+#include "team.hpp"
 #include "system.hpp"
 
 namespace aifmm {
@@ -74,14 +75,19 @@ struct LevelPtrs {
 constexpr int CT = 512;
 
 __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* __restrict__ ent, int nent, double* ws,
-                                                 int64_t wsz, int cap, double tol, int64_t tbase) {
-  int e = blockIdx.x;
+                                                 int64_t wsz, int cap, double tol, int64_t tbase, int G,
+                                                 unsigned* ctr, Cand* part, int* abort) {
+  int e = blockIdx.x / G;
   if (e >= nent) return;
+  Team<CT> T;
+  T.init(blockIdx.x - e * G, G, ctr + e, part + (size_t)e * 2 * G, abort);
   RoundEntry R = ent[e];
   int* tr = P.trace + (tbase + e) * 6;
   double* trr = P.trace_ratio + (tbase + e) * 8;
   __shared__ ValIdx shv[CT / WAVE + 1];
-  extern __shared__ double vsh[];  // one reflector (cap doubles)
+  extern __shared__ double vsh[];  // one reflector (cap doubles), then pivot positions (2 x 2cap ints)
+  int* pos = (int*)(vsh + cap);
+  int* at = pos + 2 * cap;
   double* w = ws + (size_t)e * wsz;
   size_t c2 = (size_t)cap * cap;
   double* Lb_i = w;
@@ -116,67 +122,67 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     double* Aji = P.slab + P.il_slot[R.e_ji];  // (Z_j, y_i): kj x ki, ld ni
     // RRQR1: [U_i | P2P_ij] = U~_i L_ij
     int ld = ki + nj;
-    wg_copy<CT>(ni, ki, U_i, ni, M, ld);
-    wg_copy<CT>(ni, nj, Fij, nj, M + ki, ld);
-    int r1 = wg_cpqr<CT>(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, trr);
+    t_copy(T, ni, ki, U_i, ni, M, ld);
+    t_copy(T, ni, nj, Fij, nj, M + ki, ld);
+    int r1 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr);
     // RRQR2: [U_j | P2P_ji] = U~_j L_ji
     ld = kj + ni;
-    wg_copy<CT>(nj, kj, U_j, nj, M, ld);
-    wg_copy<CT>(nj, ni, Fji, ni, M + kj, ld);
-    int r2 = wg_cpqr<CT>(nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, trr + 2);
+    t_copy(T, nj, kj, U_j, nj, M, ld);
+    t_copy(T, nj, ni, Fji, ni, M + kj, ld);
+    int r2 = t_cpqr(T, nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2);
     // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
-    wg_formq<CT>(ni, r1, r1, V1, cap, tau, nU, cap, vsh);
+    t_formq(T, ni, r1, r1, V1, cap, tau, nU, cap, vsh);
     ld = kj + r1;
-    wg_copy<CT>(nj, kj, V_j, nj, M, ld);
-    wg_gemm<CT>(nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
-    int r3 = wg_cpqr<CT>(nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, vsh, trr + 4);
+    t_copy(T, nj, kj, V_j, nj, M, ld);
+    t_gemm(T, nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
+    int r3 = t_cpqr(T, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, vsh, pos, at, trr + 4);
     // RRQR4: [V_i | L~_ji^*]
-    wg_formq<CT>(nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh);
+    t_formq(T, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh);
     ld = ki + r2;
-    wg_copy<CT>(ni, ki, V_i, ni, M, ld);
-    wg_gemm<CT>(ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, M + ki, ld);
-    int r4 = wg_cpqr<CT>(ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, vsh, trr + 6);
+    t_copy(T, ni, ki, V_i, ni, M, ld);
+    t_gemm(T, ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, M + ki, ld);
+    int r4 = t_cpqr(T, ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, vsh, pos, at, trr + 6);
     int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
     // new orthonormal bases: columns beyond a tolerance rank are further columns of the same
     // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed)
-    wg_formq<CT>(ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1);
-    wg_formq<CT>(ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh);
-    wg_formq<CT>(nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2);
-    wg_formq<CT>(nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh);
+    t_formq(T, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1);
+    t_formq(T, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh);
+    t_formq(T, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2);
+    t_formq(T, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh);
     // coefficients by projection: U_i = U~_i L_i, V_i = V~_i R_i, ...
-    wg_gemm<CT>(kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
-    wg_gemm<CT>(kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
-    wg_gemm<CT>(kjn, kj, nj, 1.0, nUj, cap, true, U_j, nj, false, 0.0, Lb_j, kj1);
-    wg_gemm<CT>(kjn, kj, nj, 1.0, nVj, cap, true, V_j, nj, false, 0.0, Rb_j, kj1);
+    t_gemm(T, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
+    t_gemm(T, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
+    t_gemm(T, kjn, kj, nj, 1.0, nUj, cap, true, U_j, nj, false, 0.0, Lb_j, kj1);
+    t_gemm(T, kjn, kj, nj, 1.0, nVj, cap, true, V_j, nj, false, 0.0, Rb_j, kj1);
     // A_ij := L_i A_ij R_j^* + R~_ij^*,  L~_ij = U~_i^* P2P_ij (kin x nj), R~_ij = V~_j^* L~_ij^*
     int nj1 = nj > 0 ? nj : 1, ni1 = ni > 0 ? ni : 1;
-    wg_gemm<CT>(kin, nj, ni, 1.0, nU, cap, true, Fij, nj, false, 0.0, t1, nj1);
-    wg_gemm<CT>(kjn, kin, nj, 1.0, nVj, cap, true, t1, nj1, true, 0.0, t2, cap);   // R~_ij
-    wg_gemm<CT>(kin, kj, ki, 1.0, Lb_i, ki1, false, Aij, nj, false, 0.0, t1, kj1);  // L_i A_ij
-    for (int idx = threadIdx.x; idx < kin * kjn; idx += CT) {
+    t_gemm(T, kin, nj, ni, 1.0, nU, cap, true, Fij, nj, false, 0.0, t1, nj1);
+    t_gemm(T, kjn, kin, nj, 1.0, nVj, cap, true, t1, nj1, true, 0.0, t2, cap);   // R~_ij
+    t_gemm(T, kin, kj, ki, 1.0, Lb_i, ki1, false, Aij, nj, false, 0.0, t1, kj1);  // L_i A_ij
+    for (int idx = T.gtid; idx < kin * kjn; idx += T.GT) {
       int r = idx / kjn, c = idx - r * kjn;
       Aij[(size_t)r * nj + c] = t2[(size_t)c * cap + r];
     }
-    __syncthreads();
-    wg_gemm<CT>(kin, kjn, kj, 1.0, t1, kj1, false, Rb_j, kj1, true, 1.0, Aij, nj);
+    T.sync();
+    t_gemm(T, kin, kjn, kj, 1.0, t1, kj1, false, Rb_j, kj1, true, 1.0, Aij, nj);
     // A_ji := L_j A_ji R_i^* + R~_ji^*
-    wg_gemm<CT>(kjn, ni, nj, 1.0, nUj, cap, true, Fji, ni, false, 0.0, t1, ni1);
-    wg_gemm<CT>(kin, kjn, ni, 1.0, nV, cap, true, t1, ni1, true, 0.0, t2, cap);    // R~_ji
-    wg_gemm<CT>(kjn, ki, kj, 1.0, Lb_j, kj1, false, Aji, ni, false, 0.0, t1, ki1);
-    for (int idx = threadIdx.x; idx < kjn * kin; idx += CT) {
+    t_gemm(T, kjn, ni, nj, 1.0, nUj, cap, true, Fji, ni, false, 0.0, t1, ni1);
+    t_gemm(T, kin, kjn, ni, 1.0, nV, cap, true, t1, ni1, true, 0.0, t2, cap);    // R~_ji
+    t_gemm(T, kjn, ki, kj, 1.0, Lb_j, kj1, false, Aji, ni, false, 0.0, t1, ki1);
+    for (int idx = T.gtid; idx < kjn * kin; idx += T.GT) {
       int r = idx / kin, c = idx - r * kin;
       Aji[(size_t)r * ni + c] = t2[(size_t)c * cap + r];
     }
-    __syncthreads();
-    wg_gemm<CT>(kjn, kin, ki, 1.0, t1, ki1, false, Rb_i, ki1, true, 1.0, Aji, ni);
+    T.sync();
+    t_gemm(T, kjn, kin, ki, 1.0, t1, ki1, false, Rb_i, ki1, true, 1.0, Aji, ni);
     // bases, fill-ins, ranks
-    wg_copy<CT>(ni, kin, nU, cap, (double*)U_i, ni);
-    wg_copy<CT>(ni, kin, nV, cap, (double*)V_i, ni);
-    wg_copy<CT>(nj, kjn, nUj, cap, (double*)U_j, nj);
-    wg_copy<CT>(nj, kjn, nVj, cap, (double*)V_j, nj);
-    wg_zero<CT>(ni, nj, Fij, nj);
-    wg_zero<CT>(nj, ni, Fji, ni);
-    if (threadIdx.x == 0) {
+    t_copy(T, ni, kin, nU, cap, (double*)U_i, ni);
+    t_copy(T, ni, kin, nV, cap, (double*)V_i, ni);
+    t_copy(T, nj, kjn, nUj, cap, (double*)U_j, nj);
+    t_copy(T, nj, kjn, nVj, cap, (double*)V_j, nj);
+    t_zero(T, ni, nj, Fij, nj);
+    t_zero(T, nj, ni, Fji, ni);
+    if (T.gtid == 0) {
       P.kn[i] = kin;
       P.kn[j] = kjn;
       tr[0] = r1; tr[1] = r2; tr[2] = r3; tr[3] = r4; tr[4] = kin; tr[5] = kjn;
@@ -190,35 +196,35 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     double* Ari = P.slab + P.il_slot[R.e_ji];  // (Z_r, y_i): kr x ki, ld ni
     int ld = ki + kr;
     // RRQR: [V_i | P2L_ri^*] = V~_i R_ri
-    wg_copy<CT>(ni, ki, V_i, ni, M, ld);
-    for (int idx = threadIdx.x; idx < ni * kr; idx += CT) {
+    t_copy(T, ni, ki, V_i, ni, M, ld);
+    for (int idx = T.gtid; idx < ni * kr; idx += T.GT) {
       int a = idx / kr, c = idx - a * kr;
       M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
     }
-    __syncthreads();
-    int r5 = wg_cpqr<CT>(ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, trr);
+    T.sync();
+    int r5 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr);
     // RRQR: [U_i | M2P_ir] = U~_i L_ir
-    wg_copy<CT>(ni, ki, U_i, ni, M, ld);
-    wg_copy<CT>(ni, kr, M2P, nr, M + ki, ld);
-    int r6 = wg_cpqr<CT>(ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, trr + 2);
+    t_copy(T, ni, ki, U_i, ni, M, ld);
+    t_copy(T, ni, kr, M2P, nr, M + ki, ld);
+    int r6 = t_cpqr(T, ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2);
     int kin = r5 > r6 ? r5 : r6;
-    wg_formq<CT>(ni, r5, kin, V1, cap, tau, nV, cap, vsh);
-    wg_formq<CT>(ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh);
-    wg_gemm<CT>(kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
-    wg_gemm<CT>(kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
+    t_formq(T, ni, r5, kin, V1, cap, tau, nV, cap, vsh);
+    t_formq(T, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh);
+    t_gemm(T, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
+    t_gemm(T, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
     // A_ri := A_ri R_i^* + P2L_ri V~_i
-    wg_gemm<CT>(kr, kin, ki, 1.0, Ari, ni, false, Rb_i, ki1, true, 0.0, t1, cap);
-    wg_gemm<CT>(kr, kin, ni, 1.0, P2L, ni, false, nV, cap, false, 1.0, t1, cap);
+    t_gemm(T, kr, kin, ki, 1.0, Ari, ni, false, Rb_i, ki1, true, 0.0, t1, cap);
+    t_gemm(T, kr, kin, ni, 1.0, P2L, ni, false, nV, cap, false, 1.0, t1, cap);
     // A_ir := L_i A_ir + U~_i^* M2P_ir
-    wg_gemm<CT>(kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
-    wg_gemm<CT>(kin, kr, ni, 1.0, nU, cap, true, M2P, nr, false, 1.0, t2, kr1);
-    wg_copy<CT>(kr, kin, t1, cap, Ari, ni);
-    wg_copy<CT>(kin, kr, t2, kr1, Air, nr);
-    wg_copy<CT>(ni, kin, nU, cap, (double*)U_i, ni);
-    wg_copy<CT>(ni, kin, nV, cap, (double*)V_i, ni);
-    wg_zero<CT>(nr, ni, P2L, ni);
-    wg_zero<CT>(ni, nr, M2P, nr);
-    if (threadIdx.x == 0) {
+    t_gemm(T, kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
+    t_gemm(T, kin, kr, ni, 1.0, nU, cap, true, M2P, nr, false, 1.0, t2, kr1);
+    t_copy(T, kr, kin, t1, cap, Ari, ni);
+    t_copy(T, kin, kr, t2, kr1, Air, nr);
+    t_copy(T, ni, kin, nU, cap, (double*)U_i, ni);
+    t_copy(T, ni, kin, nV, cap, (double*)V_i, ni);
+    t_zero(T, nr, ni, P2L, ni);
+    t_zero(T, ni, nr, M2P, nr);
+    if (T.gtid == 0) {
       P.kn[i] = kin;
       tr[0] = r5; tr[1] = r6; tr[2] = 0; tr[3] = 0; tr[4] = kin; tr[5] = 0;
       trr[4] = trr[5] = trr[6] = trr[7] = 0.0;
@@ -1014,6 +1020,11 @@ static void count_flops(aifmm_system& s, int l) {
   }
 }
 
+static bool team_off() {
+  const char* v = getenv("AIFMM_NO_TEAMS");
+  return v && *v && *v != '0';
+}
+
 static bool verbose() {
   const char* v = getenv("AIFMM_VERBOSE");
   return v && *v && *v != '0';
@@ -1097,6 +1108,28 @@ void factor_system(aifmm_system& s) {
     P.trace = d_tr.p;
     P.trace_ratio = d_trr.p;
     size_t rix = 0;
+    // compressions of a small round are spread over teams of G workgroups each (cooperative
+    // launch, so every team is co-resident); pivot positions and a reflector live in LDS
+    size_t shmem = (size_t)cap * sizeof(double) + (size_t)4 * cap * sizeof(int);
+    if (shmem > 160 * 1024) throw Error{AIFMM_ERR_CAPACITY, "box size too large for the compression kernel"};
+    if (shmem > 64 * 1024)
+      AIFMM_HIP(hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    int coop_max = 0;
+    {
+      int dev = 0, coop = 0, ncu = 0, per = 0;
+      AIFMM_HIP(hipGetDevice(&dev));
+      AIFMM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+      AIFMM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_compress, CT, shmem));
+      if (coop && !team_off()) coop_max = per * ncu;
+    }
+    DBuf<unsigned> d_ctr;
+    DBuf<Cand> d_part;
+    DBuf<int> d_abort;
+    d_ctr.alloc(std::max(1, maxcol));
+    d_part.alloc((size_t)std::max(1, maxcol) * 2 * 16);
+    d_abort.alloc(1);
+    d_abort.zero(st);
     hipEvent_t ev[4];
     for (auto& e : ev) AIFMM_HIP(hipEventCreate(&e));
     std::vector<std::pair<hipEvent_t, hipEvent_t>> sch_ev, cmp_ev;
@@ -1115,7 +1148,23 @@ void factor_system(aifmm_system& s) {
         const XformEntry* ex = d_xent.p + x_off[rix];
         auto ce = ev_pair(cmp_ev);
         AIFMM_HIP(hipEventRecord(ce.first, st));
-        hipLaunchKernelGGL(k_compress, dim3(ne), dim3(CT), (size_t)cap * sizeof(double), st, P, er, ne, ws.p, wsz, cap, s.tol, r_off[rix]);
+        int G = 1;
+        if (coop_max > 0 && ne > 0)
+          G = std::max(1, std::min({16, coop_max / ne, (int)((int64_t)2 * cap * cap / 49152)}));
+        if (G == 1) {
+          hipLaunchKernelGGL(k_compress, dim3(ne), dim3(CT), shmem, st, P, er, ne, ws.p, wsz, cap, s.tol, r_off[rix],
+                             1, d_ctr.p, d_part.p, d_abort.p);
+        } else {
+          AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * ne, st));
+          int64_t tb = r_off[rix];
+          double tol = s.tol;
+          Cand* partp = d_part.p;
+          unsigned* ctrp = d_ctr.p;
+          int* abortp = d_abort.p;
+          double* wsp = ws.p;
+          void* args[] = {&P, (void*)&er, &ne, &wsp, &wsz, &cap, &tol, &tb, &G, &ctrp, &partp, &abortp};
+          AIFMM_HIP(hipLaunchCooperativeKernel((const void*)k_compress, dim3(ne * G), dim3(CT), args, shmem, st));
+        }
         AIFMM_HIP(hipEventRecord(ce.second, st));
         int grid = std::min<int64_t>(XG, (int64_t)nx * maxblk);
         hipLaunchKernelGGL(k_row_xform, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p, sstride);
@@ -1137,6 +1186,8 @@ void factor_system(aifmm_system& s) {
     }
     lv.kfin = lv.d_k.download(st);
     AIFMM_HIP(hipStreamSynchronize(st));
+    if (d_abort.download(st)[0])
+      throw Error{AIFMM_ERR_DEVICE, "level " + std::to_string(l) + ": a compression team barrier timed out"};
     for (auto& pr : sch_ev) {
       float ms = 0;
       AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));

@@ -1,0 +1,293 @@
+// A "team" of G co-resident workgroups (NT threads each) working on one dense task, with
+// team-wide barriers through a counter in device memory.  G == 1 is a plain workgroup and its
+// barrier is __syncthreads().  Team routines distribute their work over the G * NT team
+// threads and end with a team barrier, so results are visible to every member on return.
+//
+// The arithmetic of every output element is done by one thread in the same order as the
+// single-workgroup routines of dense_wg.hpp, so results do not depend on G.
+#pragma once
+#include "dense_wg.hpp"
+
+namespace aifmm {
+
+// Candidate of one team member for the pivot rule of t_cpqr: its largest trailing norm mv,
+// the lowest position p among its columns within a relative 1e-11 of mv, and that column's
+// norm nv (p = INT_MAX when the member has no live column).
+struct Cand {
+  double mv, nv;
+  int p, pad;
+};
+
+template <int NT>
+struct Team {
+  int member = 0, G = 1;      // this workgroup's index in the team, team size
+  int gtid = 0, GT = NT;      // team thread index and count
+  int cid = 0;                // column-interleaved team thread index: member + G * thread
+  unsigned* ctr = nullptr;    // barrier counter (zero at launch)
+  Cand* part = nullptr;       // 2 x G exchange slots (double-buffered)
+  int* abort = nullptr;       // set when a barrier waited too long; every later barrier returns
+  unsigned epoch = 0;
+  int slot = 0;
+
+  __device__ void init(int member_, int G_, unsigned* ctr_, Cand* part_, int* abort_) {
+    member = member_;
+    G = G_;
+    gtid = member * NT + (int)threadIdx.x;
+    GT = G * NT;
+    cid = member + G * (int)threadIdx.x;
+    ctr = ctr_;
+    part = part_;
+    abort = abort_;
+  }
+
+  // Wait for every member.  The workgroup barrier orders this workgroup's writes before thread
+  // 0's agent-scope release; thread 0's acquire after the wait makes the other members' writes
+  // visible to the whole workgroup.  The wait is bounded (a few seconds of polling): on expiry
+  // the abort flag is raised and the team falls through, so every workgroup still runs to its
+  // end and the host reports the failure.
+  __device__ void sync() {
+    __syncthreads();
+    if (G == 1) return;
+    if (threadIdx.x == 0) {
+      ++epoch;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      atomicAdd(ctr, 1u);
+      unsigned target = epoch * (unsigned)G;
+      unsigned spins = 0;
+      while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 24)) {
+          atomicExch(abort, 1);
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+  }
+
+  // Publish one value per member and return all G of them (the same array on every thread).
+  __device__ const Cand* exchange(const Cand& c) {
+    Cand* p = part + slot * G;
+    if (threadIdx.x == 0) p[member] = c;
+    sync();
+    slot ^= 1;
+    return p;
+  }
+
+  // Team-wide argmax (ties to the lowest index); the same value on every thread of the team.
+  __device__ ValIdx argmax(ValIdx x, ValIdx* shv) {
+    ValIdx r = wg_argmax<NT>(x, shv);
+    if (G == 1) return r;
+    const Cand* all = exchange(Cand{r.v, 0.0, r.i, 0});
+    ValIdx b{-1.0, INT_MAX};
+    for (int q = 0; q < G; ++q) {
+      ValIdx c{all[q].mv, all[q].p};
+      if (vi_better(c, b)) b = c;
+    }
+    return b;
+  }
+};
+
+template <int NT>
+__device__ inline void t_copy(Team<NT>& T, int M, int N, const double* __restrict__ A, int lda, double* __restrict__ C,
+                              int ldc) {
+  for (int idx = T.gtid; idx < M * N; idx += T.GT) {
+    int r = idx / N, c = idx - r * N;
+    C[(size_t)r * ldc + c] = A[(size_t)r * lda + c];
+  }
+  T.sync();
+}
+template <int NT>
+__device__ inline void t_zero(Team<NT>& T, int M, int N, double* C, int ldc) {
+  for (int idx = T.gtid; idx < M * N; idx += T.GT) {
+    int r = idx / N, c = idx - r * N;
+    C[(size_t)r * ldc + c] = 0.0;
+  }
+  T.sync();
+}
+// C = alpha op(A) op(B) + beta C, each element accumulated in ascending k (as wg_gemm).
+template <int NT>
+__device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
+                              bool ta, const double* __restrict__ B, int ldb, bool tb, double beta, double* C, int ldc) {
+  for (int idx = T.gtid; idx < M * N; idx += T.GT) {
+    int r = idx / N, c = idx - r * N;
+    const double* pa = ta ? A + r : A + (size_t)r * lda;
+    const double* pb = tb ? B + (size_t)c * ldb : B + c;
+    size_t sa = ta ? (size_t)lda : 1, sb = tb ? 1 : (size_t)ldb;
+    double acc = seq_dot(K, [&](int k) { return pa[k * sa]; }, [&](int k) { return pb[k * sb]; }, 0.0);
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * C[(size_t)r * ldc + c];
+    C[(size_t)r * ldc + c] = v;
+  }
+  T.sync();
+}
+
+// Householder QR with column pivoting of the m x n row-major M, truncated as wg_cpqr (same
+// pivot rule, same operation order per column).  Columns stay where they are: column c is
+// owned by member c mod G (columns interleave across members), and its pivot-order position is tracked in pos / at (LDS of
+// every member, n entries each) — a swap of positions s and p is exactly the column exchange
+// of wg_cpqr.  The pivot column is read by every member to form the reflector (vsh: m
+// doubles of LDS).  Reflector s is written to column s of V (ldv), its scale to tau[s]; nrm
+// (device memory, n) holds each column's trailing norm.  M's pivot columns are left as they
+// were when chosen (R is not formed).  Returns the rank; ratio (if given) receives the two
+// decision ratios of wg_cpqr.
+template <int NT>
+__device__ inline int t_cpqr(Team<NT>& T, int m, int n, double* M, int ldm, double tol, double* V, int ldv, double* tau,
+                             double* nrm, ValIdx* shv, double* vsh, int* pos, int* at, double* ratio = nullptr) {
+  double kept = 0.0, next = 0.0;
+  int smax = m < n ? m : n;
+  double r11 = 0.0;
+  for (int c = T.cid; c < n; c += T.GT) {
+    const double* col = M + c;
+    double t = seq_dot(m, [&](int i) { return col[(size_t)i * ldm]; }, [&](int i) { return col[(size_t)i * ldm]; }, 0.0);
+    nrm[c] = sqrt(t);
+  }
+  for (int c = threadIdx.x; c < n; c += NT) {
+    pos[c] = c;
+    at[c] = c;
+  }
+  __syncthreads();
+  int s = 0;
+  for (; s < smax; ++s) {
+    // largest live norm, then the lowest position within a relative 1e-11 of it: first per
+    // workgroup, then across the team in one exchange (a second one only when a member's
+    // candidate falls between its own and the team's threshold)
+    ValIdx mx{-1.0, INT_MAX};
+    for (int c = T.cid; c < n; c += T.GT)
+      if (pos[c] >= s) {
+        ValIdx x{nrm[c], pos[c]};
+        if (vi_better(x, mx)) mx = x;
+      }
+    mx = wg_argmax<NT>(mx, shv);
+    double lthr = mx.v * (1.0 - 1e-11);
+    ValIdx lb{-1.0, INT_MAX};
+    for (int c = T.cid; c < n; c += T.GT)
+      if (pos[c] >= s && nrm[c] >= lthr && pos[c] < lb.i) lb = ValIdx{0.0, pos[c]};
+    lb = wg_argmax<NT>(lb, shv);
+    int pp = lb.i;
+    if (T.G > 1) {
+      double lnv = lb.i != INT_MAX ? nrm[at[lb.i]] : -1.0;
+      const Cand* all = T.exchange(Cand{mx.v, lnv, lb.i, 0});
+      double mstar = -1.0;
+      for (int q = 0; q < T.G; ++q) mstar = fmax(mstar, all[q].mv);
+      double thr = mstar * (1.0 - 1e-11);
+      bool amb = false;
+      pp = INT_MAX;
+      for (int q = 0; q < T.G; ++q)
+        if (all[q].p != INT_MAX && all[q].mv >= thr) {
+          if (all[q].nv >= thr) pp = min(pp, all[q].p);
+          else amb = true;
+        }
+      if (amb) {
+        ValIdx b2{-1.0, INT_MAX};
+        for (int c = T.cid; c < n; c += T.GT)
+          if (pos[c] >= s && nrm[c] >= thr && pos[c] < b2.i) b2 = ValIdx{0.0, pos[c]};
+        pp = T.argmax(b2, shv).i;
+      }
+    }
+    const int cp = at[pp];
+    const double bv = nrm[cp];
+    if (s == 0) {
+      r11 = bv;
+      if (r11 == 0.0) break;
+    } else if (bv <= tol * r11) {
+      next = bv / (tol * r11);
+      break;
+    }
+    kept = bv / (tol * r11);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int cs = at[s];
+      at[s] = cp;
+      at[pp] = cs;
+      pos[cp] = s;
+      pos[cs] = pp;
+    }
+    double x0 = M[(size_t)s * ldm + cp];
+    double beta = x0 >= 0.0 ? -bv : bv;
+    double scale = x0 - beta;
+    double tv = (beta - x0) / beta;
+    for (int i = threadIdx.x; i < m; i += NT) {
+      double v = 0.0;
+      if (i == s) v = 1.0;
+      else if (i > s) v = M[(size_t)i * ldm + cp] / scale;
+      vsh[i] = v;
+      if (T.member == 0) V[(size_t)i * ldv + s] = v;
+    }
+    if (T.member == 0 && threadIdx.x == 0) tau[s] = tv;
+    __syncthreads();
+    const int len = m - s;
+    const double* vv = vsh + s;
+    for (int c = T.cid; c < n; c += T.GT) {
+      if (pos[c] <= s) continue;
+      double* col = M + (size_t)s * ldm + c;
+      double w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldm]; }, 0.0);
+      w *= tv;
+      col[0] = fma(-w, vv[0], col[0]);
+      double t = 0.0;
+      int i = 1;
+      for (; i + 8 <= len; i += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldm];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = fma(-w, vv[i + u], a[u]);
+          col[(size_t)(i + u) * ldm] = a[u];
+          t = fma(a[u], a[u], t);
+        }
+      }
+      for (; i < len; ++i) {
+        double a = fma(-w, vv[i], col[(size_t)i * ldm]);
+        col[(size_t)i * ldm] = a;
+        t = fma(a, a, t);
+      }
+      nrm[c] = sqrt(t);
+    }
+  }
+  if (ratio && T.gtid == 0) {
+    ratio[0] = kept;
+    ratio[1] = next;
+  }
+  T.sync();
+  return s;
+}
+
+// Columns c0 .. q-1 of Q = H_0 ... H_{rank-1} [I; 0] (m x q, ldq), as wg_formq: every column is
+// formed by one team thread through all reflectors, so members only synchronise at the end.
+template <int NT>
+__device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const double* V, int ldv, const double* tau,
+                               double* Q, int ldq, double* vsh, int c0 = 0) {
+  for (int j = c0 + T.cid; j < q; j += T.GT)
+    for (int r = 0; r < m; ++r) Q[(size_t)r * ldq + j] = (r == j) ? 1.0 : 0.0;
+  for (int s = rank - 1; s >= 0; --s) {
+    double tv = tau[s];
+    __syncthreads();
+    for (int i = s + threadIdx.x; i < m; i += NT) vsh[i] = V[(size_t)i * ldv + s];
+    __syncthreads();
+    int len = m - s;
+    const double* vv = vsh + s;
+    int j0 = c0 > s ? c0 : s;
+    // a column is still e_j while s > j, so the reflector leaves it unchanged
+    for (int j = c0 + T.cid; j < q; j += T.GT) {
+      if (j < j0) continue;
+      double* col = Q + (size_t)s * ldq + j;
+      double w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldq]; }, 0.0);
+      w *= tv;
+      int i = 0;
+      for (; i + 8 <= len; i += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldq];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) col[(size_t)(i + u) * ldq] = fma(-w, vv[i + u], a[u]);
+      }
+      for (; i < len; ++i) col[(size_t)i * ldq] = fma(-w, vv[i], col[(size_t)i * ldq]);
+    }
+  }
+  T.sync();
+}
+
+}  // namespace aifmm
