@@ -30,6 +30,25 @@ FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
+def schur_traffic(config):
+    """HBM bytes per k_elim_schur launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    (profiles/k_elim_schur_c2_traffic.json), or None when they were taken on another workload or
+    on a different version of the kernel's source."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "k_elim_schur_c2_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2301_12704_amd", "csrc", "k_factor.hip")).read()
+    except OSError:
+        return None
+    s = src.find("constexpr int ST = ")
+    e = src.find("// New rows Z_b: (Z_b, cols(q))")
+    if config != "c2" or s < 0 or e < 0:
+        return None
+    if hashlib.sha256(src[s:e].encode()).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(cfg, n_sample=8192, depth=4):
     """The oracle (plain FP64 C++, one thread) on a bounded sample of the same workload:
     N=8192 points, depth 4, same kernel, tolerance, leaf size and 16 right-hand sides; its
@@ -146,7 +165,8 @@ def main():
         "direct_solves_per_s": round(nrhs / med("direct"), 3),
         "roofline": {"kernel": "k_elim_schur (Schur fill-in update)", "bound": bound,
                      "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4) if peak > 0 else None, "traffic": None,
+                     "frac": round(achieved / peak, 4) if peak > 0 else None,
+                     "traffic": schur_traffic(args.config), "traffic_unit": "bytes per launch",
                      "flops_per_launch": schur_flops / max(st["schur_launches"], 1),
                      "avg_launch_s": schur_s / max(st["schur_launches"], 1),
                      "arith_intensity": round(ai, 3)},

@@ -347,6 +347,7 @@ __device__ inline int wg_lu(int m, double* A, int lda, int* ipiv, ValIdx* shv) {
 // after it in step order; then the U12 rows are solved column by column and the trailing
 // matrix is updated in 64 x 64 tiles staged through LDS.  sh: LDS of at least
 // NB + 64 (NB + 1) + 65 NB doubles; ipv: NB ints of LDS.
+typedef double lu_dbl4 __attribute__((ext_vector_type(4)));
 template <int NB>
 __device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx* shv, double* sh, int* ipv) {
   constexpr int NT = WG;
@@ -426,16 +427,20 @@ __device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx
         if (t < nb) A[(size_t)(k0 + t) * lda + c] = u[t];
     }
     __syncthreads();
-    // A22 -= L21 U12, one fused multiply-add per step in ascending order, 64 x 64 tiles
+    // A22 -= L21 U12 in 64 x 64 tiles, each wave a 32 x 32 quarter as 2 x 2 FP64 MFMA 16x16x4
+    // blocks accumulating onto the current entries: an MFMA adds its four products one fused
+    // multiply-add at a time in ascending step order, as the unblocked update does
     const int rem = m - c1;
     const int tiles = (rem + 63) / 64;
-    const int ty = tid / 16, tx = tid % 16;
+    const int lane = tid % WAVE, wv = tid / WAVE;
+    const int wr = (wv / 2) * 32, wc = (wv % 2) * 32;
+    const int fr = lane % 16, fk = lane / 16;
     for (int tt = 0; tt < tiles * tiles; ++tt) {
       int r0 = c1 + (tt / tiles) * 64, cc0 = c1 + (tt % tiles) * 64;
       for (int idx = tid; idx < 64 * NB; idx += NT) {
         int r = idx / NB, t = idx - r * NB;
         int gr = r0 + r;
-        Ls[r * (NB + 1) + t] = (gr < m && t < nb) ? A[(size_t)gr * lda + k0 + t] : 0.0;
+        Ls[r * (NB + 1) + t] = (gr < m && t < nb) ? -A[(size_t)gr * lda + k0 + t] : 0.0;
       }
       for (int idx = tid; idx < NB * 64; idx += NT) {
         int t = idx / 64, c = idx - t * 64;
@@ -443,32 +448,34 @@ __device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx
         Us[t * 65 + c] = (gc < m && t < nb) ? A[(size_t)(k0 + t) * lda + gc] : 0.0;
       }
       __syncthreads();
-      double a[4][4];
+      lu_dbl4 acc[2][2];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          int gr = r0 + ty * 4 + x, gc = cc0 + tx * 4 + y;
-          a[x][y] = (gr < m && gc < m) ? A[(size_t)gr * lda + gc] : 0.0;
-        }
-      for (int t = 0; t < nb; ++t) {
-        double lv[4], uv[4];
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int x = 0; x < 4; ++x) lv[x] = -Ls[(ty * 4 + x) * (NB + 1) + t];
+          for (int q = 0; q < 4; ++q) {
+            int gr = r0 + wr + 16 * i + fk + 4 * q, gc = cc0 + wc + 16 * j + fr;
+            acc[i][j][q] = (gr < m && gc < m) ? A[(size_t)gr * lda + gc] : 0.0;
+          }
 #pragma unroll
-        for (int y = 0; y < 4; ++y) uv[y] = Us[t * 65 + tx * 4 + y];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) a[x][y] = fma(lv[x], uv[y], a[x][y]);
+      for (int k4 = 0; k4 < NB; k4 += 4) {
+        double a0 = Ls[(wr + fr) * (NB + 1) + k4 + fk], a1 = Ls[(wr + 16 + fr) * (NB + 1) + k4 + fk];
+        double b0 = Us[(k4 + fk) * 65 + wc + fr], b1 = Us[(k4 + fk) * 65 + wc + 16 + fr];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
       }
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          int gr = r0 + ty * 4 + x, gc = cc0 + tx * 4 + y;
-          if (gr < m && gc < m) A[(size_t)gr * lda + gc] = a[x][y];
-        }
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            int gr = r0 + wr + 16 * i + fk + 4 * q, gc = cc0 + wc + 16 * j + fr;
+            if (gr < m && gc < m) A[(size_t)gr * lda + gc] = acc[i][j][q];
+          }
       __syncthreads();
     }
   }

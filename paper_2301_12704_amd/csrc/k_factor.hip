@@ -58,6 +58,7 @@ struct LevelPtrs {
   const int64_t* m2m_off;
   const int* kP;
   const int64_t* tslot;
+  int* grc;          // per box 2 x 28 ints: row and column offsets of the coupled groups
   int Gmax;
   double* fslab;
   const int64_t* fLU;
@@ -328,6 +329,19 @@ __global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __re
   int C = 0;
   for (int g = 0; g < G; ++g) C += grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
   int ldw = C + n;
+  if (threadIdx.x == 0) {  // group offsets for the Schur update: rows (all but y_b's group), columns
+    int* rc = P.grc + (size_t)b * 56;
+    int ro = 0, co = 0;
+    for (int g = 0; g < G; ++g) {
+      int cd = grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
+      rc[g] = ro;
+      rc[28 + g] = co;
+      if (g < G - 1) ro += cd;
+      co += cd;
+    }
+    rc[G] = ro;
+    rc[28 + G] = co;
+  }
   const double* Kbb = P.slab + near_entry(P, b, b);
   const double* Ub = P.slab + P.U_off[b];
   const double* Vb = P.slab + P.V_off[b];
@@ -419,82 +433,124 @@ __global__ void __launch_bounds__(WG) k_elim_trsm(LevelPtrs P, const int* __rest
 }
 
 // Schur update of the coupled blocks: T[p, q] -= A[rows(p), x_b] W_x[:, cols(q)], with the
-// column y_b written (not accumulated): 64 x 64 output tile per workgroup, 4 x 4 per thread.
-constexpr int ST = 64, SK = 16;
+// column y_b written (not accumulated).  One ST x ST output tile per workgroup; each wave owns
+// an (ST/2) x (ST/2) quarter as BL x BL blocks of FP64 MFMA 16x16x4.  The MFMA adds its four
+// products to the accumulator one fused multiply-add at a time in ascending k, so every output
+// is the ascending-k fused multiply-add sum, exactly as the sequential product.  The tiles of
+// the next k chunk are loaded into registers while the current chunk is multiplied from LDS.
+constexpr int ST = 64, SK = 32, BL = ST / 32;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(WG) k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int tiles_c) {
   if (flag[0]) return;
   int b = boxes[blockIdx.y];
   int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
-  int n = P.n[b], k = P.k[b];
+  int n = P.n[b];
   __shared__ int rstart[28], cstart[28];
   __shared__ double As[ST][SK + 1];
   __shared__ double Bs[SK][ST + 1];
-  if (threadIdx.x == 0) {
-    int ro = 0, co = 0;
-    for (int g = 0; g < G; ++g) {
-      int cd = grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
-      rstart[g] = ro;
-      cstart[g] = co;
-      if (g < G - 1) ro += cd;
-      co += cd;
-    }
-    rstart[G] = ro;
-    cstart[G] = co;
-  }
+  const int* rc = P.grc + (size_t)b * 56;
+  if (threadIdx.x <= G) rstart[threadIdx.x] = rc[threadIdx.x];
+  else if (threadIdx.x >= 64 && threadIdx.x <= 64 + G) cstart[threadIdx.x - 64] = rc[28 + threadIdx.x - 64];
   __syncthreads();
   int R = rstart[G - 1], C = cstart[G];
-  int tr = blockIdx.x / tiles_c, tc = blockIdx.x - tr * tiles_c;
+  // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs, so workgroup x
+  // runs on XCD x % 8; each XCD takes a contiguous range of this box's tiles, walked in groups
+  // of SG tile rows column by column, so the A strips of a group and the W strip of a column
+  // stay in that XCD's L2 while they are reused.
+  int tiles_r = (R + ST - 1) / ST, tcn = (C + ST - 1) / ST;
+  int nt = tiles_r * tcn, per = (nt + 7) / 8;
+  int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (blockIdx.x >= 8 * per || t >= nt) return;
+  constexpr int SG = 8;
+  int grp = t / (SG * tcn), rem = t - grp * SG * tcn;
+  int gh = min(SG, tiles_r - grp * SG);
+  int tr = grp * SG + rem % gh, tc = rem / gh;
   int r0 = tr * ST, c0 = tc * ST;
-  if (r0 >= R || c0 >= C) return;
+  (void)tiles_c;
   int ldw = C + n;
   const double* Cb = P.fslab + P.fC[b];
   const double* W = P.fslab + P.fW[b];
-  int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-  double acc[4][4];
-  for (int a = 0; a < 4; ++a)
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-  for (int k0 = 0; k0 < n; k0 += SK) {
-    for (int idx = threadIdx.x; idx < ST * SK; idx += WG) {
-      int r = idx / SK, kk = idx - r * SK;
-      int gr = r0 + r, gk = k0 + kk;
-      As[r][kk] = (gr < R && gk < n) ? Cb[(size_t)gr * n + gk] : 0.0;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int wr = (wv / 2) * (ST / 2), wc = (wv % 2) * (ST / 2);
+  const int fr = lane % 16, fk = lane / 16;
+  dbl4 acc[BL][BL];
+#pragma unroll
+  for (int i = 0; i < BL; ++i)
+#pragma unroll
+    for (int j = 0; j < BL; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  constexpr int NA = ST * SK / WG, NBv = SK * ST / WG;
+  double ra[NA], rb[NBv];
+  // A chunk: row r = idx / SK, k = idx % SK; B chunk: k = idx / ST, column = idx % ST
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      int idx = threadIdx.x + u * WG;
+      int gr = r0 + idx / SK, gk = k0 + idx % SK;
+      ra[u] = (gr < R && gk < n) ? Cb[(size_t)gr * n + gk] : 0.0;
     }
-    for (int idx = threadIdx.x; idx < SK * ST; idx += WG) {
-      int kk = idx / ST, c = idx - kk * ST;
-      int gk = k0 + kk, gc = c0 + c;
-      Bs[kk][c] = (gk < n && gc < C) ? W[(size_t)gk * ldw + gc] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NBv; ++u) {
+      int idx = threadIdx.x + u * WG;
+      int gk = k0 + idx / ST, gc = c0 + idx % ST;
+      rb[u] = (gk < n && gc < C) ? W[(size_t)gk * ldw + gc] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < n; k0 += SK) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      int idx = threadIdx.x + u * WG;
+      As[idx / SK][idx % SK] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NBv; ++u) {
+      int idx = threadIdx.x + u * WG;
+      Bs[idx / ST][idx % ST] = rb[u];
     }
     __syncthreads();
-    for (int kk = 0; kk < SK; ++kk) {
-      double av[4], bv[4];
-      for (int a = 0; a < 4; ++a) av[a] = As[ty * 4 + a][kk];
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx * 4 + c];
-      for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 4; ++c) acc[a][c] = fma(av[a], bv[c], acc[a][c]);
+    if (k0 + SK < n) fetch(k0 + SK);
+#pragma unroll
+    for (int k4 = 0; k4 < SK; k4 += 4) {
+      double a[BL], bb[BL];
+#pragma unroll
+      for (int i = 0; i < BL; ++i) a[i] = As[wr + 16 * i + fr][k4 + fk];
+#pragma unroll
+      for (int j = 0; j < BL; ++j) bb[j] = Bs[k4 + fk][wc + 16 * j + fr];
+#pragma unroll
+      for (int i = 0; i < BL; ++i)
+#pragma unroll
+        for (int j = 0; j < BL; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   const int64_t* ts = P.tslot + (size_t)b * P.Gmax * P.Gmax;
-  for (int a = 0; a < 4; ++a) {
-    int r = r0 + ty * 4 + a;
-    if (r >= R) continue;
-    int gr = 0;
-    while (rstart[gr + 1] <= r) ++gr;
-    int lr = r - rstart[gr];
-    for (int c4 = 0; c4 < 4; ++c4) {
-      int c = c0 + tx * 4 + c4;
-      if (c >= C) continue;
-      int gc = 0;
-      while (cstart[gc + 1] <= c) ++gc;
-      int lc = c - cstart[gc];
-      int q = P.grp_box[g0 + gc];
-      double* T = P.slab + ts[gr * P.Gmax + gc];
-      size_t addr = (size_t)lr * P.n[q] + lc;
-      if (gc == G - 1) T[addr] = -acc[a][c4];
-      else T[addr] -= acc[a][c4];
-    }
+  // output (lane, q) of block (i, j): row wr + 16 i + lane / 16 + 4 q, column wc + 16 j + lane % 16
+#pragma unroll
+  for (int j = 0; j < BL; ++j) {
+    int c = c0 + wc + 16 * j + fr;
+    if (c >= C) continue;
+    int gc = 0;
+    while (cstart[gc + 1] <= c) ++gc;
+    int lc = c - cstart[gc];
+    int q = P.grp_box[g0 + gc];
+    int ldq = P.n[q];
+    bool last = gc == G - 1;
+#pragma unroll
+    for (int i = 0; i < BL; ++i)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        int r = r0 + wr + 16 * i + fk + 4 * qq;
+        if (r >= R) continue;
+        int gr = 0;
+        while (rstart[gr + 1] <= r) ++gr;
+        int lr = r - rstart[gr];
+        double* T = P.slab + ts[gr * P.Gmax + gc];
+        size_t addr = (size_t)lr * ldq + lc;
+        double v = acc[i][j][qq];
+        if (last) T[addr] = -v;
+        else T[addr] -= v;
+      }
   }
-  (void)k;
 }
 
 // New rows Z_b: (Z_b, cols(q)) = W_z[:, cols(q)] for every coupled column group.
@@ -799,6 +855,7 @@ static LevelPtrs ptrs(aifmm_system& s, int l) {
   P.fW = v.d_fW.p;
   P.fpiv = v.d_fpiv.p;
   P.fpiv_off = v.d_fpiv_off.p;
+  P.grc = v.d_grc.p;
   return P;
 }
 
@@ -880,6 +937,7 @@ static void activate_level(aifmm_system& s, int l) {
       }
   }
   lv.d_tslot.upload(ts, st);
+  lv.d_grc.alloc((size_t)nb * 56);
   // factor store
   lv.fLU.assign(nb, 0);
   lv.fPx.assign(nb, 0);
@@ -1177,9 +1235,10 @@ void factor_system(aifmm_system& s) {
       hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
       hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, WG), nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
       int tiles_c = cdiv(lv.Cmax, ST), tiles_r = cdiv(std::max(1, lv.Rmax), ST);
+      int tiles_x = 8 * cdiv((int64_t)tiles_r * tiles_c, 8);
       auto se = ev_pair(sch_ev);
       AIFMM_HIP(hipEventRecord(se.first, st));
-      hipLaunchKernelGGL(k_elim_schur, dim3(tiles_r * tiles_c, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
+      hipLaunchKernelGGL(k_elim_schur, dim3(tiles_x, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
       AIFMM_HIP(hipEventRecord(se.second, st));
       hipLaunchKernelGGL(k_elim_zrow, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
       launch_check("elimination");
@@ -1188,6 +1247,7 @@ void factor_system(aifmm_system& s) {
     AIFMM_HIP(hipStreamSynchronize(st));
     if (d_abort.download(st)[0])
       throw Error{AIFMM_ERR_DEVICE, "level " + std::to_string(l) + ": a compression team barrier timed out"};
+    double sch_before = s.stats.schur_kernel_s;
     for (auto& pr : sch_ev) {
       float ms = 0;
       AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
@@ -1224,7 +1284,14 @@ void factor_system(aifmm_system& s) {
     if (flag[0]) throw Error{AIFMM_ERR_SINGULAR, "singular self-block at level " + std::to_string(flag[2]) + " box " + std::to_string(flag[1])};
     for (int b = 0; b < lv.nb; ++b)
       if (lv.kfin[b] > lv.n[b]) throw Error{AIFMM_ERR_CAPACITY, "rank above box size"};
-    count_flops(s, l);
+    {
+      double f0 = s.stats.schur_flops;
+      count_flops(s, l);
+      if (verbose())
+        fprintf(stderr, "[aifmm] level %d Schur %.3e flop in %.4f s (%.2f TFLOP/s)\n", l, s.stats.schur_flops - f0,
+                s.stats.schur_kernel_s - sch_before,
+                (s.stats.schur_flops - f0) / std::max(1e-12, s.stats.schur_kernel_s - sch_before) * 1e-12);
+    }
     lv.xoff.assign(lv.nb + 1, 0);
     lv.koff.assign(lv.nb + 1, 0);
     for (int b = 0; b < lv.nb; ++b) {

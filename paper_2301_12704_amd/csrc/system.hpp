@@ -148,6 +148,7 @@ struct LevelDev {
   DBuf<int64_t> d_U_off, d_V_off, d_l2l_off, d_m2m_off;  // per box
   DBuf<int> d_kP;              // NNCA rank of the parent (columns of L2L / M2M), 0 at level 2
   DBuf<int64_t> d_tslot;       // per box: Gmax x Gmax target offsets (Schur scatter)
+  DBuf<int> d_grc;             // per box 2 x 28: row / column offsets of the coupled groups
   // factor store (kept for the solve)
   DBuf<double> fslab;
   DBuf<int64_t> d_fLU, d_fPx, d_fC, d_fW;  // per box offsets into fslab
