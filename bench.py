@@ -82,6 +82,86 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes": n, "copies": 5}))
 
 
+SERVE_SYSTEMS = [
+    # (d, N, kernel, tol): the served workload's resident systems, one of each kernel family
+    (2, 16384, ("exp", 1.0, 0.1), 1e-10),
+    (2, 65536, ("invmq", 1e-2, 1.0), 1e-8),
+    (2, 32768, ("exp", 0.5, 0.05), 1e-8),
+    (3, 8192, ("invmq", 8192 ** (-1.0 / 3.0), 1.0), 1e-6),
+]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def serve(A, n_req=200, rate=2000.0, seed=5999):
+    """Served form: the resident systems above answer a Poisson stream of requests (rate per
+    second, nrhs ~ U{1..64}, system ~ uniform), each solved to relative residual 1e-10 by
+    FGMRES preconditioned by its factorization, with continuous per-system batching.  Latency
+    is submission to completion.  The plain comparison solves the first requests one at a time
+    with the same factors and FGMRES, without a server."""
+    import threading
+    systems = []
+    t0 = time.perf_counter()
+    for q, (d, n, kern, tol) in enumerate(SERVE_SYSTEMS):
+        pts, _ = I.points_and_rhs(n, d, 1, 5001 + q)
+        s = A.System(pts, kern, tol, 64, 0)
+        s.factor()
+        systems.append(s)
+        log(f"served system {q} ({d}D N={n}) factored at {time.perf_counter() - t0:.1f} s")
+    setup = time.perf_counter() - t0
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n_req)
+    which = rng.integers(0, len(systems), n_req)
+    nrhs = rng.integers(1, 65, n_req)
+    rhs = [np.asfortranarray(rng.standard_normal((systems[w].N, k))) for w, k in zip(which, nrhs)]
+    # plain form on the same requests (the first few, one at a time)
+    n_plain = 12
+    tp = time.perf_counter()
+    for q in range(n_plain):
+        systems[which[q]].gmres(rhs[q], rtol=1e-10, restart=30, maxit=500)
+    t_plain = time.perf_counter() - tp
+    log(f"plain form: {n_plain} requests one at a time in {t_plain:.2f} s")
+    plain_rate = float(np.sum(nrhs[:n_plain])) / t_plain
+    srv = A.Server(systems, rtol=1e-10, max_cols=64)
+    tickets = [None] * n_req
+    results = [None] * n_req
+
+    def waiter():
+        for q in range(n_req):
+            while tickets[q] is None:
+                time.sleep(1e-4)
+            results[q] = srv.wait(tickets[q])
+            if (q + 1) % 25 == 0:
+                log(f"served {q + 1} / {n_req} requests")
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    ts = time.perf_counter()
+    due = ts
+    for q in range(n_req):
+        due += gaps[q]
+        while time.perf_counter() < due:
+            pass
+        tickets[q] = srv.submit(int(which[q]), rhs[q])
+    th.join()
+    wall = time.perf_counter() - ts
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r[1] for r in results])
+    worst = max(float(np.max(r[4])) for r in results)
+    out = {"systems": [f"{d}D N={n} {k[0]} tol {t}" for d, n, k, t in SERVE_SYSTEMS], "requests": n_req,
+           "rate_per_s": rate, "rhs_total": int(np.sum(nrhs)), "wall_s": round(wall, 3),
+           "solves_per_s": round(float(np.sum(nrhs)) / wall, 2), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+           "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "batches": st["batches"],
+           "mean_batch_requests": round(st["requests"] / max(1, st["batches"]), 2), "max_relres": worst,
+           "plain_solves_per_s": round(plain_rate, 2), "setup_s": round(setup, 2)}
+    for s in systems:
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +170,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a fill and five plain device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -173,6 +254,8 @@ def main():
         "compress_kernel_s": round(st["compress_kernel_s"], 4),
         "schur_kernel_s": round(schur_s, 5),
     }
+    if not args.no_serve:
+        out["served"] = serve(A)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))

@@ -141,6 +141,40 @@ const char* aifmm_last_error(const aifmm_system* s);
 /* Free every resource of the system; NULL is accepted. */
 void aifmm_destroy(aifmm_system* s);
 
+/* ---- Serving: resident factorizations, continuously batched solve requests ----------------
+ * The factorization does not depend on the right-hand side (Sec. 3.4: the solve reuses the
+ * stored factors), so factored systems stay on the device and answer any number of requests.
+ * Each system gets a worker thread and a stream of its own (its previous stream is restored by
+ * aifmm_server_destroy); requests for a system that arrive while a batch of it runs are merged,
+ * FIFO and up to max_cols right-hand sides, into its next batch; batches of different systems
+ * run concurrently.  A batch is admitted when its device workspace (about N x cols x 8 bytes x
+ * (8 + 60 when rtol > 0)) fits in hbm_budget next to the running ones (0 = 90% of the free
+ * device memory at creation; a batch alone is always admitted).  rtol > 0 solves every
+ * request to that relative residual with flexible GMRES(30) preconditioned by the factors
+ * (aifmm_gmres); rtol = 0 uses the direct solve (aifmm_solve).  While served, the systems
+ * must not be used through other calls.
+ * Errors: AIFMM_ERR_ARG (NULL, nsys <= 0, a system listed twice, max_cols <= 0, rtol < 0),
+ * AIFMM_ERR_STATE (a system not factored), AIFMM_ERR_DEVICE (stream creation failed). */
+typedef struct aifmm_server aifmm_server;
+aifmm_status aifmm_server_create(aifmm_system* const* systems, int32_t nsys, size_t hbm_budget, double rtol,
+                                 int32_t max_cols, aifmm_server** out);
+/* Queue a request: b is N x nrhs column-major in the system's original point order, host
+ * memory, copied before the call returns (1 <= nrhs <= max_cols, ldb >= N).  *ticket
+ * identifies it for aifmm_server_wait.  AIFMM_ERR_STATE once the server is shutting down. */
+aifmm_status aifmm_server_submit(aifmm_server* srv, int32_t sys, const double* b, int64_t nrhs, int64_t ldb,
+                                 int64_t* ticket);
+/* Block until the request is done and copy its solution to x (host, N x nrhs, ldx >= N).
+ * *latency_s gets submission-to-completion seconds, *batch_cols the right-hand sides of the
+ * batch that served it, iters / relres (nrhs entries each) the GMRES iterations and final
+ * relative residuals (0 for direct solves); each may be NULL.  Returns the status of that
+ * batch's solve.  A ticket is waited for once, by one thread. */
+aifmm_status aifmm_server_wait(aifmm_server* srv, int64_t ticket, double* x, int64_t ldx, double* latency_s,
+                               int32_t* batch_cols, int32_t* iters, double* relres);
+/* Batches run so far, requests they served, and the peak device workspace admitted (bytes). */
+aifmm_status aifmm_server_stats(aifmm_server* srv, int64_t* batches, int64_t* requests, size_t* peak_bytes);
+/* Finish the queued requests, stop the workers and restore the systems' streams. */
+void aifmm_server_destroy(aifmm_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,15 @@ def lib():
         L.aifmm_last_error.argtypes = [vp]
         L.aifmm_last_error.restype = ctypes.c_char_p
         L.aifmm_destroy.argtypes = [vp]
+        L.aifmm_server_create.argtypes = [vp, i32, ctypes.c_size_t, d, i32, ctypes.POINTER(vp)]
+        L.aifmm_server_create.restype = ctypes.c_int
+        L.aifmm_server_submit.argtypes = [vp, i32, vp, i64, i64, ctypes.POINTER(i64)]
+        L.aifmm_server_submit.restype = ctypes.c_int
+        L.aifmm_server_wait.argtypes = [vp, i64, vp, i64, ctypes.POINTER(d), ctypes.POINTER(i32), vp, vp]
+        L.aifmm_server_wait.restype = ctypes.c_int
+        L.aifmm_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
+        L.aifmm_server_stats.restype = ctypes.c_int
+        L.aifmm_server_destroy.argtypes = [vp]
         for f in ["aifmm_options_default", "aifmm_build", "aifmm_factor", "aifmm_solve", "aifmm_get_depth",
                   "aifmm_get_ranks", "aifmm_get_stats"]:
             getattr(L, f).restype = ctypes.c_int
@@ -190,3 +199,56 @@ class System:
         out = np.zeros(16)
         _check(lib().aifmm_get_stats(self._h, _ptr(out)), self._h)
         return dict(zip(STAT_NAMES, out[: len(STAT_NAMES)]))
+
+
+class Server:
+    """Resident factorizations answering solve requests with continuous per-system batching
+    (aifmm_server_*).  submit() copies the right-hand sides and returns a ticket; wait(ticket)
+    returns (x, latency_s, batch_cols, iters, relres)."""
+
+    def __init__(self, systems, hbm_budget=0, rtol=1e-10, max_cols=64):
+        self._systems = list(systems)
+        arr = (ctypes.c_void_p * len(self._systems))(*[s._h for s in self._systems])
+        h = ctypes.c_void_p()
+        _check(lib().aifmm_server_create(arr, len(self._systems), int(hbm_budget), float(rtol), int(max_cols),
+                                         ctypes.byref(h)))
+        self._h = h
+        self._nrhs = {}
+
+    def submit(self, sys, b):
+        if not 0 <= int(sys) < len(self._systems):
+            raise AifmmError(1, f"no system {sys} on this server")
+        s = self._systems[sys]
+        b2 = np.asfortranarray(np.asarray(b, dtype=np.float64).reshape(s.N, -1))
+        t = ctypes.c_int64()
+        _check(lib().aifmm_server_submit(self._h, int(sys), _ptr(b2), b2.shape[1], s.N, ctypes.byref(t)))
+        self._nrhs[t.value] = (sys, b2.shape[1], np.shape(b))
+        return t.value
+
+    def wait(self, ticket):
+        sys, nr, shape = self._nrhs.pop(ticket)
+        n = self._systems[sys].N
+        x = np.zeros((n, nr), order="F")
+        lat = ctypes.c_double()
+        bc = ctypes.c_int32()
+        it = np.zeros(nr, np.int32)
+        rr = np.zeros(nr)
+        _check(lib().aifmm_server_wait(self._h, int(ticket), _ptr(x), n, ctypes.byref(lat), ctypes.byref(bc), _ptr(it),
+                                       _ptr(rr)))
+        return x.reshape(shape), lat.value, bc.value, it, rr
+
+    def stats(self):
+        b, r, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(lib().aifmm_server_stats(self._h, ctypes.byref(b), ctypes.byref(r), ctypes.byref(p)))
+        return {"batches": b.value, "requests": r.value, "peak_bytes": p.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().aifmm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaifmm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["plan.cpp", "k_build.hip", "k_factor.hip", "k_solve.hip", "k_gmres.hip", "api.cpp"]
+SOURCES = ["plan.cpp", "k_build.hip", "k_factor.hip", "k_solve.hip", "k_gmres.hip", "api.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

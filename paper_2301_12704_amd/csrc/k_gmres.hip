@@ -148,23 +148,34 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
   int nr = (int)nrhs, m = std::max(1, restart);
   int64_t N = s.N;
   size_t vec = (size_t)N * nr;
-  DBuf<double> bin, bt, xt, r, w, part, dalpha;
+  GmresCache& G = s.gc;
+  if (nr > G.nr_cap || m > G.m_cap) {
+    int nc = std::max(nr, G.nr_cap), mc = std::max(m, G.m_cap);
+    size_t v2 = (size_t)N * nc;
+    G.bt.alloc(v2);
+    G.xt.alloc(v2);
+    G.r.alloc(v2);
+    G.w.alloc(v2);
+    G.dalpha.alloc(nc);
+    G.V.clear();
+    G.Z.clear();
+    G.V.resize(mc + 1);
+    G.Z.resize(mc);
+    for (auto& v : G.V) v.alloc(v2);
+    for (auto& z : G.Z) z.alloc(v2);
+    G.nr_cap = nc;
+    G.m_cap = mc;
+  }
+  DBuf<double>&bt = G.bt, &xt = G.xt, &r = G.r, &w = G.w, &part = G.part, &dalpha = G.dalpha;
+  std::vector<DBuf<double>>&V = G.V, &Z = G.Z;
   const double* bs = b;
   if (!b_dev) {
-    bin.alloc((size_t)ldb * nr);
-    AIFMM_HIP(hipMemcpyAsync(bin.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
-    bs = bin.p;
+    if ((int64_t)G.bin.n < ldb * nr) G.bin.alloc((size_t)ldb * nr);
+    AIFMM_HIP(hipMemcpyAsync(G.bin.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
+    bs = G.bin.p;
   }
-  bt.alloc(vec);
-  xt.alloc(vec);
-  r.alloc(vec);
-  w.alloc(vec);
-  dalpha.alloc(nr);
   xt.zero(st);
   hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(vec, WG)), dim3(WG), 0, st, bs, ldb, s.d_perm.p, N, nr, bt.p);
-  std::vector<DBuf<double>> V(m + 1), Z(m);
-  for (auto& v : V) v.alloc(vec);
-  for (auto& z : Z) z.alloc(vec);
   std::vector<double> bnorm = coldots(s, bt.p, bt.p, nr, part);
   for (auto& v : bnorm) v = std::sqrt(v);
   std::vector<int> done(nr, 0), its(nr, 0);
@@ -266,9 +277,9 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
   if (x_dev) {
     hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(vec, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, x, ldx);
   } else {
-    DBuf<double> xo;
-    xo.alloc((size_t)ldx * nr);
-    xo.zero(st);
+    DBuf<double>& xo = G.xo;
+    if (xo.n < (size_t)ldx * nr) xo.alloc((size_t)ldx * nr);
+    if (ldx > N) AIFMM_HIP(hipMemsetAsync(xo.p, 0, sizeof(double) * ldx * nr, st));
     hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(vec, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, xo.p, ldx);
     AIFMM_HIP(hipMemcpyAsync(x, xo.p, sizeof(double) * ldx * nr, hipMemcpyDeviceToHost, st));
   }

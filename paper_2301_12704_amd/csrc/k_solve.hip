@@ -89,34 +89,54 @@ __global__ void __launch_bounds__(WG) k_gather_seg(const STask* __restrict__ seg
   for (int idx = threadIdx.x; idx < T.rows * nr; idx += WG) dst[idx] = src[idx];
 }
 
-// dense LU solve of the level-2 system, columns of the right-hand side in parallel
-__global__ void __launch_bounds__(WG) k_top_solve(const double* A, const int* ipiv, int K, double* X, int nr) {
-  for (int r = 0; r < K; ++r) {
-    int p = ipiv[r];
-    if (p != r)
-      for (int c = threadIdx.x; c < nr; c += WG) {
-        double t = X[(size_t)r * nr + c];
-        X[(size_t)r * nr + c] = X[(size_t)p * nr + c];
-        X[(size_t)p * nr + c] = t;
+// Top (level-2 multipole) system, Sec. 3.2: y = U^{-1} L^{-1} P rhs with the dense LU of the
+// top matrix.  The solves are blocked by 64 rows: one workgroup solves the block's triangle
+// (the block and its right-hand sides staged in LDS, one column per thread), then the rows
+// beyond the block are updated by a tiled product (k_rows_gemm), block after block.
+constexpr int TB = 64;
+__global__ void k_top_perm(const double* __restrict__ B, const int* __restrict__ perm, int K, int nr, double* X) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)K * nr) return;
+  int r = (int)(idx / nr), c = (int)(idx - (int64_t)r * nr);
+  X[idx] = B[(size_t)perm[r] * nr + c];
+}
+__global__ void __launch_bounds__(WG) k_top_diag(const double* __restrict__ A, int K, int b0, int bw, double* X, int nr,
+                                                 int lower) {
+  __shared__ double Ab[TB][TB + 1];
+  __shared__ double Xb[TB][TB + 1];
+  for (int idx = threadIdx.x; idx < bw * bw; idx += WG) {
+    int r = idx / bw, c = idx - r * bw;
+    Ab[r][c] = A[(size_t)(b0 + r) * K + b0 + c];
+  }
+  for (int c0 = 0; c0 < nr; c0 += TB) {
+    int nc = min(TB, nr - c0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < bw * nc; idx += WG) {
+      int r = idx / nc, c = idx - r * nc;
+      Xb[r][c] = X[(size_t)(b0 + r) * nr + c0 + c];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+      int c = threadIdx.x;
+      if (lower) {
+        for (int r = 1; r < bw; ++r) {
+          double v = Xb[r][c];
+          for (int t = 0; t < r; ++t) v = fma(-Ab[r][t], Xb[t][c], v);
+          Xb[r][c] = v;
+        }
+      } else {
+        for (int r = bw - 1; r >= 0; --r) {
+          double v = Xb[r][c];
+          for (int t = r + 1; t < bw; ++t) v = fma(-Ab[r][t], Xb[t][c], v);
+          Xb[r][c] = v / Ab[r][r];
+        }
       }
-    __syncthreads();
-  }
-  // forward: x_r -= L[r, 0:r] x   (column-oriented updates)
-  for (int t = 0; t < K; ++t) {
-    for (int idx = threadIdx.x; idx < (K - t - 1) * nr; idx += WG) {
-      int r = t + 1 + idx / nr, c = idx % nr;
-      X[(size_t)r * nr + c] -= A[(size_t)r * K + t] * X[(size_t)t * nr + c];
     }
     __syncthreads();
-  }
-  for (int t = K - 1; t >= 0; --t) {
-    for (int c = threadIdx.x; c < nr; c += WG) X[(size_t)t * nr + c] /= A[(size_t)t * K + t];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < t * nr; idx += WG) {
-      int r = idx / nr, c = idx % nr;
-      X[(size_t)r * nr + c] -= A[(size_t)r * K + t] * X[(size_t)t * nr + c];
+    for (int idx = threadIdx.x; idx < bw * nc; idx += WG) {
+      int r = idx / nc, c = idx - r * nc;
+      X[(size_t)(b0 + r) * nr + c0 + c] = Xb[r][c];
     }
-    __syncthreads();
   }
 }
 
@@ -246,6 +266,48 @@ static void build_solve_plan(aifmm_system& s) {
     sl.bw.upload(bw, st);
     sl.gs.upload(gs, st);
   }
+  // top system: the row order of its LU pivoting and the block-update tiles
+  int K = s.Ktop;
+  if (K > 0) {
+    std::vector<int> piv = s.d_top_piv.download(st, K), perm(K);
+    for (int r = 0; r < K; ++r) perm[r] = r;
+    for (int r = 0; r < K; ++r) std::swap(perm[r], perm[piv[r]]);
+    sc.top_perm.upload(perm, st);
+    std::vector<STask> fw, bw;
+    sc.top_fw_off = {0};
+    sc.top_bw_off = {0};
+    int nblk = (K + TB - 1) / TB;
+    for (int bi = 0; bi < nblk; ++bi) {  // forward: rows below block bi
+      int b0 = bi * TB, w = std::min(TB, K - b0);
+      for (int r0 = b0 + w; r0 < K; r0 += TB) {
+        STask t{};
+        t.a = (int64_t)r0 * K + b0;
+        t.lda = K;
+        t.K = w;
+        t.rows = std::min(TB, K - r0);
+        t.b = b0;
+        t.y = r0;
+        fw.push_back(t);
+      }
+      sc.top_fw_off.push_back((int)fw.size());
+    }
+    for (int bi = nblk - 1; bi >= 0; --bi) {  // backward: rows above block bi
+      int b0 = bi * TB, w = std::min(TB, K - b0);
+      for (int r0 = 0; r0 < b0; r0 += TB) {
+        STask t{};
+        t.a = (int64_t)r0 * K + b0;
+        t.lda = K;
+        t.K = w;
+        t.rows = std::min(TB, b0 - r0);
+        t.b = b0;
+        t.y = r0;
+        bw.push_back(t);
+      }
+      sc.top_bw_off.push_back((int)bw.size());
+    }
+    sc.top_fw.upload(fw, st);
+    sc.top_bw.upload(bw, st);
+  }
   sc.nr_cap = 0;
   sc.built = true;
 }
@@ -316,8 +378,22 @@ void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x) {
   launch_check("forward sweep");
   // level-2 multipoles: y^{(2)} = Top^{-1} rhs(Z^{(2)})
   if (s.Ktop > 0) {
-    AIFMM_HIP(hipMemcpyAsync(sc.X[1].p, sc.R[1].p, sizeof(double) * s.Ktop * nr, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_top_solve, dim3(1), dim3(WG), 0, st, s.d_top.p, s.d_top_piv.p, s.Ktop, sc.X[1].p, nr);
+    int K = s.Ktop, nblk = (K + TB - 1) / TB;
+    double* Xt = sc.X[1].p;
+    hipLaunchKernelGGL(k_top_perm, dim3(cdiv((int64_t)K * nr, WG)), dim3(WG), 0, st, sc.R[1].p, sc.top_perm.p, K, nr, Xt);
+    for (int bi = 0; bi < nblk; ++bi) {
+      int b0 = bi * TB, w = std::min(TB, K - b0);
+      hipLaunchKernelGGL(k_top_diag, dim3(1), dim3(WG), 0, st, s.d_top.p, K, b0, w, Xt, nr, 1);
+      launch_rows<1>(sc.top_fw_off[bi + 1] - sc.top_fw_off[bi], sc.top_fw.p + sc.top_fw_off[bi], s.d_top.p, Xt, Xt,
+                     nullptr, nullptr, nr, st);
+    }
+    for (int q = 0; q < nblk; ++q) {
+      int bi = nblk - 1 - q;
+      int b0 = bi * TB, w = std::min(TB, K - b0);
+      hipLaunchKernelGGL(k_top_diag, dim3(1), dim3(WG), 0, st, s.d_top.p, K, b0, w, Xt, nr, 0);
+      launch_rows<1>(sc.top_bw_off[q + 1] - sc.top_bw_off[q], sc.top_bw.p + sc.top_bw_off[q], s.d_top.p, Xt, Xt,
+                     nullptr, nullptr, nr, st);
+    }
   }
   for (int l = 2; l <= L; ++l) {
     LevelDev& lv = s.lev[l];
@@ -342,25 +418,25 @@ void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
   hipStream_t st = s.stream;
   int nr = (int)nrhs;
   int64_t N = s.N;
-  DBuf<double> bdev, rt, xt;
+  // staging buffers are the system's (kept across calls)
+  GmresCache& G = s.gc;
+  if ((int64_t)G.bt.n < N * nr) G.bt.alloc((size_t)N * nr);
+  if ((int64_t)G.xt.n < N * nr) G.xt.alloc((size_t)N * nr);
   const double* bsrc = b;
   if (!b_dev) {
-    bdev.alloc((size_t)ldb * nr);
-    AIFMM_HIP(hipMemcpyAsync(bdev.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
-    bsrc = bdev.p;
+    if ((int64_t)G.bin.n < ldb * nr) G.bin.alloc((size_t)ldb * nr);
+    AIFMM_HIP(hipMemcpyAsync(G.bin.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
+    bsrc = G.bin.p;
   }
-  rt.alloc((size_t)N * nr);
-  xt.alloc((size_t)N * nr);
-  hipLaunchKernelGGL(k_perm_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, bsrc, ldb, s.d_perm.p, N, nr, rt.p);
-  solve_tree(s, rt.p, nr, xt.p);
+  hipLaunchKernelGGL(k_perm_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, bsrc, ldb, s.d_perm.p, N, nr, G.bt.p);
+  solve_tree(s, G.bt.p, nr, G.xt.p);
   if (x_dev) {
-    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, x, ldx);
+    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, G.xt.p, s.d_perm.p, N, nr, x, ldx);
   } else {
-    DBuf<double> xd;
-    xd.alloc((size_t)ldx * nr);
-    xd.zero(st);
-    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, xd.p, ldx);
-    AIFMM_HIP(hipMemcpyAsync(x, xd.p, sizeof(double) * ldx * nr, hipMemcpyDeviceToHost, st));
+    if ((int64_t)G.xo.n < ldx * nr) G.xo.alloc((size_t)ldx * nr);
+    if (ldx > N) AIFMM_HIP(hipMemsetAsync(G.xo.p, 0, sizeof(double) * ldx * nr, st));
+    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, G.xt.p, s.d_perm.p, N, nr, G.xo.p, ldx);
+    AIFMM_HIP(hipMemcpyAsync(x, G.xo.p, sizeof(double) * ldx * nr, hipMemcpyDeviceToHost, st));
   }
   AIFMM_HIP(hipStreamSynchronize(st));
   launch_check("solve");

@@ -185,9 +185,23 @@ struct SolveLevel {
 struct SolveCache {
   bool built = false;
   int nr_cap = 0;
+  // blocked triangular solves of the top system: row permutation of its LU, and the update
+  // tiles of every 64-row block step (forward below the block, backward above it)
+  DBuf<int> top_perm;
+  DBuf<STask> top_fw, top_bw;
+  std::vector<int> top_fw_off, top_bw_off;
   std::vector<SolveLevel> lev;
   std::vector<DBuf<double>> R, X, W;
   DBuf<double> G;
+};
+
+// FGMRES workspace kept across calls (grown to the largest right-hand-side count seen), so a
+// served system allocates nothing per request once warm.
+struct GmresCache {
+  int nr_cap = 0, m_cap = 0;
+  int64_t ld_cap = 0;
+  DBuf<double> bin, bt, xt, r, w, part, dalpha, xo;
+  std::vector<DBuf<double>> V, Z;
 };
 
 struct Stats {
@@ -224,6 +238,7 @@ struct aifmm_system {
   aifmm::DBuf<int> d_rounds;      // scratch upload area for round lists
   aifmm::Stats stats;
   aifmm::SolveCache sc;           // solve task lists and buffers (rebuilt after every factor)
+  aifmm::GmresCache gc;           // FGMRES vectors
   std::vector<aifmm::TraceRec> trace;
   size_t device_bytes = 0;
 };

@@ -53,3 +53,18 @@ def test_argument_errors_without_device(lib):
     assert L.aifmm_solve(None, None, 1, 1, None, 1) == 1
     assert "NULL" in L.aifmm_last_error(None).decode() or L.aifmm_last_error(None)
     L.aifmm_destroy(None)
+
+
+def test_server_argument_errors_without_device(lib):
+    import paper_2301_12704_amd as A
+    L = A.lib()
+    h = ctypes.c_void_p()
+    assert L.aifmm_server_create(None, 1, 0, 0.0, 8, ctypes.byref(h)) == 1
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.aifmm_server_create(arr, 1, 0, 0.0, 8, ctypes.byref(h)) == 1
+    assert L.aifmm_server_create(arr, 0, 0, 0.0, 8, ctypes.byref(h)) == 1
+    t = ctypes.c_int64()
+    assert L.aifmm_server_submit(None, 0, None, 1, 1, ctypes.byref(t)) == 1
+    assert L.aifmm_server_wait(None, 1, None, 1, None, None, None, None) == 1
+    assert L.aifmm_server_stats(None, None, None, None) == 1
+    L.aifmm_server_destroy(None)
