@@ -61,17 +61,24 @@ typedef struct {
   double shift;  /* added on the diagonal */
 } aifmm_kernel;
 
+/* Arithmetic of the Schur fill-in updates and of the compressions (RRQRs, bases, basis
+ * changes).  The block store, the NNCA, the pivot-block LU, the solves, the matvec and GMRES
+ * are FP64 in both.  AIFMM_FP32 is the precision form: an approximate factorization used as
+ * the preconditioner of FP64 GMRES (Sec. 4, Exp. 5 uses AIFMM as a preconditioner). */
+typedef enum { AIFMM_FP64 = 0, AIFMM_FP32 = 1 } aifmm_precision;
+
 typedef struct {
   int32_t dim;         /* 2 or 3 */
   int32_t leaf_size;   /* n_max: mean points per leaf used by the depth rule (default 64) */
   int32_t depth;       /* 0: L = max(2, ceil(log_{2^d}(N / leaf_size))), else the tree depth */
   int32_t device;      /* HIP device ordinal */
   void* stream;        /* hipStream_t, NULL = default stream */
+  int32_t prec;        /* aifmm_precision (default AIFMM_FP64) */
 } aifmm_options;
 
 typedef struct aifmm_system aifmm_system;
 
-/* Fill *opt with defaults (dim 2, leaf 64, depth auto, device 0, default stream). */
+/* Fill *opt with defaults (dim 2, leaf 64, depth auto, device 0, default stream, FP64). */
 aifmm_status aifmm_options_default(aifmm_options* opt);
 
 /* Build the tree (Sec. 2.1), neighbour and interaction lists (Sec. 2.2, eta = sqrt(d)), the

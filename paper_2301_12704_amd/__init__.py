@@ -30,7 +30,7 @@ class _Kernel(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("prec", ctypes.c_int32)]
 
 
 _lib = None
@@ -99,7 +99,7 @@ def _ptr(a):
 class System:
     """One N-body system A x = b, A_ij = kappa(|p_i - p_j|) + shift delta_ij (aifmm_build)."""
 
-    def __init__(self, points, kernel, tol, leaf_size=64, depth=0, device=0, stream=None):
+    def __init__(self, points, kernel, tol, leaf_size=64, depth=0, device=0, stream=None, precision="fp64"):
         self._h = None
         if hasattr(points, "data_ptr"):
             pts = points.contiguous()
@@ -113,6 +113,7 @@ class System:
         _check(lib().aifmm_options_default(ctypes.byref(opt)))
         opt.dim, opt.leaf_size, opt.depth, opt.device = d, leaf_size, depth, device
         opt.stream = stream
+        opt.prec = {"fp64": 0, "fp32": 1}[precision]
         k = _Kernel(KERNELS[kernel[0]], float(kernel[1]), float(kernel[2]))
         h = ctypes.c_void_p()
         _check(lib().aifmm_build(_ptr(pts), n, k, float(tol), ctypes.byref(opt), ctypes.byref(h)))

@@ -51,6 +51,7 @@ aifmm_status aifmm_options_default(aifmm_options* opt) {
   opt->depth = 0;
   opt->device = 0;
   opt->stream = nullptr;
+  opt->prec = AIFMM_FP64;
   return AIFMM_OK;
 }
 
@@ -66,6 +67,7 @@ aifmm_status aifmm_build(const double* points, int64_t n, aifmm_kernel kernel, d
   if (o.leaf_size <= 0 || o.depth < 0 || o.depth > (o.dim == 2 ? 10 : 7))
     return fail(nullptr, AIFMM_ERR_ARG, "bad leaf_size or depth");
   if (kernel.kind != AIFMM_K_EXP && kernel.kind != AIFMM_K_INVMQ) return fail(nullptr, AIFMM_ERR_ARG, "bad kernel kind");
+  if (o.prec != AIFMM_FP64 && o.prec != AIFMM_FP32) return fail(nullptr, AIFMM_ERR_ARG, "bad precision");
   if (!(kernel.scale > 0.0) || !std::isfinite(kernel.shift)) return fail(nullptr, AIFMM_ERR_ARG, "bad kernel scale/shift");
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(nullptr, AIFMM_ERR_ARG, "tol must be in (0, 1)");
   if (n > (int64_t)1 << 30) return fail(nullptr, AIFMM_ERR_ARG, "n too large");
@@ -77,6 +79,7 @@ aifmm_status aifmm_build(const double* points, int64_t n, aifmm_kernel kernel, d
   s->device = o.device;
   s->stream = (hipStream_t)o.stream;
   s->tol = tol;
+  s->prec = o.prec;
   s->K = aifmm::KernelDesc{(int)kernel.kind, kernel.scale, kernel.shift};
   if (o.depth > 0) {
     s->L = o.depth;

@@ -126,29 +126,30 @@ __device__ inline double wg_sum(double x, double* sh) {
 }
 
 // C = alpha * op(A) op(B) + beta * C  (row-major; op = transpose when the flag is set).
-// Every output element accumulates its products in ascending k with fused multiply-adds.
-// C must not alias A or B.  beta == 0 never reads C.
-template <int NT = WG>
-__device__ inline void wg_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda, bool ta,
-                               const double* __restrict__ B, int ldb, bool tb, double beta, double* C, int ldc) {
+// Every output element accumulates its products in ascending k with fused multiply-adds, in
+// the precision of C (operands are converted on load).  C must not alias A or B.  beta == 0
+// never reads C.
+template <int NT = WG, class TA, class TB, class TC>
+__device__ inline void wg_gemm(int M, int N, int K, double alpha, const TA* __restrict__ A, int lda, bool ta,
+                               const TB* __restrict__ B, int ldb, bool tb, double beta, TC* C, int ldc) {
   for (int idx = threadIdx.x; idx < M * N; idx += NT) {
     int r = idx / N, c = idx - r * N;
-    const double* pa = ta ? A + r : A + (size_t)r * lda;
-    const double* pb = tb ? B + (size_t)c * ldb : B + c;
+    const TA* pa = ta ? A + r : A + (size_t)r * lda;
+    const TB* pb = tb ? B + (size_t)c * ldb : B + c;
     size_t sa = ta ? (size_t)lda : 1, sb = tb ? 1 : (size_t)ldb;
-    double acc = seq_dot(K, [&](int k) { return pa[k * sa]; }, [&](int k) { return pb[k * sb]; }, 0.0);
-    double v = alpha * acc;
-    if (beta != 0.0) v += beta * C[(size_t)r * ldc + c];
+    TC acc = seq_dot(K, [&](int k) { return (TC)pa[k * sa]; }, [&](int k) { return (TC)pb[k * sb]; }, (TC)0);
+    TC v = (TC)alpha * acc;
+    if (beta != 0.0) v += (TC)beta * C[(size_t)r * ldc + c];
     C[(size_t)r * ldc + c] = v;
   }
   __syncthreads();
 }
 
-template <int NT = WG>
-__device__ inline void wg_copy(int M, int N, const double* __restrict__ A, int lda, double* __restrict__ C, int ldc) {
+template <int NT = WG, class TS, class TD>
+__device__ inline void wg_copy(int M, int N, const TS* __restrict__ A, int lda, TD* __restrict__ C, int ldc) {
   for (int idx = threadIdx.x; idx < M * N; idx += NT) {
     int r = idx / N, c = idx - r * N;
-    C[(size_t)r * ldc + c] = A[(size_t)r * lda + c];
+    C[(size_t)r * ldc + c] = (TD)A[(size_t)r * lda + c];
   }
   __syncthreads();
 }

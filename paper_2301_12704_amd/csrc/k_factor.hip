@@ -75,6 +75,9 @@ struct LevelPtrs {
 // ------------------------------------------------------------------------------------------
 constexpr int CT = 512;
 
+// R: arithmetic of the compression (double, or float in the precision form); the block store
+// stays FP64 and operands are converted on load / store.
+template <class RT>
 __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* __restrict__ ent, int nent, double* ws,
                                                  int64_t wsz, int cap, double tol, int64_t tbase, int G,
                                                  unsigned* ctr, Cand* part, int* abort) {
@@ -86,28 +89,29 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   int* tr = P.trace + (tbase + e) * 6;
   double* trr = P.trace_ratio + (tbase + e) * 8;
   __shared__ ValIdx shv[CT / WAVE + 1];
-  extern __shared__ double vsh[];  // one reflector (cap doubles), then pivot positions (2 x 2cap ints)
+  extern __shared__ double shm[];  // one reflector (cap entries), then pivot positions (2 x 2cap ints)
+  RT* vsh = (RT*)shm;
   int* pos = (int*)(vsh + cap);
   int* at = pos + 2 * cap;
-  double* w = ws + (size_t)e * wsz;
+  RT* w = (RT*)(ws + (size_t)e * wsz);
   size_t c2 = (size_t)cap * cap;
-  double* Lb_i = w;
-  double* Rb_i = w + c2;
-  double* Lb_j = w + 2 * c2;
-  double* Rb_j = w + 3 * c2;
-  double* M = w + 4 * c2;        // cap x 2cap
-  double* V1 = w + 6 * c2;
-  double* V2 = w + 7 * c2;
-  double* V3 = w + 8 * c2;
-  double* V4 = w + 9 * c2;
-  double* nU = w + 10 * c2;      // new bases, cap x cap, ld cap
-  double* nV = w + 11 * c2;
-  double* nUj = w + 12 * c2;
-  double* nVj = w + 13 * c2;
-  double* t1 = w + 14 * c2;      // cap x 2cap
-  double* t2 = w + 16 * c2;
-  double* tau = w + 17 * c2;     // 4 * cap
-  double* nrm = tau + 4 * cap;   // 2 * cap
+  RT* Lb_i = w;
+  RT* Rb_i = w + c2;
+  RT* Lb_j = w + 2 * c2;
+  RT* Rb_j = w + 3 * c2;
+  RT* M = w + 4 * c2;        // cap x 2cap
+  RT* V1 = w + 6 * c2;
+  RT* V2 = w + 7 * c2;
+  RT* V3 = w + 8 * c2;
+  RT* V4 = w + 9 * c2;
+  RT* nU = w + 10 * c2;      // new bases, cap x cap, ld cap
+  RT* nV = w + 11 * c2;
+  RT* nUj = w + 12 * c2;
+  RT* nVj = w + 13 * c2;
+  RT* t1 = w + 14 * c2;      // cap x 2cap
+  RT* t2 = w + 16 * c2;
+  RT* tau = w + 17 * c2;     // 4 * cap
+  RT* nrm = tau + 4 * cap;   // 2 * cap
   const double* U_i = P.slab + P.U_off[R.i];
   const double* V_i = P.slab + P.V_off[R.i];
   int i = R.i, ni = P.n[i], ki = P.k[i];
@@ -235,9 +239,10 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
 
 // Left factor on the rows Z_x: every M2L block (x, c), c in IL(x), except the pair block,
 // and the L2L block become L_x * block.
+template <class RT>
 __global__ void __launch_bounds__(WG) k_row_xform(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
                                                   int64_t wsz, int cap, int maxblk, double* scratch, int64_t sstride) {
-  double* tmp = scratch + (size_t)blockIdx.x * sstride;
+  RT* tmp = (RT*)scratch + (size_t)blockIdx.x * sstride;
   size_t c2 = (size_t)cap * cap;
   int total = nx * maxblk;
   for (int task = blockIdx.x; task < total; task += gridDim.x) {
@@ -247,7 +252,7 @@ __global__ void __launch_bounds__(WG) k_row_xform(LevelPtrs P, const XformEntry*
     int nil = P.il_off[x + 1] - P.il_off[x];
     if (q > nil || (q == nil && P.l == 2)) continue;
     int kold = P.k[x], knew = P.kn[x];
-    const double* Lm = ws + (size_t)X.pair * wsz + (X.side ? 2 * c2 : 0);
+    const RT* Lm = (const RT*)(ws + (size_t)X.pair * wsz) + (X.side ? 2 * c2 : 0);
     double* B;
     int cols, ld;
     if (q < nil) {
@@ -269,9 +274,10 @@ __global__ void __launch_bounds__(WG) k_row_xform(LevelPtrs P, const XformEntry*
 
 // Right factor on the columns y_x: every M2L block (d, x), d in IL(x), except the pair
 // block, becomes block * R_x^*; the M2M block (stored transposed) becomes R_x * block.
+template <class RT>
 __global__ void __launch_bounds__(WG) k_col_xform(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
                                                   int64_t wsz, int cap, int maxblk, double* scratch, int64_t sstride) {
-  double* tmp = scratch + (size_t)blockIdx.x * sstride;
+  RT* tmp = (RT*)scratch + (size_t)blockIdx.x * sstride;
   size_t c2 = (size_t)cap * cap;
   int total = nx * maxblk;
   for (int task = blockIdx.x; task < total; task += gridDim.x) {
@@ -282,7 +288,7 @@ __global__ void __launch_bounds__(WG) k_col_xform(LevelPtrs P, const XformEntry*
     if (q > nil || (q == nil && P.l == 2)) continue;
     int kold = P.k[x], knew = P.kn[x];
     int kold1 = kold > 0 ? kold : 1;
-    const double* Rm = ws + (size_t)X.pair * wsz + (X.side ? 3 * c2 : c2);
+    const RT* Rm = (const RT*)(ws + (size_t)X.pair * wsz) + (X.side ? 3 * c2 : c2);
     if (q < nil) {
       int dbox = P.il[P.il_off[x] + q];
       if (dbox == X.skip) continue;
@@ -438,16 +444,26 @@ __global__ void __launch_bounds__(WG) k_elim_trsm(LevelPtrs P, const int* __rest
 // products to the accumulator one fused multiply-add at a time in ascending k, so every output
 // is the ascending-k fused multiply-add sum, exactly as the sequential product.  The tiles of
 // the next k chunk are loaded into registers while the current chunk is multiplied from LDS.
+// In the precision form (F32) the tiles are converted to FP32 and multiplied with FP32 MFMA
+// 16x16x4 (FP32 accumulation); the FP64 block store receives the FP32 products.
 constexpr int ST = 64, SK = 32, BL = ST / 32;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+__device__ inline dbl4 mfma16(double a, double b, dbl4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline flt4 mfma16(float a, float b, flt4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+template <bool F32> struct MfmaT { using T = double; using T4 = dbl4; };
+template <> struct MfmaT<true> { using T = float; using T4 = flt4; };
+template <bool F32>
 __global__ void __launch_bounds__(WG) k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int tiles_c) {
+  using TT = typename MfmaT<F32>::T;
+  using TT4 = typename MfmaT<F32>::T4;
   if (flag[0]) return;
   int b = boxes[blockIdx.y];
   int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
   int n = P.n[b];
   __shared__ int rstart[28], cstart[28];
-  __shared__ double As[ST][SK + 1];
-  __shared__ double Bs[SK][ST + 1];
+  __shared__ TT As[ST][SK + 1];
+  __shared__ TT Bs[SK][ST + 1];
   const int* rc = P.grc + (size_t)b * 56;
   if (threadIdx.x <= G) rstart[threadIdx.x] = rc[threadIdx.x];
   else if (threadIdx.x >= 64 && threadIdx.x <= 64 + G) cstart[threadIdx.x - 64] = rc[28 + threadIdx.x - 64];
@@ -473,26 +489,26 @@ __global__ void __launch_bounds__(WG) k_elim_schur(LevelPtrs P, const int* __res
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   const int wr = (wv / 2) * (ST / 2), wc = (wv % 2) * (ST / 2);
   const int fr = lane % 16, fk = lane / 16;
-  dbl4 acc[BL][BL];
+  TT4 acc[BL][BL];
 #pragma unroll
   for (int i = 0; i < BL; ++i)
 #pragma unroll
-    for (int j = 0; j < BL; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < BL; ++j) acc[i][j] = TT4{0, 0, 0, 0};
   constexpr int NA = ST * SK / WG, NBv = SK * ST / WG;
-  double ra[NA], rb[NBv];
+  TT ra[NA], rb[NBv];
   // A chunk: row r = idx / SK, k = idx % SK; B chunk: k = idx / ST, column = idx % ST
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       int idx = threadIdx.x + u * WG;
       int gr = r0 + idx / SK, gk = k0 + idx % SK;
-      ra[u] = (gr < R && gk < n) ? Cb[(size_t)gr * n + gk] : 0.0;
+      ra[u] = (gr < R && gk < n) ? (TT)Cb[(size_t)gr * n + gk] : (TT)0;
     }
 #pragma unroll
     for (int u = 0; u < NBv; ++u) {
       int idx = threadIdx.x + u * WG;
       int gk = k0 + idx / ST, gc = c0 + idx % ST;
-      rb[u] = (gk < n && gc < C) ? W[(size_t)gk * ldw + gc] : 0.0;
+      rb[u] = (gk < n && gc < C) ? (TT)W[(size_t)gk * ldw + gc] : (TT)0;
     }
   };
   fetch(0);
@@ -511,7 +527,7 @@ __global__ void __launch_bounds__(WG) k_elim_schur(LevelPtrs P, const int* __res
     if (k0 + SK < n) fetch(k0 + SK);
 #pragma unroll
     for (int k4 = 0; k4 < SK; k4 += 4) {
-      double a[BL], bb[BL];
+      TT a[BL], bb[BL];
 #pragma unroll
       for (int i = 0; i < BL; ++i) a[i] = As[wr + 16 * i + fr][k4 + fk];
 #pragma unroll
@@ -519,12 +535,13 @@ __global__ void __launch_bounds__(WG) k_elim_schur(LevelPtrs P, const int* __res
 #pragma unroll
       for (int i = 0; i < BL; ++i)
 #pragma unroll
-        for (int j = 0; j < BL; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < BL; ++j) acc[i][j] = mfma16(a[i], bb[j], acc[i][j]);
     }
     __syncthreads();
   }
   const int64_t* ts = P.tslot + (size_t)b * P.Gmax * P.Gmax;
-  // output (lane, q) of block (i, j): row wr + 16 i + lane / 16 + 4 q, column wc + 16 j + lane % 16
+  // output (lane, q) of block (i, j): column wc + 16 j + lane % 16; row wr + 16 i + lane / 16 + 4 q
+  // (FP64 MFMA) or wr + 16 i + 4 (lane / 16) + q (FP32 MFMA)
 #pragma unroll
   for (int j = 0; j < BL; ++j) {
     int c = c0 + wc + 16 * j + fr;
@@ -539,14 +556,14 @@ __global__ void __launch_bounds__(WG) k_elim_schur(LevelPtrs P, const int* __res
     for (int i = 0; i < BL; ++i)
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
-        int r = r0 + wr + 16 * i + fk + 4 * qq;
+        int r = r0 + wr + 16 * i + (F32 ? 4 * fk + qq : fk + 4 * qq);
         if (r >= R) continue;
         int gr = 0;
         while (rstart[gr + 1] <= r) ++gr;
         int lr = r - rstart[gr];
         double* T = P.slab + ts[gr * P.Gmax + gc];
         size_t addr = (size_t)lr * ldq + lc;
-        double v = acc[i][j][qq];
+        double v = (double)acc[i][j][qq];
         if (last) T[addr] = -v;
         else T[addr] -= v;
       }
@@ -1170,15 +1187,17 @@ void factor_system(aifmm_system& s) {
     // launch, so every team is co-resident); pivot positions and a reflector live in LDS
     size_t shmem = (size_t)cap * sizeof(double) + (size_t)4 * cap * sizeof(int);
     if (shmem > 160 * 1024) throw Error{AIFMM_ERR_CAPACITY, "box size too large for the compression kernel"};
+    const bool f32 = s.prec == AIFMM_FP32;
+    const void* kcomp = f32 ? (const void*)k_compress<float> : (const void*)k_compress<double>;
     if (shmem > 64 * 1024)
-      AIFMM_HIP(hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+      AIFMM_HIP(hipFuncSetAttribute(kcomp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
     int coop_max = 0;
     {
       int dev = 0, coop = 0, ncu = 0, per = 0;
       AIFMM_HIP(hipGetDevice(&dev));
       AIFMM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
       AIFMM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_compress, CT, shmem));
+      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kcomp, CT, shmem));
       if (coop && !team_off()) coop_max = per * ncu;
     }
     DBuf<unsigned> d_ctr;
@@ -1210,8 +1229,12 @@ void factor_system(aifmm_system& s) {
         if (coop_max > 0 && ne > 0)
           G = std::max(1, std::min({16, coop_max / ne, (int)((int64_t)2 * cap * cap / 49152)}));
         if (G == 1) {
-          hipLaunchKernelGGL(k_compress, dim3(ne), dim3(CT), shmem, st, P, er, ne, ws.p, wsz, cap, s.tol, r_off[rix],
-                             1, d_ctr.p, d_part.p, d_abort.p);
+          if (f32)
+            hipLaunchKernelGGL(k_compress<float>, dim3(ne), dim3(CT), shmem, st, P, er, ne, ws.p, wsz, cap, s.tol,
+                               r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p);
+          else
+            hipLaunchKernelGGL(k_compress<double>, dim3(ne), dim3(CT), shmem, st, P, er, ne, ws.p, wsz, cap, s.tol,
+                               r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p);
         } else {
           AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * ne, st));
           int64_t tb = r_off[rix];
@@ -1221,12 +1244,21 @@ void factor_system(aifmm_system& s) {
           int* abortp = d_abort.p;
           double* wsp = ws.p;
           void* args[] = {&P, (void*)&er, &ne, &wsp, &wsz, &cap, &tol, &tb, &G, &ctrp, &partp, &abortp};
-          AIFMM_HIP(hipLaunchCooperativeKernel((const void*)k_compress, dim3(ne * G), dim3(CT), args, shmem, st));
+          AIFMM_HIP(hipLaunchCooperativeKernel(kcomp, dim3(ne * G), dim3(CT), args, shmem, st));
         }
         AIFMM_HIP(hipEventRecord(ce.second, st));
         int grid = std::min<int64_t>(XG, (int64_t)nx * maxblk);
-        hipLaunchKernelGGL(k_row_xform, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p, sstride);
-        hipLaunchKernelGGL(k_col_xform, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p, sstride);
+        if (f32) {
+          hipLaunchKernelGGL(k_row_xform<float>, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p,
+                             sstride);
+          hipLaunchKernelGGL(k_col_xform<float>, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p,
+                             sstride);
+        } else {
+          hipLaunchKernelGGL(k_row_xform<double>, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk,
+                             scratch.p, sstride);
+          hipLaunchKernelGGL(k_col_xform<double>, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk,
+                             scratch.p, sstride);
+        }
         hipLaunchKernelGGL(k_commit, dim3(cdiv(nx, WG)), dim3(WG), 0, st, P, ex, nx);
       }
       int nbox = Pl.col_off[c + 1] - Pl.col_off[c];
@@ -1238,7 +1270,10 @@ void factor_system(aifmm_system& s) {
       int tiles_x = 8 * cdiv((int64_t)tiles_r * tiles_c, 8);
       auto se = ev_pair(sch_ev);
       AIFMM_HIP(hipEventRecord(se.first, st));
-      hipLaunchKernelGGL(k_elim_schur, dim3(tiles_x, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
+      if (s.prec == AIFMM_FP32)
+        hipLaunchKernelGGL(k_elim_schur<true>, dim3(tiles_x, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
+      else
+        hipLaunchKernelGGL(k_elim_schur<false>, dim3(tiles_x, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
       AIFMM_HIP(hipEventRecord(se.second, st));
       hipLaunchKernelGGL(k_elim_zrow, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
       launch_check("elimination");

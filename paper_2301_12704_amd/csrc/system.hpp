@@ -219,6 +219,7 @@ struct aifmm_system {
   int64_t N = 0;
   aifmm::KernelDesc K{};
   double tol = 1e-10;
+  int prec = 0;                   // AIFMM_FP64 or AIFMM_FP32 (arithmetic of Schur update and compression)
   hipStream_t stream = nullptr;
   bool factored = false;
   std::string err;

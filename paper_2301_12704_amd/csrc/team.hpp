@@ -90,35 +90,35 @@ struct Team {
   }
 };
 
-template <int NT>
-__device__ inline void t_copy(Team<NT>& T, int M, int N, const double* __restrict__ A, int lda, double* __restrict__ C,
-                              int ldc) {
+template <int NT, class TS, class TD>
+__device__ inline void t_copy(Team<NT>& T, int M, int N, const TS* __restrict__ A, int lda, TD* __restrict__ C, int ldc) {
   for (int idx = T.gtid; idx < M * N; idx += T.GT) {
     int r = idx / N, c = idx - r * N;
-    C[(size_t)r * ldc + c] = A[(size_t)r * lda + c];
+    C[(size_t)r * ldc + c] = (TD)A[(size_t)r * lda + c];
   }
   T.sync();
 }
-template <int NT>
-__device__ inline void t_zero(Team<NT>& T, int M, int N, double* C, int ldc) {
+template <int NT, class TD>
+__device__ inline void t_zero(Team<NT>& T, int M, int N, TD* C, int ldc) {
   for (int idx = T.gtid; idx < M * N; idx += T.GT) {
     int r = idx / N, c = idx - r * N;
-    C[(size_t)r * ldc + c] = 0.0;
+    C[(size_t)r * ldc + c] = (TD)0;
   }
   T.sync();
 }
-// C = alpha op(A) op(B) + beta C, each element accumulated in ascending k (as wg_gemm).
-template <int NT>
-__device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
-                              bool ta, const double* __restrict__ B, int ldb, bool tb, double beta, double* C, int ldc) {
+// C = alpha op(A) op(B) + beta C, each element accumulated in ascending k in the precision of
+// C (as wg_gemm).
+template <int NT, class TA, class TB, class TC>
+__device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, const TA* __restrict__ A, int lda,
+                              bool ta, const TB* __restrict__ B, int ldb, bool tb, double beta, TC* C, int ldc) {
   for (int idx = T.gtid; idx < M * N; idx += T.GT) {
     int r = idx / N, c = idx - r * N;
-    const double* pa = ta ? A + r : A + (size_t)r * lda;
-    const double* pb = tb ? B + (size_t)c * ldb : B + c;
+    const TA* pa = ta ? A + r : A + (size_t)r * lda;
+    const TB* pb = tb ? B + (size_t)c * ldb : B + c;
     size_t sa = ta ? (size_t)lda : 1, sb = tb ? 1 : (size_t)ldb;
-    double acc = seq_dot(K, [&](int k) { return pa[k * sa]; }, [&](int k) { return pb[k * sb]; }, 0.0);
-    double v = alpha * acc;
-    if (beta != 0.0) v += beta * C[(size_t)r * ldc + c];
+    TC acc = seq_dot(K, [&](int k) { return (TC)pa[k * sa]; }, [&](int k) { return (TC)pb[k * sb]; }, (TC)0);
+    TC v = (TC)alpha * acc;
+    if (beta != 0.0) v += (TC)beta * C[(size_t)r * ldc + c];
     C[(size_t)r * ldc + c] = v;
   }
   T.sync();
@@ -133,15 +133,18 @@ __device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, co
 // (device memory, n) holds each column's trailing norm.  M's pivot columns are left as they
 // were when chosen (R is not formed).  Returns the rank; ratio (if given) receives the two
 // decision ratios of wg_cpqr.
-template <int NT>
-__device__ inline int t_cpqr(Team<NT>& T, int m, int n, double* M, int ldm, double tol, double* V, int ldv, double* tau,
-                             double* nrm, ValIdx* shv, double* vsh, int* pos, int* at, double* ratio = nullptr) {
+template <int NT, class R>
+__device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double tol, R* V, int ldv, R* tau, R* nrm,
+                             ValIdx* shv, R* vsh, int* pos, int* at, double* ratio = nullptr) {
+  // pivot ties: norms within a relative band of the largest (1e-11 in FP64, 2e-6 in FP32)
+  const R keep = sizeof(R) == 4 ? R(1.0 - 2e-6) : R(1.0 - 1e-11);
+  const R tolr = (R)tol;
   double kept = 0.0, next = 0.0;
   int smax = m < n ? m : n;
-  double r11 = 0.0;
+  R r11 = 0;
   for (int c = T.cid; c < n; c += T.GT) {
-    const double* col = M + c;
-    double t = seq_dot(m, [&](int i) { return col[(size_t)i * ldm]; }, [&](int i) { return col[(size_t)i * ldm]; }, 0.0);
+    const R* col = M + c;
+    R t = seq_dot(m, [&](int i) { return col[(size_t)i * ldm]; }, [&](int i) { return col[(size_t)i * ldm]; }, R(0));
     nrm[c] = sqrt(t);
   }
   for (int c = threadIdx.x; c < n; c += NT) {
@@ -157,22 +160,22 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, double* M, int ldm, doub
     ValIdx mx{-1.0, INT_MAX};
     for (int c = T.cid; c < n; c += T.GT)
       if (pos[c] >= s) {
-        ValIdx x{nrm[c], pos[c]};
+        ValIdx x{(double)nrm[c], pos[c]};
         if (vi_better(x, mx)) mx = x;
       }
     mx = wg_argmax<NT>(mx, shv);
-    double lthr = mx.v * (1.0 - 1e-11);
+    R lthr = (R)mx.v * keep;
     ValIdx lb{-1.0, INT_MAX};
     for (int c = T.cid; c < n; c += T.GT)
       if (pos[c] >= s && nrm[c] >= lthr && pos[c] < lb.i) lb = ValIdx{0.0, pos[c]};
     lb = wg_argmax<NT>(lb, shv);
     int pp = lb.i;
     if (T.G > 1) {
-      double lnv = lb.i != INT_MAX ? nrm[at[lb.i]] : -1.0;
+      double lnv = lb.i != INT_MAX ? (double)nrm[at[lb.i]] : -1.0;
       const Cand* all = T.exchange(Cand{mx.v, lnv, lb.i, 0});
       double mstar = -1.0;
       for (int q = 0; q < T.G; ++q) mstar = fmax(mstar, all[q].mv);
-      double thr = mstar * (1.0 - 1e-11);
+      R thr = (R)mstar * keep;
       bool amb = false;
       pp = INT_MAX;
       for (int q = 0; q < T.G; ++q)
@@ -188,15 +191,15 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, double* M, int ldm, doub
       }
     }
     const int cp = at[pp];
-    const double bv = nrm[cp];
+    const R bv = nrm[cp];
     if (s == 0) {
       r11 = bv;
-      if (r11 == 0.0) break;
-    } else if (bv <= tol * r11) {
-      next = bv / (tol * r11);
+      if (r11 == R(0)) break;
+    } else if (bv <= tolr * r11) {
+      next = (double)bv / ((double)tolr * (double)r11);
       break;
     }
-    kept = bv / (tol * r11);
+    kept = (double)bv / ((double)tolr * (double)r11);
     __syncthreads();
     if (threadIdx.x == 0) {
       int cs = at[s];
@@ -205,13 +208,13 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, double* M, int ldm, doub
       pos[cp] = s;
       pos[cs] = pp;
     }
-    double x0 = M[(size_t)s * ldm + cp];
-    double beta = x0 >= 0.0 ? -bv : bv;
-    double scale = x0 - beta;
-    double tv = (beta - x0) / beta;
+    R x0 = M[(size_t)s * ldm + cp];
+    R beta = x0 >= R(0) ? -bv : bv;
+    R scale = x0 - beta;
+    R tv = (beta - x0) / beta;
     for (int i = threadIdx.x; i < m; i += NT) {
-      double v = 0.0;
-      if (i == s) v = 1.0;
+      R v = 0;
+      if (i == s) v = 1;
       else if (i > s) v = M[(size_t)i * ldm + cp] / scale;
       vsh[i] = v;
       if (T.member == 0) V[(size_t)i * ldv + s] = v;
@@ -219,17 +222,17 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, double* M, int ldm, doub
     if (T.member == 0 && threadIdx.x == 0) tau[s] = tv;
     __syncthreads();
     const int len = m - s;
-    const double* vv = vsh + s;
+    const R* vv = vsh + s;
     for (int c = T.cid; c < n; c += T.GT) {
       if (pos[c] <= s) continue;
-      double* col = M + (size_t)s * ldm + c;
-      double w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldm]; }, 0.0);
+      R* col = M + (size_t)s * ldm + c;
+      R w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldm]; }, R(0));
       w *= tv;
       col[0] = fma(-w, vv[0], col[0]);
-      double t = 0.0;
+      R t = 0;
       int i = 1;
       for (; i + 8 <= len; i += 8) {
-        double a[8];
+        R a[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldm];
 #pragma unroll
@@ -240,7 +243,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, double* M, int ldm, doub
         }
       }
       for (; i < len; ++i) {
-        double a = fma(-w, vv[i], col[(size_t)i * ldm]);
+        R a = fma(-w, vv[i], col[(size_t)i * ldm]);
         col[(size_t)i * ldm] = a;
         t = fma(a, a, t);
       }
@@ -257,28 +260,28 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, double* M, int ldm, doub
 
 // Columns c0 .. q-1 of Q = H_0 ... H_{rank-1} [I; 0] (m x q, ldq), as wg_formq: every column is
 // formed by one team thread through all reflectors, so members only synchronise at the end.
-template <int NT>
-__device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const double* V, int ldv, const double* tau,
-                               double* Q, int ldq, double* vsh, int c0 = 0) {
+template <int NT, class R>
+__device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, int ldv, const R* tau, R* Q, int ldq,
+                               R* vsh, int c0 = 0) {
   for (int j = c0 + T.cid; j < q; j += T.GT)
-    for (int r = 0; r < m; ++r) Q[(size_t)r * ldq + j] = (r == j) ? 1.0 : 0.0;
+    for (int r = 0; r < m; ++r) Q[(size_t)r * ldq + j] = (r == j) ? R(1) : R(0);
   for (int s = rank - 1; s >= 0; --s) {
-    double tv = tau[s];
+    R tv = tau[s];
     __syncthreads();
     for (int i = s + threadIdx.x; i < m; i += NT) vsh[i] = V[(size_t)i * ldv + s];
     __syncthreads();
     int len = m - s;
-    const double* vv = vsh + s;
+    const R* vv = vsh + s;
     int j0 = c0 > s ? c0 : s;
     // a column is still e_j while s > j, so the reflector leaves it unchanged
     for (int j = c0 + T.cid; j < q; j += T.GT) {
       if (j < j0) continue;
-      double* col = Q + (size_t)s * ldq + j;
-      double w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldq]; }, 0.0);
+      R* col = Q + (size_t)s * ldq + j;
+      R w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldq]; }, R(0));
       w *= tv;
       int i = 0;
       for (; i + 8 <= len; i += 8) {
-        double a[8];
+        R a[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldq];
 #pragma unroll
