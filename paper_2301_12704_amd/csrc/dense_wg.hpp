@@ -55,19 +55,21 @@ __device__ inline double kernel_entry(const KernelDesc& K, const double* __restr
 }
 
 // acc + sum_{i<n} a(i) b(i), accumulated in ascending i with fused multiply-adds; the loads of
-// every batch of eight terms are issued before its multiply-adds.
-template <class FA, class FB>
-__device__ inline double seq_dot(int n, FA a, FB b, double acc) {
+// every batch of SEQ_B terms are issued before its multiply-adds (loads in flight hide the
+// memory latency of the sequential chain).
+constexpr int SEQ_B = 16;
+template <int B = SEQ_B, class FA, class FB, class T>
+__device__ inline T seq_dot(int n, FA a, FB b, T acc) {
   int i = 0;
-  for (; i + 8 <= n; i += 8) {
-    double x[8], y[8];
+  for (; i + B <= n; i += B) {
+    T x[B], y[B];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < B; ++u) {
       x[u] = a(i + u);
       y[u] = b(i + u);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = fma(x[u], y[u], acc);
+    for (int u = 0; u < B; ++u) acc = fma(x[u], y[u], acc);
   }
   for (; i < n; ++i) acc = fma(a(i), b(i), acc);
   return acc;
@@ -160,148 +162,6 @@ __device__ inline void wg_zero(int M, int N, double* C, int ldc) {
     C[(size_t)r * ldc + c] = 0.0;
   }
   __syncthreads();
-}
-
-// Householder QR with column pivoting on the m x n row-major matrix M (destroyed), truncated
-// at the first step whose pivot column norm is <= tol times the first one (RRQR with
-// threshold eps_A of Sec. 3.2.1).  Pivot: the lowest-index column whose trailing norm is
-// within a relative 1e-11 of the largest, so norms equal in exact arithmetic (orthonormal
-// basis columns) tie whatever the rounding.  Trailing norms are sums over the rows in
-// ascending order; the norms of step s+1 are formed while the reflector of step s is applied
-// (the same sums as recomputing them).  Reflector s is stored in column s of V (ldv) with
-// V[s][s] = 1, tau[s] its scale; nrm is scratch of length n.  Returns the rank; ratio (if
-// given) receives |R_kk|/(tol |R_11|) of the last kept and of the first rejected pivot.
-template <int NT = WG>
-__device__ inline int wg_cpqr(int m, int n, double* M, int ldm, double tol, double* V, int ldv, double* tau,
-                              double* nrm, ValIdx* shv, double* vsh, double* ratio = nullptr) {
-  double kept = 0.0, next = 0.0;
-  int smax = m < n ? m : n;
-  double r11 = 0.0;
-  for (int j = threadIdx.x; j < n; j += NT) {
-    const double* col = M + j;
-    double t = seq_dot(m, [&](int i) { return col[(size_t)i * ldm]; }, [&](int i) { return col[(size_t)i * ldm]; }, 0.0);
-    nrm[j] = sqrt(t);
-  }
-  __syncthreads();
-  int s = 0;
-  for (; s < smax; ++s) {
-    ValIdx mx{-1.0, INT_MAX};
-    for (int j = s + (int)threadIdx.x; j < n; j += NT) {
-      ValIdx c{nrm[j], j};
-      if (vi_better(c, mx)) mx = c;
-    }
-    mx = wg_argmax<NT>(mx, shv);
-    double thr = mx.v * (1.0 - 1e-11);
-    ValIdx best{-1.0, INT_MAX};
-    for (int j = s + (int)threadIdx.x; j < n; j += NT)
-      if (nrm[j] >= thr && j < best.i) best = ValIdx{0.0, j};
-    best = wg_argmax<NT>(best, shv);
-    best.v = nrm[best.i];
-    if (s == 0) {
-      r11 = best.v;
-      if (r11 == 0.0) break;
-    } else if (best.v <= tol * r11) {
-      next = best.v / (tol * r11);
-      break;
-    }
-    kept = best.v / (tol * r11);
-    int p = best.i;
-    if (p != s) {
-      for (int i = threadIdx.x; i < m; i += NT) {
-        double a = M[(size_t)i * ldm + s];
-        M[(size_t)i * ldm + s] = M[(size_t)i * ldm + p];
-        M[(size_t)i * ldm + p] = a;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double t = nrm[s];
-        nrm[s] = nrm[p];
-        nrm[p] = t;
-      }
-    }
-    double x0 = M[(size_t)s * ldm + s];
-    double alpha = best.v;
-    double beta = x0 >= 0.0 ? -alpha : alpha;
-    double scale = x0 - beta;
-    double tv = (beta - x0) / beta;
-    for (int i = threadIdx.x; i < m; i += NT) {
-      double v = 0.0;
-      if (i == s) v = 1.0;
-      else if (i > s) v = M[(size_t)i * ldm + s] / scale;
-      V[(size_t)i * ldv + s] = v;
-      vsh[i] = v;
-    }
-    if (threadIdx.x == 0) tau[s] = tv;
-    __syncthreads();
-    int len = m - s;
-    for (int j = s + 1 + (int)threadIdx.x; j < n; j += NT) {
-      double* col = M + (size_t)s * ldm + j;
-      const double* vv = vsh + s;
-      double w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldm]; }, 0.0);
-      w *= tv;
-      col[0] = fma(-w, vv[0], col[0]);
-      double t = 0.0;
-      int i = 1;
-      for (; i + 8 <= len; i += 8) {
-        double a[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldm];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          a[u] = fma(-w, vv[i + u], a[u]);
-          col[(size_t)(i + u) * ldm] = a[u];
-          t = fma(a[u], a[u], t);
-        }
-      }
-      for (; i < len; ++i) {
-        double a = fma(-w, vv[i], col[(size_t)i * ldm]);
-        col[(size_t)i * ldm] = a;
-        t = fma(a, a, t);
-      }
-      nrm[j] = sqrt(t);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < m; i += NT) M[(size_t)i * ldm + s] = (i == s) ? beta : (i > s ? 0.0 : M[(size_t)i * ldm + s]);
-    __syncthreads();
-  }
-  if (ratio && threadIdx.x == 0) { ratio[0] = kept; ratio[1] = next; }
-  __syncthreads();
-  return s;
-}
-
-// Columns c0 .. q-1 of Q = H_0 H_1 ... H_{rank-1} [I; 0]  (m x q row-major, ldq); columns
-// below c0 are left untouched (already formed).
-template <int NT = WG>
-__device__ inline void wg_formq(int m, int rank, int q, const double* V, int ldv, const double* tau, double* Q, int ldq,
-                                double* vsh, int c0 = 0) {
-  for (int idx = threadIdx.x; idx < m * (q - c0); idx += NT) {
-    int r = idx / (q - c0), c = c0 + idx % (q - c0);
-    Q[(size_t)r * ldq + c] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int s = rank - 1; s >= 0; --s) {
-    double tv = tau[s];
-    for (int i = s + threadIdx.x; i < m; i += NT) vsh[i] = V[(size_t)i * ldv + s];
-    __syncthreads();
-    int len = m - s;
-    const double* vv = vsh + s;
-    // column j is still e_j while s > j, so the reflector leaves it unchanged (w = 0)
-    for (int j = (c0 > s ? c0 : s) + threadIdx.x; j < q; j += NT) {
-      double* col = Q + (size_t)s * ldq + j;
-      double w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldq]; }, 0.0);
-      w *= tv;
-      int i = 0;
-      for (; i + 8 <= len; i += 8) {
-        double a[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldq];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) col[(size_t)(i + u) * ldq] = fma(-w, vv[i + u], a[u]);
-      }
-      for (; i < len; ++i) col[(size_t)i * ldq] = fma(-w, vv[i], col[(size_t)i * ldq]);
-    }
-    __syncthreads();
-  }
 }
 
 // In-place LU with row partial pivoting (ties to the lowest row) of the m x m row-major A;

@@ -80,7 +80,8 @@ constexpr int CT = 512;
 template <class RT>
 __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* __restrict__ ent, int nent, double* ws,
                                                  int64_t wsz, int cap, double tol, int64_t tbase, int G,
-                                                 unsigned* ctr, Cand* part, int* abort) {
+                                                 unsigned* ctr, Cand* part, int* abort, int lds_cols,
+                                                 double* pubbuf) {
   int e = blockIdx.x / G;
   if (e >= nent) return;
   Team<CT> T;
@@ -93,6 +94,10 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   RT* vsh = (RT*)shm;
   int* pos = (int*)(vsh + cap);
   int* at = pos + 2 * cap;
+  // columns of the pivoted QRs and Q formations kept in LDS (lds_cols per member), the
+  // members' candidate pivot columns published in pub (2 x G x cap entries per compression)
+  RT* lcol = lds_cols > 0 ? (RT*)(at + 2 * cap) : nullptr;
+  RT* pub = (RT*)pubbuf + (size_t)e * 2 * G * cap;
   RT* w = (RT*)(ws + (size_t)e * wsz);
   size_t c2 = (size_t)cap * cap;
   RT* Lb_i = w;
@@ -129,31 +134,31 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     int ld = ki + nj;
     t_copy(T, ni, ki, U_i, ni, M, ld);
     t_copy(T, ni, nj, Fij, nj, M + ki, ld);
-    int r1 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr);
+    int r1 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr, lcol, pub);
     // RRQR2: [U_j | P2P_ji] = U~_j L_ji
     ld = kj + ni;
     t_copy(T, nj, kj, U_j, nj, M, ld);
     t_copy(T, nj, ni, Fji, ni, M + kj, ld);
-    int r2 = t_cpqr(T, nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2);
+    int r2 = t_cpqr(T, nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2, lcol, pub);
     // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
-    t_formq(T, ni, r1, r1, V1, cap, tau, nU, cap, vsh);
+    t_formq(T, ni, r1, r1, V1, cap, tau, nU, cap, vsh, 0, lcol);
     ld = kj + r1;
     t_copy(T, nj, kj, V_j, nj, M, ld);
     t_gemm(T, nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
-    int r3 = t_cpqr(T, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, vsh, pos, at, trr + 4);
+    int r3 = t_cpqr(T, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, vsh, pos, at, trr + 4, lcol, pub);
     // RRQR4: [V_i | L~_ji^*]
-    t_formq(T, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh);
+    t_formq(T, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh, 0, lcol);
     ld = ki + r2;
     t_copy(T, ni, ki, V_i, ni, M, ld);
     t_gemm(T, ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, M + ki, ld);
-    int r4 = t_cpqr(T, ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, vsh, pos, at, trr + 6);
+    int r4 = t_cpqr(T, ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, vsh, pos, at, trr + 6, lcol, pub);
     int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
     // new orthonormal bases: columns beyond a tolerance rank are further columns of the same
     // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed)
-    t_formq(T, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1);
-    t_formq(T, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh);
-    t_formq(T, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2);
-    t_formq(T, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh);
+    t_formq(T, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1, lcol);
+    t_formq(T, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh, 0, lcol);
+    t_formq(T, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2, lcol);
+    t_formq(T, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh, 0, lcol);
     // coefficients by projection: U_i = U~_i L_i, V_i = V~_i R_i, ...
     t_gemm(T, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
     t_gemm(T, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
@@ -207,14 +212,14 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
     }
     T.sync();
-    int r5 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr);
+    int r5 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr, lcol, pub);
     // RRQR: [U_i | M2P_ir] = U~_i L_ir
     t_copy(T, ni, ki, U_i, ni, M, ld);
     t_copy(T, ni, kr, M2P, nr, M + ki, ld);
-    int r6 = t_cpqr(T, ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2);
+    int r6 = t_cpqr(T, ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2, lcol, pub);
     int kin = r5 > r6 ? r5 : r6;
-    t_formq(T, ni, r5, kin, V1, cap, tau, nV, cap, vsh);
-    t_formq(T, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh);
+    t_formq(T, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol);
+    t_formq(T, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol);
     t_gemm(T, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
     t_gemm(T, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
     // A_ri := A_ri R_i^* + P2L_ri V~_i
@@ -1095,6 +1100,11 @@ static void count_flops(aifmm_system& s, int l) {
   }
 }
 
+static bool lds_off() {
+  const char* v = getenv("AIFMM_NO_LDS_COLUMNS");
+  return v && *v && *v != '0';
+}
+
 static bool team_off() {
   const char* v = getenv("AIFMM_NO_TEAMS");
   return v && *v && *v != '0';
@@ -1185,26 +1195,57 @@ void factor_system(aifmm_system& s) {
     size_t rix = 0;
     // compressions of a small round are spread over teams of G workgroups each (cooperative
     // launch, so every team is co-resident); pivot positions and a reflector live in LDS
-    size_t shmem = (size_t)cap * sizeof(double) + (size_t)4 * cap * sizeof(int);
-    if (shmem > 160 * 1024) throw Error{AIFMM_ERR_CAPACITY, "box size too large for the compression kernel"};
+    // compression teams: a round with few pending compressions spreads each over a team of G
+    // co-resident workgroups (cooperative launch); when a team's share of the pivoted-QR columns
+    // fits, the columns live in LDS (lds_cols per member), otherwise in the workspace
     const bool f32 = s.prec == AIFMM_FP32;
+    const size_t rs = f32 ? sizeof(float) : sizeof(double);
     const void* kcomp = f32 ? (const void*)k_compress<float> : (const void*)k_compress<double>;
-    if (shmem > 64 * 1024)
-      AIFMM_HIP(hipFuncSetAttribute(kcomp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-    int coop_max = 0;
+    const size_t base = (size_t)cap * rs + (size_t)4 * cap * sizeof(int);  // reflector + pivot positions
+    const size_t lds_max = 152 * 1024;
+    if (base > lds_max) throw Error{AIFMM_ERR_CAPACITY, "box size too large for the compression kernel"};
+    AIFMM_HIP(hipFuncSetAttribute(kcomp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
+    constexpr int GMAX = 32;
+    int coop_g = 0, coop_l = 0;
     {
-      int dev = 0, coop = 0, ncu = 0, per = 0;
+      int dev = 0, coop = 0, ncu = 0, per_g = 0, per_l = 0;
       AIFMM_HIP(hipGetDevice(&dev));
       AIFMM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
       AIFMM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kcomp, CT, shmem));
-      if (coop && !team_off()) coop_max = per * ncu;
+      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_g, kcomp, CT, base));
+      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_l, kcomp, CT, lds_max));
+      if (coop && !team_off()) {
+        coop_g = per_g * ncu;
+        coop_l = per_l * ncu;
+      }
     }
+    auto team_shape = [&](int ne, int& G, int& lcols, size_t& shm) {
+      G = 1;
+      lcols = 0;
+      shm = base;
+      // LDS columns pay off for small teams only: a larger team's per-step reductions and
+      // barrier cost more than the column traffic it saves
+      if (!lds_off())
+        for (int g = 1; g <= 8; ++g) {
+          if (g > 1 && (coop_l == 0 || (int64_t)ne * g > coop_l)) break;
+          int cols = (2 * cap + g - 1) / g;
+          if (base + (size_t)cols * cap * rs <= lds_max) {
+            G = g;
+            lcols = cols;
+            shm = base + (size_t)cols * cap * rs;
+            return;
+          }
+        }
+      if (coop_g > 0 && ne > 0)
+        G = std::max(1, std::min({16, coop_g / ne, (int)((int64_t)2 * cap * cap / 49152)}));
+    };
     DBuf<unsigned> d_ctr;
     DBuf<Cand> d_part;
     DBuf<int> d_abort;
+    DBuf<double> d_pub;
     d_ctr.alloc(std::max(1, maxcol));
-    d_part.alloc((size_t)std::max(1, maxcol) * 2 * 16);
+    d_part.alloc((size_t)std::max(1, maxcol) * 2 * GMAX);
+    d_pub.alloc((size_t)std::max(1, maxcol) * 2 * GMAX * cap);
     d_abort.alloc(1);
     d_abort.zero(st);
     hipEvent_t ev[4];
@@ -1225,16 +1266,16 @@ void factor_system(aifmm_system& s) {
         const XformEntry* ex = d_xent.p + x_off[rix];
         auto ce = ev_pair(cmp_ev);
         AIFMM_HIP(hipEventRecord(ce.first, st));
-        int G = 1;
-        if (coop_max > 0 && ne > 0)
-          G = std::max(1, std::min({16, coop_max / ne, (int)((int64_t)2 * cap * cap / 49152)}));
+        int G = 1, lcols = 0;
+        size_t shm = base;
+        team_shape(ne, G, lcols, shm);
         if (G == 1) {
           if (f32)
-            hipLaunchKernelGGL(k_compress<float>, dim3(ne), dim3(CT), shmem, st, P, er, ne, ws.p, wsz, cap, s.tol,
-                               r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p);
+            hipLaunchKernelGGL(k_compress<float>, dim3(ne), dim3(CT), shm, st, P, er, ne, ws.p, wsz, cap, s.tol,
+                               r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p, lcols, d_pub.p);
           else
-            hipLaunchKernelGGL(k_compress<double>, dim3(ne), dim3(CT), shmem, st, P, er, ne, ws.p, wsz, cap, s.tol,
-                               r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p);
+            hipLaunchKernelGGL(k_compress<double>, dim3(ne), dim3(CT), shm, st, P, er, ne, ws.p, wsz, cap, s.tol,
+                               r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p, lcols, d_pub.p);
         } else {
           AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * ne, st));
           int64_t tb = r_off[rix];
@@ -1243,8 +1284,9 @@ void factor_system(aifmm_system& s) {
           unsigned* ctrp = d_ctr.p;
           int* abortp = d_abort.p;
           double* wsp = ws.p;
-          void* args[] = {&P, (void*)&er, &ne, &wsp, &wsz, &cap, &tol, &tb, &G, &ctrp, &partp, &abortp};
-          AIFMM_HIP(hipLaunchCooperativeKernel(kcomp, dim3(ne * G), dim3(CT), args, shmem, st));
+          double* pubp = d_pub.p;
+          void* args[] = {&P, (void*)&er, &ne, &wsp, &wsz, &cap, &tol, &tb, &G, &ctrp, &partp, &abortp, &lcols, &pubp};
+          AIFMM_HIP(hipLaunchCooperativeKernel(kcomp, dim3(ne * G), dim3(CT), args, shm, st));
         }
         AIFMM_HIP(hipEventRecord(ce.second, st));
         int grid = std::min<int64_t>(XG, (int64_t)nx * maxblk);

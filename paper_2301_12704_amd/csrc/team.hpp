@@ -124,27 +124,108 @@ __device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, co
   T.sync();
 }
 
-// Householder QR with column pivoting of the m x n row-major M, truncated as wg_cpqr (same
-// pivot rule, same operation order per column).  Columns stay where they are: column c is
-// owned by member c mod G (columns interleave across members), and its pivot-order position is tracked in pos / at (LDS of
-// every member, n entries each) — a swap of positions s and p is exactly the column exchange
-// of wg_cpqr.  The pivot column is read by every member to form the reflector (vsh: m
-// doubles of LDS).  Reflector s is written to column s of V (ldv), its scale to tau[s]; nrm
-// (device memory, n) holds each column's trailing norm.  M's pivot columns are left as they
-// were when chosen (R is not formed).  Returns the rank; ratio (if given) receives the two
-// decision ratios of wg_cpqr.
+// Pivot candidate state for one pass over the live columns: the largest norm mx, the lowest
+// position p among the columns whose norm is >= keep * mx, that column's norm nv, and amb set
+// when merging lost the information needed to know p exactly (a column within the band of a
+// smaller maximum that may or may not reach the band of the larger one).  Merging is
+// associative; when amb is clear, p is exactly the pivot of the two-pass rule.
+struct PivState {
+  double mx, nv;
+  int p, amb;
+};
+template <class R>
+__device__ inline PivState piv_merge(const PivState& a, const PivState& b, R keep) {
+  PivState r;
+  r.mx = fmax(a.mx, b.mx);
+  r.p = INT_MAX;
+  r.nv = -1.0;
+  r.amb = a.amb | b.amb;
+  const double thr = (double)((R)r.mx * keep);
+  const PivState* s[2] = {&a, &b};
+  for (int q = 0; q < 2; ++q) {
+    const PivState& x = *s[q];
+    if (x.p == INT_MAX || x.mx < thr) continue;
+    if (x.nv >= thr) {
+      if (x.p < r.p) { r.p = x.p; r.nv = x.nv; }
+    } else {
+      r.amb = 1;
+    }
+  }
+  return r;
+}
+// Workgroup-wide merge of the per-thread states (the same result on every thread).
+template <int NT, class R>
+__device__ inline PivState wg_pivmerge(PivState x, R keep, PivState* sh) {
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    PivState o;
+    o.mx = __shfl_down(x.mx, off, WAVE);
+    o.nv = __shfl_down(x.nv, off, WAVE);
+    o.p = __shfl_down(x.p, off, WAVE);
+    o.amb = __shfl_down(x.amb, off, WAVE);
+    x = piv_merge(x, o, keep);
+  }
+  int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    PivState b = sh[0];
+    for (int q = 1; q < NT / WAVE; ++q) b = piv_merge(b, sh[q], keep);
+    sh[NT / WAVE] = b;
+  }
+  __syncthreads();
+  PivState r = sh[NT / WAVE];
+  return r;
+}
+
+// Householder QR with column pivoting of the m x n row-major M, truncated at the first step
+// whose pivot column norm is <= tol times the first one (RRQR with threshold eps_A of
+// Sec. 3.2.1).  Pivot: the lowest-position column whose trailing norm is within a relative
+// band (1e-11 in FP64, 2e-6 in FP32) of the largest, so norms equal in exact arithmetic
+// (orthonormal basis columns) tie whatever the rounding.  Trailing norms are recomputed every
+// step as sums over the rows in ascending order (formed while the previous reflector is
+// applied; never downdated).  Columns stay where they are: column c is owned by member c mod G
+// (columns interleave across members), and its pivot-order position is tracked in pos / at
+// (LDS of every member, n entries each), so a swap of positions s and p is the column exchange
+// of the textbook algorithm.  The pivot column is read by every member to form the reflector
+// (vsh: m entries of LDS).  Reflector s is written to column s of V (ldv) with V[s][s] = 1, its
+// scale to tau[s]; nrm (device memory, n) holds each column's trailing norm.  M's pivot columns
+// are left as they were when chosen (R is not formed).  Returns the rank; ratio (if given)
+// receives |R_kk| / (tol |R_11|) of the last kept and of the first rejected pivot.
+// column passes of the pivoted QR and Q formation keep this many loads in flight per thread
+constexpr int COL_B = SEQ_B;
 template <int NT, class R>
 __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double tol, R* V, int ldv, R* tau, R* nrm,
-                             ValIdx* shv, R* vsh, int* pos, int* at, double* ratio = nullptr) {
+                             ValIdx* shv, R* vsh, int* pos, int* at, double* ratio, R* lcol, R* pub) {
+  __shared__ PivState psh[NT / WAVE + 1];
   // pivot ties: norms within a relative band of the largest (1e-11 in FP64, 2e-6 in FP32)
   const R keep = sizeof(R) == 4 ? R(1.0 - 2e-6) : R(1.0 - 1e-11);
   const R tolr = (R)tol;
+  // column storage: with lcol the member's own columns are copied to its LDS (column c at
+  // lcol + (c / G) m, rows contiguous) and M is only read once; otherwise M in place
+  const bool lds = lcol != nullptr;
+  auto cptr = [&](int c) -> R* { return lds ? lcol + (size_t)(c / T.G) * m : M + c; };
+  const size_t cst = lds ? 1 : (size_t)ldm;
   double kept = 0.0, next = 0.0;
   int smax = m < n ? m : n;
   R r11 = 0;
+  if (lds)
+    for (int c = T.cid; c < n; c += T.GT) {
+      R* d = cptr(c);
+      const R* g = M + c;
+      int i = 0;
+      for (; i + SEQ_B <= m; i += SEQ_B) {
+        R a[SEQ_B];
+#pragma unroll
+        for (int u = 0; u < SEQ_B; ++u) a[u] = g[(size_t)(i + u) * ldm];
+#pragma unroll
+        for (int u = 0; u < SEQ_B; ++u) d[i + u] = a[u];
+      }
+      for (; i < m; ++i) d[i] = g[(size_t)i * ldm];
+    }
   for (int c = T.cid; c < n; c += T.GT) {
-    const R* col = M + c;
-    R t = seq_dot(m, [&](int i) { return col[(size_t)i * ldm]; }, [&](int i) { return col[(size_t)i * ldm]; }, R(0));
+    const R* col = cptr(c);
+    R t = seq_dot<COL_B>(m, [&](int i) { return col[i * cst]; }, [&](int i) { return col[i * cst]; }, R(0));
     nrm[c] = sqrt(t);
   }
   for (int c = threadIdx.x; c < n; c += NT) {
@@ -154,41 +235,41 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
   __syncthreads();
   int s = 0;
   for (; s < smax; ++s) {
-    // largest live norm, then the lowest position within a relative 1e-11 of it: first per
-    // workgroup, then across the team in one exchange (a second one only when a member's
-    // candidate falls between its own and the team's threshold)
-    ValIdx mx{-1.0, INT_MAX};
+    // one merged pass per workgroup, then one exchange across the team: the largest live norm
+    // and the lowest position within the tie band of it; the exact two-pass selection runs
+    // only when a merge reports an ambiguity
+    PivState ps{-1.0, -1.0, INT_MAX, 0};
     for (int c = T.cid; c < n; c += T.GT)
-      if (pos[c] >= s) {
-        ValIdx x{(double)nrm[c], pos[c]};
-        if (vi_better(x, mx)) mx = x;
-      }
-    mx = wg_argmax<NT>(mx, shv);
-    R lthr = (R)mx.v * keep;
-    ValIdx lb{-1.0, INT_MAX};
-    for (int c = T.cid; c < n; c += T.GT)
-      if (pos[c] >= s && nrm[c] >= lthr && pos[c] < lb.i) lb = ValIdx{0.0, pos[c]};
-    lb = wg_argmax<NT>(lb, shv);
-    int pp = lb.i;
+      if (pos[c] >= s) ps = piv_merge(ps, PivState{(double)nrm[c], (double)nrm[c], pos[c], 0}, keep);
+    ps = wg_pivmerge<NT>(ps, keep, psh);
+    // LDS columns of a team: each member publishes its candidate column (rows s..m-1) before
+    // the exchange, in a buffer alternating with the step parity
+    R* slot = pub + ((size_t)(s & 1) * T.G + T.member) * m;
+    if (lds && T.G > 1 && ps.p != INT_MAX) {
+      const R* src = cptr(at[ps.p]);
+      for (int i = s + threadIdx.x; i < m; i += NT) slot[i] = src[i];
+    }
     if (T.G > 1) {
-      double lnv = lb.i != INT_MAX ? (double)nrm[at[lb.i]] : -1.0;
-      const Cand* all = T.exchange(Cand{mx.v, lnv, lb.i, 0});
-      double mstar = -1.0;
-      for (int q = 0; q < T.G; ++q) mstar = fmax(mstar, all[q].mv);
-      R thr = (R)mstar * keep;
-      bool amb = false;
-      pp = INT_MAX;
-      for (int q = 0; q < T.G; ++q)
-        if (all[q].p != INT_MAX && all[q].mv >= thr) {
-          if (all[q].nv >= thr) pp = min(pp, all[q].p);
-          else amb = true;
+      const Cand* all = T.exchange(Cand{ps.mx, ps.nv, ps.p, ps.amb});
+      PivState g{-1.0, -1.0, INT_MAX, 0};
+      for (int q = 0; q < T.G; ++q) g = piv_merge(g, PivState{all[q].mv, all[q].nv, all[q].p, all[q].pad}, keep);
+      ps = g;
+    }
+    int pp = ps.p;
+    bool amb = ps.amb != 0;
+    if (amb) {  // exact rule: team maximum, then the lowest position within its band
+      ValIdx mx{-1.0, INT_MAX};
+      for (int c = T.cid; c < n; c += T.GT)
+        if (pos[c] >= s) {
+          ValIdx x{(double)nrm[c], pos[c]};
+          if (vi_better(x, mx)) mx = x;
         }
-      if (amb) {
-        ValIdx b2{-1.0, INT_MAX};
-        for (int c = T.cid; c < n; c += T.GT)
-          if (pos[c] >= s && nrm[c] >= thr && pos[c] < b2.i) b2 = ValIdx{0.0, pos[c]};
-        pp = T.argmax(b2, shv).i;
-      }
+      mx = T.argmax(mx, shv);
+      R thr = (R)mx.v * keep;
+      ValIdx b2{-1.0, INT_MAX};
+      for (int c = T.cid; c < n; c += T.GT)
+        if (pos[c] >= s && nrm[c] >= thr && pos[c] < b2.i) b2 = ValIdx{0.0, pos[c]};
+      pp = T.argmax(b2, shv).i;
     }
     const int cp = at[pp];
     const R bv = nrm[cp];
@@ -200,6 +281,26 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
       break;
     }
     kept = (double)bv / ((double)tolr * (double)r11);
+    // where the pivot column is read from
+    const R* pcol = M + cp;
+    size_t pst = (size_t)ldm;
+    if (lds) {
+      pst = 1;
+      if (T.G == 1) {
+        pcol = cptr(cp);
+      } else {
+        const int owner = cp % T.G;
+        R* oslot = pub + ((size_t)(s & 1) * T.G + owner) * m;
+        if (amb) {  // the chosen column may not be its owner's candidate: publish it
+          if (T.member == owner) {
+            const R* src = cptr(cp);
+            for (int i = s + threadIdx.x; i < m; i += NT) oslot[i] = src[i];
+          }
+          T.sync();
+        }
+        pcol = oslot;
+      }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       int cs = at[s];
@@ -208,14 +309,14 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
       pos[cp] = s;
       pos[cs] = pp;
     }
-    R x0 = M[(size_t)s * ldm + cp];
+    R x0 = pcol[(size_t)s * pst];
     R beta = x0 >= R(0) ? -bv : bv;
     R scale = x0 - beta;
     R tv = (beta - x0) / beta;
     for (int i = threadIdx.x; i < m; i += NT) {
       R v = 0;
       if (i == s) v = 1;
-      else if (i > s) v = M[(size_t)i * ldm + cp] / scale;
+      else if (i > s) v = pcol[(size_t)i * pst] / scale;
       vsh[i] = v;
       if (T.member == 0) V[(size_t)i * ldv + s] = v;
     }
@@ -225,26 +326,26 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
     const R* vv = vsh + s;
     for (int c = T.cid; c < n; c += T.GT) {
       if (pos[c] <= s) continue;
-      R* col = M + (size_t)s * ldm + c;
-      R w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldm]; }, R(0));
+      R* col = cptr(c) + (size_t)s * cst;
+      R w = seq_dot<COL_B>(len, [&](int i) { return vv[i]; }, [&](int i) { return col[i * cst]; }, R(0));
       w *= tv;
       col[0] = fma(-w, vv[0], col[0]);
       R t = 0;
       int i = 1;
-      for (; i + 8 <= len; i += 8) {
-        R a[8];
+      for (; i + COL_B <= len; i += COL_B) {
+        R a[COL_B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldm];
+        for (int u = 0; u < COL_B; ++u) a[u] = col[(i + u) * cst];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < COL_B; ++u) {
           a[u] = fma(-w, vv[i + u], a[u]);
-          col[(size_t)(i + u) * ldm] = a[u];
+          col[(i + u) * cst] = a[u];
           t = fma(a[u], a[u], t);
         }
       }
       for (; i < len; ++i) {
-        R a = fma(-w, vv[i], col[(size_t)i * ldm]);
-        col[(size_t)i * ldm] = a;
+        R a = fma(-w, vv[i], col[i * cst]);
+        col[i * cst] = a;
         t = fma(a, a, t);
       }
       nrm[c] = sqrt(t);
@@ -258,13 +359,22 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
   return s;
 }
 
-// Columns c0 .. q-1 of Q = H_0 ... H_{rank-1} [I; 0] (m x q, ldq), as wg_formq: every column is
+// Columns c0 .. q-1 of Q = H_0 ... H_{rank-1} [I; 0] (m x q, ldq); columns below c0 are left
+// as they are (already formed).  Every column is
 // formed by one team thread through all reflectors, so members only synchronise at the end.
 template <int NT, class R>
 __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, int ldv, const R* tau, R* Q, int ldq,
-                               R* vsh, int c0 = 0) {
-  for (int j = c0 + T.cid; j < q; j += T.GT)
-    for (int r = 0; r < m; ++r) Q[(size_t)r * ldq + j] = (r == j) ? R(1) : R(0);
+                               R* vsh, int c0, R* lcol) {
+  // with lcol every column is formed in the member's LDS (column j at lcol + ((j - c0) / G) m)
+  // and written to Q at the end
+  if (q <= c0) return;  // nothing to form (uniform over the team)
+  const bool lds = lcol != nullptr;
+  auto cptr = [&](int j) -> R* { return lds ? lcol + (size_t)((j - c0) / T.G) * m : Q + j; };
+  const size_t cst = lds ? 1 : (size_t)ldq;
+  for (int j = c0 + T.cid; j < q; j += T.GT) {
+    R* col = cptr(j);
+    for (int r = 0; r < m; ++r) col[r * cst] = (r == j) ? R(1) : R(0);
+  }
   for (int s = rank - 1; s >= 0; --s) {
     R tv = tau[s];
     __syncthreads();
@@ -276,20 +386,25 @@ __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, 
     // a column is still e_j while s > j, so the reflector leaves it unchanged
     for (int j = c0 + T.cid; j < q; j += T.GT) {
       if (j < j0) continue;
-      R* col = Q + (size_t)s * ldq + j;
-      R w = seq_dot(len, [&](int i) { return vv[i]; }, [&](int i) { return col[(size_t)i * ldq]; }, R(0));
+      R* col = cptr(j) + (size_t)s * cst;
+      R w = seq_dot<COL_B>(len, [&](int i) { return vv[i]; }, [&](int i) { return col[i * cst]; }, R(0));
       w *= tv;
       int i = 0;
-      for (; i + 8 <= len; i += 8) {
-        R a[8];
+      for (; i + COL_B <= len; i += COL_B) {
+        R a[COL_B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(i + u) * ldq];
+        for (int u = 0; u < COL_B; ++u) a[u] = col[(i + u) * cst];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) col[(size_t)(i + u) * ldq] = fma(-w, vv[i + u], a[u]);
+        for (int u = 0; u < COL_B; ++u) col[(i + u) * cst] = fma(-w, vv[i + u], a[u]);
       }
-      for (; i < len; ++i) col[(size_t)i * ldq] = fma(-w, vv[i], col[(size_t)i * ldq]);
+      for (; i < len; ++i) col[i * cst] = fma(-w, vv[i], col[i * cst]);
     }
   }
+  if (lds)
+    for (int j = c0 + T.cid; j < q; j += T.GT) {
+      const R* col = cptr(j);
+      for (int r = 0; r < m; ++r) Q[(size_t)r * ldq + j] = col[r];
+    }
   T.sync();
 }
 
