@@ -162,6 +162,43 @@ def serve(A, n_req=200, rate=2000.0, seed=5999):
     return out
 
 
+def batched(A, count=16, nstreams=4, n_seq=4):
+    """Batching form: independent 2D systems with N log-uniform in [2048, 32768] (every 16th of
+    the 256-system draw), A_ij = exp(-r/0.5) + 0.05 delta_ij, 64 points per leaf, factored
+    concurrently (aifmm_factor_batch, nstreams streams) in FP64 at 1e-8 and FP32 at 1e-5; the
+    plain comparison factors the first n_seq of them one at a time."""
+    sizes = I.batch_sizes(256)[::256 // count]
+    kern = ("exp", 0.5, 0.05)
+    out = {"systems": len(sizes), "n_min": int(min(sizes)), "n_max": int(max(sizes)), "points": int(sum(sizes)),
+           "nstreams": nstreams}
+    for prec, tol in (("fp64", 1e-8), ("fp32", 1e-5)):
+        def build(k):
+            res = []
+            for q in range(k):
+                pts, _ = I.points_and_rhs(int(sizes[q]), 2, 1, 4000 + 16 * q)
+                res.append(A.System(pts, kern, tol, 64, 0, precision=prec))
+            return res
+        systems = build(len(sizes))
+        t0 = time.perf_counter()
+        A.factor_batch(systems, nstreams=nstreams)
+        tb = time.perf_counter() - t0
+        for s in systems:
+            s.close()
+        seq = build(n_seq)
+        t0 = time.perf_counter()
+        for s in seq:
+            s.factor()
+        ts = time.perf_counter() - t0
+        for s in seq:
+            s.close()
+        pts_seq = float(sum(sizes[:n_seq]))
+        out[prec] = {"tol": tol, "factor_s": round(tb, 3), "systems_per_s": round(len(sizes) / tb, 3),
+                     "points_per_s": round(out["points"] / tb, 1),
+                     "sequential_points_per_s": round(pts_seq / ts, 1)}
+        log(f"batched {prec}: {len(sizes)} systems in {tb:.2f} s; sequential sample {n_seq} in {ts:.2f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +208,7 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batching-form measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a fill and five plain device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -256,6 +294,8 @@ def main():
     }
     if not args.no_serve:
         out["served"] = serve(A)
+    if not args.no_batch:
+        out["batched"] = batched(A)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))

@@ -148,6 +148,14 @@ const char* aifmm_last_error(const aifmm_system* s);
 /* Free every resource of the system; NULL is accepted. */
 void aifmm_destroy(aifmm_system* s);
 
+/* Batching: factor n independent built systems concurrently (each as aifmm_factor).  nstreams
+ * worker threads, each with a HIP stream of its own, take the systems in order, so the
+ * factorizations of different systems overlap on the device; each system's own stream is
+ * restored afterwards.  Every system is attempted; returns AIFMM_OK or the first failing
+ * status (aifmm_last_error(system) tells each one's error).  AIFMM_ERR_ARG for NULL, n <= 0,
+ * nstreams <= 0 or a system listed twice; AIFMM_ERR_STATE if one is already factored. */
+aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t nstreams);
+
 /* ---- Serving: resident factorizations, continuously batched solve requests ----------------
  * The factorization does not depend on the right-hand side (Sec. 3.4: the solve reuses the
  * stored factors), so factored systems stay on the device and answer any number of requests.

@@ -76,6 +76,8 @@ def lib():
         L.aifmm_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
         L.aifmm_server_stats.restype = ctypes.c_int
         L.aifmm_server_destroy.argtypes = [vp]
+        L.aifmm_factor_batch.argtypes = [vp, i32, i32]
+        L.aifmm_factor_batch.restype = ctypes.c_int
         for f in ["aifmm_options_default", "aifmm_build", "aifmm_factor", "aifmm_solve", "aifmm_get_depth",
                   "aifmm_get_ranks", "aifmm_get_stats"]:
             getattr(L, f).restype = ctypes.c_int
@@ -200,6 +202,15 @@ class System:
         out = np.zeros(16)
         _check(lib().aifmm_get_stats(self._h, _ptr(out)), self._h)
         return dict(zip(STAT_NAMES, out[: len(STAT_NAMES)]))
+
+
+def factor_batch(systems, nstreams=4):
+    """Factor independent systems concurrently (aifmm_factor_batch)."""
+    arr = (ctypes.c_void_p * len(systems))(*[s._h for s in systems])
+    st = lib().aifmm_factor_batch(arr, len(systems), int(nstreams))
+    if st != 0:
+        bad = [i for i, s in enumerate(systems) if lib().aifmm_last_error(s._h)]
+        raise AifmmError(st, f"batched factorization failed (systems with errors: {bad[:8]})")
 
 
 class Server:

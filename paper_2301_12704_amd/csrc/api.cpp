@@ -2,7 +2,10 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <atomic>
 #include <cmath>
+#include <thread>
+#include <vector>
 #include <cstring>
 #include <new>
 #include <string>
@@ -112,6 +115,47 @@ aifmm_status aifmm_factor(aifmm_system* s) {
   });
   if (st == AIFMM_OK) s->factored = true;
   return st;
+}
+
+// Independent systems factored concurrently: nstreams worker threads, each with a stream of
+// its own, take the systems in order; each system runs on its worker's stream and gets its
+// previous stream back.  Returns the first failing status (every system is still attempted;
+// aifmm_last_error of a system tells its own error).
+aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t nstreams) {
+  if (!systems || n <= 0 || nstreams <= 0) return fail(nullptr, AIFMM_ERR_ARG, "bad systems / n / nstreams");
+  for (int i = 0; i < n; ++i) {
+    if (!systems[i]) return fail(nullptr, AIFMM_ERR_ARG, "a system is NULL");
+    if (systems[i]->factored) return fail(systems[i], AIFMM_ERR_STATE, "already factored");
+    for (int j = 0; j < i; ++j)
+      if (systems[j] == systems[i]) return fail(nullptr, AIFMM_ERR_ARG, "a system is listed twice");
+  }
+  int nw = std::min<int>(nstreams, n);
+  std::atomic<int> next{0};
+  std::vector<aifmm_status> st(n, AIFMM_OK);
+  std::vector<std::thread> pool;
+  std::atomic<int> stream_fail{0};
+  for (int w = 0; w < nw; ++w)
+    pool.emplace_back([&] {
+      hipStream_t own = nullptr;
+      if (hipSetDevice(systems[0]->device) != hipSuccess ||
+          hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) {
+        stream_fail = 1;
+        return;
+      }
+      for (int i; (i = next.fetch_add(1)) < n;) {
+        aifmm_system* s = systems[i];
+        hipStream_t old = s->stream;
+        s->stream = own;
+        st[i] = aifmm_factor(s);
+        s->stream = old;
+      }
+      (void)hipStreamDestroy(own);
+    });
+  for (auto& t : pool) t.join();
+  if (stream_fail) return fail(nullptr, AIFMM_ERR_DEVICE, "stream creation failed");
+  for (int i = 0; i < n; ++i)
+    if (st[i] != AIFMM_OK) return st[i];
+  return AIFMM_OK;
 }
 
 aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx) {

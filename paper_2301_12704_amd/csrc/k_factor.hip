@@ -1115,7 +1115,25 @@ static bool verbose() {
   return v && *v && *v != '0';
 }
 
+static void factor_levels(aifmm_system& s);
+
 void factor_system(aifmm_system& s) {
+  // buffers released during the factorization are freed after its last synchronization
+  struct Defer {
+    std::vector<void*> ptrs;
+    std::vector<void*>* prev;
+    hipStream_t st;
+    Defer(hipStream_t s_) : prev(g_defer_free), st(s_) { g_defer_free = &ptrs; }
+    ~Defer() {
+      g_defer_free = prev;
+      (void)hipStreamSynchronize(st);
+      for (void* p : ptrs) (void)hipFree(p);
+    }
+  } defer(s.stream);
+  factor_levels(s);
+}
+
+static void factor_levels(aifmm_system& s) {
   auto t0 = std::chrono::steady_clock::now();
   auto since = [&](std::chrono::steady_clock::time_point a) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();

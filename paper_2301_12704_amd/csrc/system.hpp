@@ -38,6 +38,11 @@ struct Error {
       throw ::aifmm::Error{AIFMM_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
   } while (0)
 
+// While a factorization runs on this thread, buffers released are only collected here and
+// freed when it ends: hipFree waits for the whole device, which would stall the other systems'
+// streams in a batched factorization.
+inline thread_local std::vector<void*>* g_defer_free = nullptr;
+
 // Device buffer owned by the system (hipMalloc / hipFree).
 template <class T>
 struct DBuf {
@@ -53,7 +58,10 @@ struct DBuf {
   }
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (g_defer_free) g_defer_free->push_back((void*)p);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
   }
