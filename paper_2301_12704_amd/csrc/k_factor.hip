@@ -450,8 +450,10 @@ __global__ void __launch_bounds__(WG) k_elim_trsm(LevelPtrs P, const int* __rest
 // is the ascending-k fused multiply-add sum, exactly as the sequential product.  The tiles of
 // the next k chunk are loaded into registers while the current chunk is multiplied from LDS.
 // In the precision form (F32) the tiles are converted to FP32 and multiplied with FP32 MFMA
-// 16x16x4 (FP32 accumulation); the FP64 block store receives the FP32 products.
-constexpr int ST = 64, SK = 32, BL = ST / 32;
+// 16x16x4 (FP32 accumulation); the FP64 block store receives the FP32 products.  K chunks of
+// 16 keep the register use low enough for five workgroups per CU, whose prologues, barriers
+// and scatter epilogues then overlap the others' MFMA streams.
+constexpr int ST = 64, SK = 16, BL = ST / 32;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 __device__ inline dbl4 mfma16(double a, double b, dbl4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
@@ -459,7 +461,8 @@ __device__ inline flt4 mfma16(float a, float b, flt4 c) { return __builtin_amdgc
 template <bool F32> struct MfmaT { using T = double; using T4 = dbl4; };
 template <> struct MfmaT<true> { using T = float; using T4 = flt4; };
 template <bool F32>
-__global__ void __launch_bounds__(WG) k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int tiles_c) {
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5)))
+k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int tiles_c) {
   using TT = typename MfmaT<F32>::T;
   using TT4 = typename MfmaT<F32>::T4;
   if (flag[0]) return;
