@@ -140,6 +140,11 @@ __global__ void __launch_bounds__(WG) k_top_diag(const double* __restrict__ A, i
   }
 }
 
+__global__ void k_zero(double* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 // b (N x nrhs column-major, original order) -> rhs rows in tree order (row-major)
 __global__ void k_perm_in(const double* b, int64_t ldb, const int64_t* perm, int64_t N, int nr, double* out) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,18 +353,19 @@ static void launch_rows(int ntask, const STask* t, const double* fslab, const do
 }
 
 // Solve with tree-ordered row-major right-hand sides (N x nr) on the device; x may alias nothing.
-void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x) {
+// The launch sequence of one solve (buffers already sized for nr): kernels and one
+// device-to-device copy only, so it can also be captured into a graph.
+static void solve_tree_launch(aifmm_system& s, const double* rhs, int nr, double* x) {
   hipStream_t st = s.stream;
   int L = s.L;
   int64_t N = s.N;
-  ensure_solve_buffers(s, nr);
   SolveCache& sc = s.sc;
   // rhs of the X rows of level L is the input; rhs of Z rows of level l = X rows of level l-1
   AIFMM_HIP(hipMemcpyAsync(x, rhs, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, st));
   auto Xrows = [&](int l) { return l == L ? x : sc.R[l].p; };   // rhs, overwritten in place
   for (int l = L; l >= 2; --l) {
     int64_t K = s.lev[l].koff[s.lev[l].nb];
-    if (K > 0) AIFMM_HIP(hipMemsetAsync(sc.R[l - 1].p, 0, sizeof(double) * K * nr, st));
+    if (K > 0) hipLaunchKernelGGL(k_zero, dim3(cdiv(K * nr, WG)), dim3(WG), 0, st, sc.R[l - 1].p, K * nr);
   }
   // the forward sweep keeps rhs(X^{(L)}) in x; the backward sweep overwrites x with sol(x^{(L)})
   // box by box after every read of rhs(X_b) (the forward sweep has finished by then)
@@ -409,7 +415,17 @@ void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x) {
     }
   }
   launch_check("backward sweep");
-  AIFMM_HIP(hipStreamSynchronize(st));
+}
+
+void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x) {
+  ensure_solve_buffers(s, nr);
+  solve_tree_launch(s, rhs, nr, x);
+  AIFMM_HIP(hipStreamSynchronize(s.stream));
+}
+
+static bool graphs_off() {
+  const char* v = getenv("AIFMM_NO_GRAPH");
+  return v && *v && *v != '0';
 }
 
 void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx, bool b_dev,
@@ -429,7 +445,35 @@ void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
     bsrc = G.bin.p;
   }
   hipLaunchKernelGGL(k_perm_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, bsrc, ldb, s.d_perm.p, N, nr, G.bt.p);
-  solve_tree(s, G.bt.p, nr, G.xt.p);
+  ensure_solve_buffers(s, nr);
+  SolveCache& sc = s.sc;
+  if (graphs_off() || st == nullptr) {  // the legacy default stream cannot be captured
+    solve_tree_launch(s, G.bt.p, nr, G.xt.p);
+  } else {
+    // the solve's few hundred launches replayed from one graph, captured for this column count
+    // and these buffers (recaptured when either changes; a factorization resets it)
+    if (!sc.graph.exec || sc.graph.nr != nr || sc.graph.in != G.bt.p || sc.graph.out != G.xt.p ||
+        sc.graph.cap != sc.nr_cap) {
+      sc.graph.reset();
+      hipGraph_t g = nullptr;
+      AIFMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        solve_tree_launch(s, G.bt.p, nr, G.xt.p);
+      } catch (...) {
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      AIFMM_HIP(hipStreamEndCapture(st, &g));
+      sc.graph.graph = g;
+      AIFMM_HIP(hipGraphInstantiate(&sc.graph.exec, g, nullptr, nullptr, 0));
+      sc.graph.nr = nr;
+      sc.graph.in = G.bt.p;
+      sc.graph.out = G.xt.p;
+      sc.graph.cap = sc.nr_cap;
+    }
+    AIFMM_HIP(hipGraphLaunch(sc.graph.exec, st));
+  }
   if (x_dev) {
     hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, G.xt.p, s.d_perm.p, N, nr, x, ldx);
   } else {

@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/aifmm.h"
@@ -190,8 +191,38 @@ struct SolveLevel {
   std::vector<int64_t> woff;  // rows of w = Piv^{-1} rhs per box
   int64_t grows = 0;          // rows of the largest gathered colour
 };
+// A captured solve (graph and its executable), released with the cache.
+struct SolveGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int nr = 0, cap = 0;
+  const double* in = nullptr;
+  const double* out = nullptr;
+  SolveGraph() = default;
+  SolveGraph(const SolveGraph&) = delete;
+  SolveGraph& operator=(const SolveGraph&) = delete;
+  SolveGraph(SolveGraph&& o) noexcept { *this = std::move(o); }
+  SolveGraph& operator=(SolveGraph&& o) noexcept {
+    if (this != &o) {
+      reset();
+      graph = o.graph; exec = o.exec; nr = o.nr; cap = o.cap; in = o.in; out = o.out;
+      o.graph = nullptr; o.exec = nullptr;
+    }
+    return *this;
+  }
+  ~SolveGraph() { reset(); }
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    nr = 0;
+  }
+};
+
 struct SolveCache {
   bool built = false;
+  SolveGraph graph;
   int nr_cap = 0;
   // blocked triangular solves of the top system: row permutation of its LU, and the update
   // tiles of every 64-row block step (forward below the block, backward above it)
