@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 
 #include "dense_wg.hpp"
 #include "team.hpp"
@@ -1103,6 +1104,12 @@ static void count_flops(aifmm_system& s, int l) {
   }
 }
 
+static int lds_gmax() {
+  const char* v = getenv("AIFMM_LDS_TEAM_MAX");
+  int g = v && *v ? atoi(v) : 64;
+  return std::max(1, std::min(64, g));
+}
+
 static bool lds_off() {
   const char* v = getenv("AIFMM_NO_LDS_COLUMNS");
   return v && *v && *v != '0';
@@ -1226,7 +1233,7 @@ static void factor_levels(aifmm_system& s) {
     const size_t lds_max = 152 * 1024;
     if (base > lds_max) throw Error{AIFMM_ERR_CAPACITY, "box size too large for the compression kernel"};
     AIFMM_HIP(hipFuncSetAttribute(kcomp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
-    constexpr int GMAX = 32;
+    constexpr int GMAX = 64;
     int coop_g = 0, coop_l = 0;
     {
       int dev = 0, coop = 0, ncu = 0, per_g = 0, per_l = 0;
@@ -1244,22 +1251,23 @@ static void factor_levels(aifmm_system& s) {
       G = 1;
       lcols = 0;
       shm = base;
-      // LDS columns pay off for small teams only: a larger team's per-step reductions and
-      // barrier cost more than the column traffic it saves
+      // the smallest team whose share of the columns fits in LDS (up to 64 members)
       if (!lds_off())
-        for (int g = 1; g <= 8; ++g) {
+        for (int g = 1; g <= lds_gmax(); ++g) {
           if (g > 1 && (coop_l == 0 || (int64_t)ne * g > coop_l)) break;
           int cols = (2 * cap + g - 1) / g;
-          if (base + (size_t)cols * cap * rs <= lds_max) {
+          size_t need = base + (size_t)cols * (cap | 1) * rs;
+          if (need <= lds_max) {
             G = g;
             lcols = cols;
-            shm = base + (size_t)cols * cap * rs;
+            shm = need;
             return;
           }
         }
       if (coop_g > 0 && ne > 0)
         G = std::max(1, std::min({16, coop_g / ne, (int)((int64_t)2 * cap * cap / 49152)}));
     };
+    std::map<std::pair<int, int>, int> team_hist;  // (team size, LDS columns) -> rounds
     DBuf<unsigned> d_ctr;
     DBuf<Cand> d_part;
     DBuf<int> d_abort;
@@ -1290,6 +1298,9 @@ static void factor_levels(aifmm_system& s) {
         int G = 1, lcols = 0;
         size_t shm = base;
         team_shape(ne, G, lcols, shm);
+        if (verbose()) {
+          ++team_hist[{G, lcols > 0 ? 1 : 0}];
+        }
         if (G == 1) {
           if (f32)
             hipLaunchKernelGGL(k_compress<float>, dim3(ne), dim3(CT), shm, st, P, er, ne, ws.p, wsz, cap, s.tol,
@@ -1363,7 +1374,12 @@ static void factor_levels(aifmm_system& s) {
       (void)hipEventDestroy(pr.second);
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    if (verbose()) fprintf(stderr, "[aifmm] level %d factored in %.3f s (%zu compressions)\n", l, since(tl), rent.size());
+    if (verbose()) {
+      fprintf(stderr, "[aifmm] level %d factored in %.3f s (%zu compressions), cap %d, coop %d/%d; rounds by team:", l,
+              since(tl), rent.size(), cap, coop_g, coop_l);
+      for (auto& kv : team_hist) fprintf(stderr, " G%d%s:%d", kv.first.first, kv.first.second ? "L" : "", kv.second);
+      fprintf(stderr, "\n");
+    }
     {
       std::vector<int> tr = d_tr.download(st, rent.size() * 6);
       std::vector<double> trr = d_trr.download(st, rent.size() * 8);

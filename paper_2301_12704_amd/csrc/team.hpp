@@ -204,7 +204,8 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
   // column storage: with lcol the member's own columns are copied to its LDS (column c at
   // lcol + (c / G) m, rows contiguous) and M is only read once; otherwise M in place
   const bool lds = lcol != nullptr;
-  auto cptr = [&](int c) -> R* { return lds ? lcol + (size_t)(c / T.G) * m : M + c; };
+  const int lstride = m | 1;  // odd column stride: the lanes of a wave hit distinct LDS banks
+  auto cptr = [&](int c) -> R* { return lds ? lcol + (size_t)(c / T.G) * lstride : M + c; };
   const size_t cst = lds ? 1 : (size_t)ldm;
   double kept = 0.0, next = 0.0;
   int smax = m < n ? m : n;
@@ -369,7 +370,8 @@ __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, 
   // and written to Q at the end
   if (q <= c0) return;  // nothing to form (uniform over the team)
   const bool lds = lcol != nullptr;
-  auto cptr = [&](int j) -> R* { return lds ? lcol + (size_t)((j - c0) / T.G) * m : Q + j; };
+  const int lstride = m | 1;
+  auto cptr = [&](int j) -> R* { return lds ? lcol + (size_t)((j - c0) / T.G) * lstride : Q + j; };
   const size_t cst = lds ? 1 : (size_t)ldq;
   for (int j = c0 + T.cid; j < q; j += T.GT) {
     R* col = cptr(j);
