@@ -30,10 +30,10 @@ FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
-def schur_traffic(config):
-    """HBM bytes per k_elim_schur launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-    (profiles/k_elim_schur_c2_traffic.json), or None when they were taken on another workload or
-    on a different version of the kernel's source."""
+def schur_counters(config):
+    """The committed rocprofv3 counter record of k_elim_schur (profiles/k_elim_schur_c2_traffic.json:
+    HBM bytes per launch from FETCH_SIZE / WRITE_SIZE, MFMA busy fraction), or None when it was
+    taken on another workload or on a different version of the kernel's source."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "k_elim_schur_c2_traffic.json")))
@@ -46,7 +46,7 @@ def schur_traffic(config):
         return None
     if hashlib.sha256(src[s:e].encode()).hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec
 
 
 def cpu_baseline(cfg, n_sample=8192, depth=4):
@@ -257,6 +257,7 @@ def main():
     peak = min(FP64_PEAK_TFLOPS, ai * HBM_PEAK_GBS / 1000.0)
     bound = "mfma" if FP64_PEAK_TFLOPS <= ai * HBM_PEAK_GBS / 1000.0 else "hbm"
     value = med("factor") + med("gmres")
+    counters = schur_counters(args.config)
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -285,7 +286,8 @@ def main():
         "roofline": {"kernel": "k_elim_schur (Schur fill-in update)", "bound": bound,
                      "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4) if peak > 0 else None,
-                     "traffic": schur_traffic(args.config), "traffic_unit": "bytes per launch",
+                     "traffic": (counters or {}).get("traffic_bytes_per_launch"), "traffic_unit": "bytes per launch",
+                     "mfma_busy": (counters or {}).get("mfma_busy_fraction"),
                      "flops_per_launch": schur_flops / max(st["schur_launches"], 1),
                      "avg_launch_s": schur_s / max(st["schur_launches"], 1),
                      "arith_intensity": round(ai, 3)},
