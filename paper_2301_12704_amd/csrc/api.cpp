@@ -108,6 +108,7 @@ aifmm_status aifmm_build(const double* points, int64_t n, aifmm_kernel kernel, d
 
 aifmm_status aifmm_factor(aifmm_system* s) {
   if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  std::lock_guard<std::mutex> lk(s->use);
   if (s->factored) return fail(s, AIFMM_ERR_STATE, "already factored");
   aifmm_status st = guarded(s, [&] {
     AIFMM_HIP(hipSetDevice(s->device));
@@ -160,6 +161,7 @@ aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t
 
 aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx) {
   if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  std::lock_guard<std::mutex> lk(s->use);
   if (!s->factored) return fail(s, AIFMM_ERR_STATE, "solve before factor");
   if (!b || !x || nrhs <= 0 || ldb < s->N || ldx < s->N) return fail(s, AIFMM_ERR_ARG, "bad b/x/nrhs/ld");
   if (nrhs > 4096) return fail(s, AIFMM_ERR_ARG, "nrhs too large");
@@ -171,6 +173,7 @@ aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t
 
 aifmm_status aifmm_matvec(aifmm_system* s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy) {
   if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  std::lock_guard<std::mutex> lk(s->use);
   if (!x || !y || nrhs <= 0 || ldx < s->N || ldy < s->N || nrhs > 4096) return fail(s, AIFMM_ERR_ARG, "bad x/y/nrhs/ld");
   return guarded(s, [&] {
     AIFMM_HIP(hipSetDevice(s->device));
@@ -181,6 +184,7 @@ aifmm_status aifmm_matvec(aifmm_system* s, const double* x, int64_t nrhs, int64_
 aifmm_status aifmm_gmres(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int32_t restart,
                          int32_t maxit, double* x, int64_t ldx, int32_t* iters, double* relres) {
   if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  std::lock_guard<std::mutex> lk(s->use);
   if (!s->factored) return fail(s, AIFMM_ERR_STATE, "gmres before factor");
   if (!b || !x || nrhs <= 0 || ldb < s->N || ldx < s->N || nrhs > 4096 || !(rtol > 0.0) || restart <= 0 || maxit <= 0)
     return fail(s, AIFMM_ERR_ARG, "bad b/x/nrhs/ld/rtol/restart/maxit");

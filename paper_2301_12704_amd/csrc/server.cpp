@@ -104,6 +104,7 @@ struct aifmm_server {
       }
       aifmm_status st = AIFMM_OK;
       std::string msg;
+      std::lock_guard<std::mutex> use(s.use);  // other calls on this system wait for the batch
       try {
         if (rtol > 0)
           aifmm::gmres_system(s, B.data(), cols, N, rtol, 30, 500, X.data(), N, its.data(), rel.data(), false, false);
@@ -177,6 +178,7 @@ aifmm_status aifmm_server_create(aifmm_system* const* systems, int32_t nsys, siz
       delete srv;
       return AIFMM_ERR_DEVICE;
     }
+    std::lock_guard<std::mutex> use(srv->sys[i]->use);
     srv->old_streams.push_back(srv->sys[i]->stream);
     srv->own_streams.push_back(st);
     srv->sys[i]->stream = st;
@@ -248,6 +250,7 @@ void aifmm_server_destroy(aifmm_server* srv) {
   srv->cv_mem.notify_all();
   for (auto& t : srv->workers) t.join();
   for (size_t i = 0; i < srv->sys.size(); ++i) {
+    std::lock_guard<std::mutex> use(srv->sys[i]->use);
     (void)hipStreamSynchronize(srv->own_streams[i]);
     srv->sys[i]->stream = srv->old_streams[i];
     (void)hipStreamDestroy(srv->own_streams[i]);

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <cstdio>
 #include <string>
 #include <utility>
@@ -262,6 +263,7 @@ struct aifmm_system {
   hipStream_t stream = nullptr;
   bool factored = false;
   std::string err;
+  std::mutex use;                  // held by every call that runs work on the system
   // tree
   aifmm::DBuf<double> d_pts;      // points in tree order, N x d
   aifmm::DBuf<int64_t> d_perm;    // tree position -> original index

@@ -103,3 +103,22 @@ def test_server_argument_errors():
         srv.close()
     with pytest.raises(A.AifmmError):
         A.Server([sy[0][0], sy[0][0]])              # a system listed twice
+
+
+def test_admission_by_memory_budget():
+    """With a budget smaller than any batch, batches are admitted one at a time (a batch alone
+    is always admitted): the peak admitted workspace is one batch's, and results are unchanged."""
+    sy = _systems()
+    srv = A.Server([s for s, _ in sy], hbm_budget=1, rtol=0.0, max_cols=8)
+    try:
+        reqs = [(q % 2, _rhs(sy[q % 2][0].N, 1 + q % 8, 400 + q)) for q in range(10)]
+        tickets = [srv.submit(sys, b) for sys, b in reqs]
+        for (sys, b), t in zip(reqs, tickets):
+            x, _, bc, _, _ = srv.wait(t)
+            np.testing.assert_array_equal(x, sy[sys][0].solve(b))
+        st = srv.stats()
+        one_batch_max = max(s.N for s, _ in sy) * 8 * 8 * 8   # N x cols x 8 bytes x 8 vectors, cols <= 8
+        print("peak admitted bytes", st["peak_bytes"], "bound", one_batch_max)
+        assert 0 < st["peak_bytes"] <= one_batch_max
+    finally:
+        srv.close()
