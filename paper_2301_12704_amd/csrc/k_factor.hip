@@ -1106,8 +1106,8 @@ static void count_flops(aifmm_system& s, int l) {
 
 static int lds_gmax() {
   const char* v = getenv("AIFMM_LDS_TEAM_MAX");
-  int g = v && *v ? atoi(v) : 64;
-  return std::max(1, std::min(64, g));
+  int g = v && *v ? atoi(v) : 128;
+  return std::max(1, std::min(128, g));
 }
 
 static bool lds_off() {
@@ -1233,7 +1233,7 @@ static void factor_levels(aifmm_system& s) {
     const size_t lds_max = 152 * 1024;
     if (base > lds_max) throw Error{AIFMM_ERR_CAPACITY, "box size too large for the compression kernel"};
     AIFMM_HIP(hipFuncSetAttribute(kcomp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
-    constexpr int GMAX = 64;
+    constexpr int GMAX = 128;
     int coop_g = 0, coop_l = 0;
     {
       int dev = 0, coop = 0, ncu = 0, per_g = 0, per_l = 0;
@@ -1251,7 +1251,7 @@ static void factor_levels(aifmm_system& s) {
       G = 1;
       lcols = 0;
       shm = base;
-      // the smallest team whose share of the columns fits in LDS (up to 64 members)
+      // the smallest team whose share of the columns fits in LDS (up to 128 members)
       if (!lds_off())
         for (int g = 1; g <= lds_gmax(); ++g) {
           if (g > 1 && (coop_l == 0 || (int64_t)ne * g > coop_l)) break;
