@@ -121,6 +121,7 @@ Mat lu_solve(const Mat& LU, const std::vector<int>& perm, const Mat& B, int coun
 // Householder QR with column pivoting (Q10 reading of the RRQR with threshold eps_A,
 // Sec. 3.2.1): trailing column norms recomputed exactly every step, ties (within a relative
 // 1e-11) to the lowest column, stop at the smallest k with |R_{k+1,k+1}| <= tol |R_11|.
+// Norms and reflector products are row sums in the order of rowsum16.
 struct Cpqr {
   int rank = 0;
   int m = 0;
@@ -133,6 +134,19 @@ struct Cpqr {
 };
 
 const double kTieTol = 1e-11;
+
+// Sum over the rows i = a .. m-1 of x(i) y(i) in the fixed order of reading 28 (the paper fixes
+// no order): sixteen partial fused multiply-add chains, chain q taking the rows i = q (mod 16)
+// in ascending order, then the pairwise tree ((t0 + t1) + (t2 + t3)) + ... over the chains.
+// Every row sum of the pivoted QR and of the Q formation is taken this way.
+template <class X, class Y>
+double rowsum16(int a, int m, X x, Y y) {
+  double t[16] = {0.0};
+  for (int i = a; i < m; ++i) t[i % 16] = std::fma(x(i), y(i), t[i % 16]);
+  for (int d = 1; d < 16; d *= 2)
+    for (int q = 0; q < 16; q += 2 * d) t[q] = t[q] + t[q + d];
+  return t[0];
+}
 
 Cpqr cpqr(const Mat& M, double tol) {
   Cpqr out;
@@ -151,8 +165,7 @@ Cpqr cpqr(const Mat& M, double tol) {
     std::vector<double> nrm(n, 0.0);
     double mx = -1.0;
     for (int j = s; j < n; ++j) {
-      double t = 0.0;
-      for (int i = s; i < m; ++i) t = std::fma(A.at(i, j), A.at(i, j), t);
+      double t = rowsum16(s, m, [&](int i) { return A.at(i, j); }, [&](int i) { return A.at(i, j); });
       nrm[j] = std::sqrt(t);
       mx = std::max(mx, nrm[j]);
     }
@@ -185,8 +198,7 @@ Cpqr cpqr(const Mat& M, double tol) {
       tau = (beta - x0) / beta;
     }
     for (int j = s + 1; j < n; ++j) {
-      double w = 0.0;
-      for (int i = s; i < m; ++i) w = std::fma(v[i], A.at(i, j), w);
+      double w = rowsum16(s, m, [&](int i) { return v[i]; }, [&](int i) { return A.at(i, j); });
       w *= tau;
       for (int i = s; i < m; ++i) A.at(i, j) = std::fma(-w, v[i], A.at(i, j));
     }
@@ -212,8 +224,7 @@ Mat cpqr_q(const Cpqr& f, int q) {
     const std::vector<double>& v = f.v[s];
     double tau = f.tau[s];
     for (int j = 0; j < q; ++j) {
-      double w = 0.0;
-      for (int i = s; i < m; ++i) w = std::fma(v[i], Q.at(i, j), w);
+      double w = rowsum16(s, m, [&](int i) { return v[i]; }, [&](int i) { return Q.at(i, j); });
       w *= tau;
       for (int i = s; i < m; ++i) Q.at(i, j) = std::fma(-w, v[i], Q.at(i, j));
     }

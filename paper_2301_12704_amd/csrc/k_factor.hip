@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   RT* nV = w + 11 * c2;
   RT* nUj = w + 12 * c2;
   RT* nVj = w + 13 * c2;
-  RT* t1 = w + 14 * c2;      // cap x 2cap
+  RT* t1 = w + 14 * c2;      // cap x 2cap; column storage of the QRs without LDS columns
   RT* t2 = w + 16 * c2;
   RT* tau = w + 17 * c2;     // 4 * cap
   RT* nrm = tau + 4 * cap;   // 2 * cap
@@ -135,31 +135,31 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     int ld = ki + nj;
     t_copy(T, ni, ki, U_i, ni, M, ld);
     t_copy(T, ni, nj, Fij, nj, M + ki, ld);
-    int r1 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr, lcol, pub);
+    int r1 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr, lcol, pub, t1);
     // RRQR2: [U_j | P2P_ji] = U~_j L_ji
     ld = kj + ni;
     t_copy(T, nj, kj, U_j, nj, M, ld);
     t_copy(T, nj, ni, Fji, ni, M + kj, ld);
-    int r2 = t_cpqr(T, nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2, lcol, pub);
+    int r2 = t_cpqr(T, nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2, lcol, pub, t1);
     // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
-    t_formq(T, ni, r1, r1, V1, cap, tau, nU, cap, vsh, 0, lcol);
+    t_formq(T, ni, r1, r1, V1, cap, tau, nU, cap, vsh, 0, lcol, t1);
     ld = kj + r1;
     t_copy(T, nj, kj, V_j, nj, M, ld);
     t_gemm(T, nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
-    int r3 = t_cpqr(T, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, vsh, pos, at, trr + 4, lcol, pub);
+    int r3 = t_cpqr(T, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, vsh, pos, at, trr + 4, lcol, pub, t1);
     // RRQR4: [V_i | L~_ji^*]
-    t_formq(T, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh, 0, lcol);
+    t_formq(T, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh, 0, lcol, t1);
     ld = ki + r2;
     t_copy(T, ni, ki, V_i, ni, M, ld);
     t_gemm(T, ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, M + ki, ld);
-    int r4 = t_cpqr(T, ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, vsh, pos, at, trr + 6, lcol, pub);
+    int r4 = t_cpqr(T, ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, vsh, pos, at, trr + 6, lcol, pub, t1);
     int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
     // new orthonormal bases: columns beyond a tolerance rank are further columns of the same
     // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed)
-    t_formq(T, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1, lcol);
-    t_formq(T, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh, 0, lcol);
-    t_formq(T, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2, lcol);
-    t_formq(T, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh, 0, lcol);
+    t_formq(T, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1, lcol, t1);
+    t_formq(T, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh, 0, lcol, t1);
+    t_formq(T, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2, lcol, t1);
+    t_formq(T, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh, 0, lcol, t1);
     // coefficients by projection: U_i = U~_i L_i, V_i = V~_i R_i, ...
     t_gemm(T, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
     t_gemm(T, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
@@ -213,14 +213,14 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
     }
     T.sync();
-    int r5 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr, lcol, pub);
+    int r5 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr, lcol, pub, t1);
     // RRQR: [U_i | M2P_ir] = U~_i L_ir
     t_copy(T, ni, ki, U_i, ni, M, ld);
     t_copy(T, ni, kr, M2P, nr, M + ki, ld);
-    int r6 = t_cpqr(T, ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2, lcol, pub);
+    int r6 = t_cpqr(T, ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2, lcol, pub, t1);
     int kin = r5 > r6 ? r5 : r6;
-    t_formq(T, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol);
-    t_formq(T, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol);
+    t_formq(T, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol, t1);
+    t_formq(T, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, t1);
     t_gemm(T, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
     t_gemm(T, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
     // A_ri := A_ri R_i^* + P2L_ri V~_i

@@ -3,8 +3,9 @@
 // barrier is __syncthreads().  Team routines distribute their work over the G * NT team
 // threads and end with a team barrier, so results are visible to every member on return.
 //
-// The arithmetic of every output element is done by one thread in the same order as the
-// single-workgroup routines of dense_wg.hpp, so results do not depend on G.
+// Every output element is computed in one fixed order whatever G is: by one thread in the
+// order of the single-workgroup routines of dense_wg.hpp, or, for the row sums of the pivoted
+// QR and the Q formation, by one group of 16 lanes in the fixed chain-and-tree order below.
 #pragma once
 #include "dense_wg.hpp"
 
@@ -178,56 +179,81 @@ __device__ inline PivState wg_pivmerge(PivState x, R keep, PivState* sh) {
   return r;
 }
 
+// Row sums of the pivoted QR and of the Q formation are taken in one fixed order: sixteen
+// partial fused multiply-add chains over the rows, chain q holding the rows i = q (mod 16) in
+// ascending order, then the pairwise tree ((t0 + t1) + (t2 + t3)) + ... over the chains.  A
+// group of PL = 16 lanes owns a column: lane q runs chain q, and the butterfly of lane_sum16
+// leaves the tree's sum on all 16 lanes (IEEE addition is commutative, so both lanes of a
+// pair form the same bits).  A column's dependent chain is then m / 16 terms long instead of m.
+constexpr int PL = 16;
+template <class R>
+__device__ inline R lane_sum16(R t) {
+  t = t + __shfl_xor(t, 1, PL);
+  t = t + __shfl_xor(t, 2, PL);
+  t = t + __shfl_xor(t, 4, PL);
+  t = t + __shfl_xor(t, 8, PL);
+  return t;
+}
+// loads in flight per lane in the column passes
+constexpr int COL_B = 4;
+
 // Householder QR with column pivoting of the m x n row-major M, truncated at the first step
 // whose pivot column norm is <= tol times the first one (RRQR with threshold eps_A of
 // Sec. 3.2.1).  Pivot: the lowest-position column whose trailing norm is within a relative
 // band (1e-11 in FP64, 2e-6 in FP32) of the largest, so norms equal in exact arithmetic
 // (orthonormal basis columns) tie whatever the rounding.  Trailing norms are recomputed every
-// step as sums over the rows in ascending order (formed while the previous reflector is
-// applied; never downdated).  Columns stay where they are: column c is owned by member c mod G
-// (columns interleave across members), and its pivot-order position is tracked in pos / at
-// (LDS of every member, n entries each), so a swap of positions s and p is the column exchange
-// of the textbook algorithm.  The pivot column is read by every member to form the reflector
-// (vsh: m entries of LDS).  Reflector s is written to column s of V (ldv) with V[s][s] = 1, its
-// scale to tau[s]; nrm (device memory, n) holds each column's trailing norm.  M's pivot columns
-// are left as they were when chosen (R is not formed).  Returns the rank; ratio (if given)
-// receives |R_kk| / (tol |R_11|) of the last kept and of the first rejected pivot.
-// column passes of the pivoted QR and Q formation keep this many loads in flight per thread
-constexpr int COL_B = SEQ_B;
+// step as row sums (formed while the previous reflector is applied; never downdated).
+// Columns stay where they are: column c is owned by member c mod G and, inside it, by the
+// lane group (c / G) mod (NT / 16); its pivot-order position is tracked in pos / at (LDS of
+// every member, n entries each), so a swap of positions s and p is the column exchange of the
+// textbook algorithm.  M is read once, into column-major storage: the member's LDS (lcol,
+// column c at lcol + (c / G) (m | 1)) or, without lcol, the workspace gcol (column c at
+// gcol + c m, m n entries).  With LDS columns in a team each member publishes its candidate
+// column in pub before the exchange.  The pivot column is read by every member to form the
+// reflector (vsh: m entries of LDS).  Reflector s is written to row s of V (ldv) with
+// V[s][s] = 1, its scale to tau[s]; nrm (device memory, n) holds each column's trailing norm.
+// M is left unchanged (R is not formed).  Returns the rank; ratio (if given) receives
+// |R_kk| / (tol |R_11|) of the last kept and of the first rejected pivot.
 template <int NT, class R>
-__device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double tol, R* V, int ldv, R* tau, R* nrm,
-                             ValIdx* shv, R* vsh, int* pos, int* at, double* ratio, R* lcol, R* pub) {
+__device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, double tol, R* V, int ldv, R* tau,
+                             R* nrm, ValIdx* shv, R* vsh, int* pos, int* at, double* ratio, R* lcol, R* pub,
+                             R* gcol) {
   __shared__ PivState psh[NT / WAVE + 1];
+  constexpr int NGW = NT / PL;  // lane groups per workgroup
   // pivot ties: norms within a relative band of the largest (1e-11 in FP64, 2e-6 in FP32)
   const R keep = sizeof(R) == 4 ? R(1.0 - 2e-6) : R(1.0 - 1e-11);
   const R tolr = (R)tol;
-  // column storage: with lcol the member's own columns are copied to its LDS (column c at
-  // lcol + (c / G) m, rows contiguous) and M is only read once; otherwise M in place
   const bool lds = lcol != nullptr;
-  const int lstride = m | 1;  // odd column stride: the lanes of a wave hit distinct LDS banks
-  auto cptr = [&](int c) -> R* { return lds ? lcol + (size_t)(c / T.G) * lstride : M + c; };
-  const size_t cst = lds ? 1 : (size_t)ldm;
+  const int lstride = m | 1;  // odd column stride: the groups of a wave start on distinct banks
+  auto colp = [&](int c) -> R* { return lds ? lcol + (size_t)(c / T.G) * lstride : gcol + (size_t)c * m; };
+  const int lane = (int)threadIdx.x & (PL - 1), grp = (int)threadIdx.x / PL;
+  const int nloc = (n - T.member + T.G - 1) / T.G;  // own columns: c = member + G lc
   double kept = 0.0, next = 0.0;
   int smax = m < n ? m : n;
   R r11 = 0;
-  if (lds)
-    for (int c = T.cid; c < n; c += T.GT) {
-      R* d = cptr(c);
-      const R* g = M + c;
-      int i = 0;
-      for (; i + SEQ_B <= m; i += SEQ_B) {
-        R a[SEQ_B];
+  // own columns into column storage, with their norms
+  for (int lc = grp; lc < nloc; lc += NGW) {
+    const int c = T.member + T.G * lc;
+    R* d = colp(c);
+    R t = 0;
+    for (int i0 = lane; i0 < m; i0 += PL * COL_B) {
+      R a[COL_B];
 #pragma unroll
-        for (int u = 0; u < SEQ_B; ++u) a[u] = g[(size_t)(i + u) * ldm];
-#pragma unroll
-        for (int u = 0; u < SEQ_B; ++u) d[i + u] = a[u];
+      for (int u = 0; u < COL_B; ++u) {
+        int i = i0 + PL * u;
+        a[u] = i < m ? M[(size_t)i * ldm + c] : R(0);
       }
-      for (; i < m; ++i) d[i] = g[(size_t)i * ldm];
+#pragma unroll
+      for (int u = 0; u < COL_B; ++u) {
+        int i = i0 + PL * u;
+        if (i < m) {
+          d[i] = a[u];
+          t = fma(a[u], a[u], t);
+        }
+      }
     }
-  for (int c = T.cid; c < n; c += T.GT) {
-    const R* col = cptr(c);
-    R t = seq_dot<COL_B>(m, [&](int i) { return col[i * cst]; }, [&](int i) { return col[i * cst]; }, R(0));
-    nrm[c] = sqrt(t);
+    t = lane_sum16(t);
+    if (lane == 0) nrm[c] = sqrt(t);
   }
   for (int c = threadIdx.x; c < n; c += NT) {
     pos[c] = c;
@@ -247,7 +273,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
     // the exchange, in a buffer alternating with the step parity
     R* slot = pub + ((size_t)(s & 1) * T.G + T.member) * m;
     if (lds && T.G > 1 && ps.p != INT_MAX) {
-      const R* src = cptr(at[ps.p]);
+      const R* src = colp(at[ps.p]);
       for (int i = s + threadIdx.x; i < m; i += NT) slot[i] = src[i];
     }
     if (T.G > 1) {
@@ -282,25 +308,20 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
       break;
     }
     kept = (double)bv / ((double)tolr * (double)r11);
-    // where the pivot column is read from
-    const R* pcol = M + cp;
-    size_t pst = (size_t)ldm;
-    if (lds) {
-      pst = 1;
-      if (T.G == 1) {
-        pcol = cptr(cp);
-      } else {
-        const int owner = cp % T.G;
-        R* oslot = pub + ((size_t)(s & 1) * T.G + owner) * m;
-        if (amb) {  // the chosen column may not be its owner's candidate: publish it
-          if (T.member == owner) {
-            const R* src = cptr(cp);
-            for (int i = s + threadIdx.x; i < m; i += NT) oslot[i] = src[i];
-          }
-          T.sync();
+    // where the pivot column is read from: the owner's LDS (a lone workgroup), the owner's
+    // publication slot (a team with LDS columns) or the workspace
+    const R* pcol = colp(cp);
+    if (lds && T.G > 1) {
+      const int owner = cp % T.G;
+      R* oslot = pub + ((size_t)(s & 1) * T.G + owner) * m;
+      if (amb) {  // the chosen column may not be its owner's candidate: publish it
+        if (T.member == owner) {
+          const R* src = colp(cp);
+          for (int i = s + threadIdx.x; i < m; i += NT) oslot[i] = src[i];
         }
-        pcol = oslot;
+        T.sync();
       }
+      pcol = oslot;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -310,47 +331,62 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
       pos[cp] = s;
       pos[cs] = pp;
     }
-    R x0 = pcol[(size_t)s * pst];
+    R x0 = pcol[s];
     R beta = x0 >= R(0) ? -bv : bv;
     R scale = x0 - beta;
     R tv = (beta - x0) / beta;
     for (int i = threadIdx.x; i < m; i += NT) {
       R v = 0;
       if (i == s) v = 1;
-      else if (i > s) v = pcol[(size_t)i * pst] / scale;
+      else if (i > s) v = pcol[i] / scale;
       vsh[i] = v;
-      if (T.member == 0) V[(size_t)i * ldv + s] = v;
+      if (T.member == 0 && i >= s) V[(size_t)s * ldv + i] = v;
     }
     if (T.member == 0 && threadIdx.x == 0) tau[s] = tv;
     __syncthreads();
-    const int len = m - s;
-    const R* vv = vsh + s;
-    for (int c = T.cid; c < n; c += T.GT) {
+    // apply the reflector to the own live columns: w = tau v^T a over rows s..m-1, a -= w v,
+    // and the new trailing norm over rows s+1..m-1
+    const int r0 = s + ((lane - s) & (PL - 1));  // this lane's first row >= s
+    for (int lc = grp; lc < nloc; lc += NGW) {
+      const int c = T.member + T.G * lc;
       if (pos[c] <= s) continue;
-      R* col = cptr(c) + (size_t)s * cst;
-      R w = seq_dot<COL_B>(len, [&](int i) { return vv[i]; }, [&](int i) { return col[i * cst]; }, R(0));
-      w *= tv;
-      col[0] = fma(-w, vv[0], col[0]);
-      R t = 0;
-      int i = 1;
-      for (; i + COL_B <= len; i += COL_B) {
-        R a[COL_B];
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u) a[u] = col[(i + u) * cst];
+      R* col = colp(c);
+      R acc = 0;
+      for (int i0 = r0; i0 < m; i0 += PL * COL_B) {
+        R a[COL_B], v[COL_B];
 #pragma unroll
         for (int u = 0; u < COL_B; ++u) {
-          a[u] = fma(-w, vv[i + u], a[u]);
-          col[(i + u) * cst] = a[u];
-          t = fma(a[u], a[u], t);
+          int i = i0 + PL * u;
+          a[u] = i < m ? col[i] : R(0);
+          v[u] = i < m ? vsh[i] : R(0);
+        }
+#pragma unroll
+        for (int u = 0; u < COL_B; ++u)
+          if (i0 + PL * u < m) acc = fma(v[u], a[u], acc);
+      }
+      const R w = lane_sum16(acc) * tv;
+      R t = 0;
+      for (int i0 = r0; i0 < m; i0 += PL * COL_B) {
+        R a[COL_B];
+#pragma unroll
+        for (int u = 0; u < COL_B; ++u) {
+          int i = i0 + PL * u;
+          a[u] = i < m ? col[i] : R(0);
+        }
+#pragma unroll
+        for (int u = 0; u < COL_B; ++u) {
+          int i = i0 + PL * u;
+          if (i < m) {
+            R x = fma(-w, vsh[i], a[u]);
+            col[i] = x;
+            if (i > s) t = fma(x, x, t);
+          }
         }
       }
-      for (; i < len; ++i) {
-        R a = fma(-w, vv[i], col[i * cst]);
-        col[i * cst] = a;
-        t = fma(a, a, t);
-      }
-      nrm[c] = sqrt(t);
+      t = lane_sum16(t);
+      if (lane == 0) nrm[c] = sqrt(t);
     }
+    __syncthreads();
   }
   if (ratio && T.gtid == 0) {
     ratio[0] = kept;
@@ -361,52 +397,73 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, R* M, int ldm, double to
 }
 
 // Columns c0 .. q-1 of Q = H_0 ... H_{rank-1} [I; 0] (m x q, ldq); columns below c0 are left
-// as they are (already formed).  Every column is
-// formed by one team thread through all reflectors, so members only synchronise at the end.
+// as they are (already formed).  Reflector s is row s of V (ldv), as t_cpqr writes it.  Column
+// j is owned by member (j - c0) mod G and formed by one lane group through all reflectors
+// (row sums in the fixed order of lane_sum16), in the member's LDS (lcol, column j at
+// lcol + ((j - c0) / G) (m | 1)) or, without lcol, in the workspace gcol (column j at
+// gcol + (j - c0) m); it is written to Q at the end, so members only synchronise there.
 template <int NT, class R>
 __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, int ldv, const R* tau, R* Q, int ldq,
-                               R* vsh, int c0, R* lcol) {
-  // with lcol every column is formed in the member's LDS (column j at lcol + ((j - c0) / G) m)
-  // and written to Q at the end
+                               R* vsh, int c0, R* lcol, R* gcol) {
   if (q <= c0) return;  // nothing to form (uniform over the team)
+  constexpr int NGW = NT / PL;
   const bool lds = lcol != nullptr;
   const int lstride = m | 1;
-  auto cptr = [&](int j) -> R* { return lds ? lcol + (size_t)((j - c0) / T.G) * lstride : Q + j; };
-  const size_t cst = lds ? 1 : (size_t)ldq;
-  for (int j = c0 + T.cid; j < q; j += T.GT) {
-    R* col = cptr(j);
-    for (int r = 0; r < m; ++r) col[r * cst] = (r == j) ? R(1) : R(0);
+  const int lane = (int)threadIdx.x & (PL - 1), grp = (int)threadIdx.x / PL;
+  const int nloc = (q - c0 - T.member + T.G - 1) / T.G;  // own columns: j = c0 + member + G lj
+  auto colp = [&](int lj, int j) -> R* { return lds ? lcol + (size_t)lj * lstride : gcol + (size_t)(j - c0) * m; };
+  for (int lj = grp; lj < nloc; lj += NGW) {
+    const int j = c0 + T.member + T.G * lj;
+    R* col = colp(lj, j);
+    for (int i = lane; i < m; i += PL) col[i] = (i == j) ? R(1) : R(0);
   }
   for (int s = rank - 1; s >= 0; --s) {
     R tv = tau[s];
     __syncthreads();
-    for (int i = s + threadIdx.x; i < m; i += NT) vsh[i] = V[(size_t)i * ldv + s];
+    for (int i = s + threadIdx.x; i < m; i += NT) vsh[i] = V[(size_t)s * ldv + i];
     __syncthreads();
-    int len = m - s;
-    const R* vv = vsh + s;
-    int j0 = c0 > s ? c0 : s;
+    const int j0 = c0 > s ? c0 : s;
+    const int r0 = s + ((lane - s) & (PL - 1));
     // a column is still e_j while s > j, so the reflector leaves it unchanged
-    for (int j = c0 + T.cid; j < q; j += T.GT) {
+    for (int lj = grp; lj < nloc; lj += NGW) {
+      const int j = c0 + T.member + T.G * lj;
       if (j < j0) continue;
-      R* col = cptr(j) + (size_t)s * cst;
-      R w = seq_dot<COL_B>(len, [&](int i) { return vv[i]; }, [&](int i) { return col[i * cst]; }, R(0));
-      w *= tv;
-      int i = 0;
-      for (; i + COL_B <= len; i += COL_B) {
+      R* col = colp(lj, j);
+      R acc = 0;
+      for (int i0 = r0; i0 < m; i0 += PL * COL_B) {
+        R a[COL_B], v[COL_B];
+#pragma unroll
+        for (int u = 0; u < COL_B; ++u) {
+          int i = i0 + PL * u;
+          a[u] = i < m ? col[i] : R(0);
+          v[u] = i < m ? vsh[i] : R(0);
+        }
+#pragma unroll
+        for (int u = 0; u < COL_B; ++u)
+          if (i0 + PL * u < m) acc = fma(v[u], a[u], acc);
+      }
+      const R w = lane_sum16(acc) * tv;
+      for (int i0 = r0; i0 < m; i0 += PL * COL_B) {
         R a[COL_B];
 #pragma unroll
-        for (int u = 0; u < COL_B; ++u) a[u] = col[(i + u) * cst];
+        for (int u = 0; u < COL_B; ++u) {
+          int i = i0 + PL * u;
+          a[u] = i < m ? col[i] : R(0);
+        }
 #pragma unroll
-        for (int u = 0; u < COL_B; ++u) col[(i + u) * cst] = fma(-w, vv[i + u], a[u]);
+        for (int u = 0; u < COL_B; ++u) {
+          int i = i0 + PL * u;
+          if (i < m) col[i] = fma(-w, vsh[i], a[u]);
+        }
       }
-      for (; i < len; ++i) col[i * cst] = fma(-w, vv[i], col[i * cst]);
     }
   }
-  if (lds)
-    for (int j = c0 + T.cid; j < q; j += T.GT) {
-      const R* col = cptr(j);
-      for (int r = 0; r < m; ++r) Q[(size_t)r * ldq + j] = col[r];
-    }
+  __syncthreads();
+  for (int lj = grp; lj < nloc; lj += NGW) {
+    const int j = c0 + T.member + T.G * lj;
+    const R* col = colp(lj, j);
+    for (int i = lane; i < m; i += PL) Q[(size_t)i * ldq + j] = col[i];
+  }
   T.sync();
 }
 
