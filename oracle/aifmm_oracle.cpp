@@ -93,8 +93,12 @@ int lu_factor(Mat& A, std::vector<int>& perm) {
   g_flops[0] += 2.0 * n * n * n / 3.0;
   return 0;
 }
-// Solve (LU) X = P B in place on B (n x m); perm from lu_factor (row i of PA = row perm[i] of A)
-Mat lu_solve(const Mat& LU, const std::vector<int>& perm, const Mat& B, int counter = 1) {
+// Solve (LU) X = P B in place on B (n x m); perm from lu_factor (row i of PA = row perm[i] of A).
+// Forward substitution sums each row's terms in ascending column order.  Backward substitution
+// sums them in ascending column order, or with back_desc in descending column order (the
+// column-oriented back substitution of reading 29, used for the pivot blocks of the
+// elimination).
+Mat lu_solve(const Mat& LU, const std::vector<int>& perm, const Mat& B, int counter = 1, bool back_desc = false) {
   int n = LU.r, m = B.c;
   Mat X(n, m);
   for (int i = 0; i < n; ++i)
@@ -106,7 +110,8 @@ Mat lu_solve(const Mat& LU, const std::vector<int>& perm, const Mat& B, int coun
       for (int j = 0; j < m; ++j) X.at(i, j) = std::fma(-l, X.at(k, j), X.at(i, j));
     }
   for (int i = n - 1; i >= 0; --i) {
-    for (int k = i + 1; k < n; ++k) {
+    for (int q = i + 1; q < n; ++q) {
+      int k = back_desc ? n + i - q : q;
       double u = LU.at(i, k);
       if (u == 0.0) continue;
       for (int j = 0; j < m; ++j) X.at(i, j) = std::fma(-u, X.at(k, j), X.at(i, j));
@@ -996,7 +1001,7 @@ bool eliminate(oracle_sys& s, int l, int i) {
     s.err = "singular self-block at level " + std::to_string(l) + " box " + std::to_string(i);
     return false;
   }
-  F.W = lu_solve(F.LU, F.perm, Rb, 1);
+  F.W = lu_solve(F.LU, F.perm, Rb, 1, true);
   Mat Upd = mul(Cb, F.W, 2);
   // scatter: A[O_r, O_c] -= A[O_r, (x_i, z_i)] Piv^{-1} A[(X_i, Y_i), O_c]
   {

@@ -398,50 +398,37 @@ __global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restri
   __shared__ ValIdx shv[WG / WAVE + 1];
   __shared__ double sh[LU_NB + 64 * (LU_NB + 1) + LU_NB * 65];
   __shared__ int ipv[LU_NB];
-  int st = wg_lu_blocked<LU_NB>(m, P.fslab + P.fLU[b], m, P.fpiv + P.fpiv_off[b], shv, sh, ipv);
-  if (st && threadIdx.x == 0) {
-    flag[0] = 1;
-    flag[1] = b;
-    flag[2] = P.l;
-  }
-}
-
-// W = Piv^{-1} [rhs]: row swaps, unit-lower forward and upper backward substitution, one
-// column per thread.
-__global__ void __launch_bounds__(WG) k_elim_trsm(LevelPtrs P, const int* __restrict__ boxes, const int* flag) {
-  if (flag[0]) return;
-  int b = boxes[blockIdx.y];
-  int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
-  int n = P.n[b], k = P.k[b], m = n + k;
-  int C = 0;
-  for (int g = 0; g < G; ++g) C += grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
-  int ldw = C + n;
-  int c = blockIdx.x * WG + threadIdx.x;
-  if (c >= ldw) return;
-  const double* A = P.fslab + P.fLU[b];
-  const int* ipiv = P.fpiv + P.fpiv_off[b];
-  double* W = P.fslab + P.fW[b];
-  for (int r = 0; r < m; ++r) {
-    int p = ipiv[r];
-    if (p != r) {
-      double t = W[(size_t)r * ldw + c];
-      W[(size_t)r * ldw + c] = W[(size_t)p * ldw + c];
-      W[(size_t)p * ldw + c] = t;
+  extern __shared__ int pm[];  // 2 m: the row swaps, then the row permutation
+  int* piv = P.fpiv + P.fpiv_off[b];
+  int st = wg_lu_blocked<LU_NB>(m, P.fslab + P.fLU[b], m, piv, shv, sh, ipv);
+  if (st) {
+    if (threadIdx.x == 0) {
+      flag[0] = 1;
+      flag[1] = b;
+      flag[2] = P.l;
     }
+    return;
   }
-  double* Wc = W + c;
-  for (int r = 1; r < m; ++r) {
-    const double* Ar = A + (size_t)r * m;
-    double v = seq_dot(r, [&](int t) { return -Ar[t]; }, [&](int t) { return Wc[(size_t)t * ldw]; }, Wc[(size_t)r * ldw]);
-    Wc[(size_t)r * ldw] = v;
+  // the row swaps of the pivoting, applied in order, as one permutation: row i of P Piv is row
+  // perm[i] of Piv; it replaces the swaps in fpiv
+  __syncthreads();
+  int* sw = pm + m;
+  for (int i = threadIdx.x; i < m; i += WG) {
+    pm[i] = i;
+    sw[i] = piv[i];
   }
-  for (int r = m - 1; r >= 0; --r) {
-    const double* Ar = A + (size_t)r * m + r + 1;
-    const double* Wr = Wc + (size_t)(r + 1) * ldw;
-    double v = seq_dot(m - r - 1, [&](int t) { return -Ar[t]; }, [&](int t) { return Wr[(size_t)t * ldw]; },
-                       Wc[(size_t)r * ldw]);
-    Wc[(size_t)r * ldw] = v / A[(size_t)r * m + r];
-  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int r = 0; r < m; ++r) {
+      int p = sw[r];
+      if (p != r && p > r && p < m) {
+        int t = pm[r];
+        pm[r] = pm[p];
+        pm[p] = t;
+      }
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += WG) piv[i] = pm[i];
 }
 
 // Schur update of the coupled blocks: T[p, q] -= A[rows(p), x_b] W_x[:, cols(q)], with the
@@ -576,6 +563,156 @@ k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int ti
         if (last) T[addr] = -v;
         else T[addr] -= v;
       }
+  }
+}
+
+// W = Piv^{-1} [rhs] for the pivot block of every box of a colour, with the LU factors of
+// k_elim_lu (row permutation in fpiv).  One wave owns 16 columns of W and walks the rows in
+// blocks of 16, left-looking.  Forward (unit lower L): a block's rows start from the permuted
+// right-hand side, take the terms of every earlier row through FP64 MFMA 16x16x4 in ascending
+// column order, then the in-block terms one at a time (16 lanes, one column each), so every
+// element is the ascending fused multiply-add chain of the forward substitution; the result
+// goes to the workspace X (the layout of W).  Backward (upper U): a block's rows take the terms
+// of every later row through MFMA in descending column order (four columns per MFMA, highest
+// first), then the in-block terms in descending order and the division by the diagonal: the
+// column-oriented back substitution, element by element.  The wave's stores are fenced before
+// its later blocks read them; waves share nothing, so the workgroup never synchronises.
+constexpr int TW = 4;  // waves per workgroup
+__global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int* __restrict__ boxes, const int* flag,
+                                                         double* tws, int64_t tstride) {
+  if (flag[0]) return;
+  const int b = boxes[blockIdx.y];
+  const int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
+  const int n = P.n[b], k = P.k[b], m = n + k;
+  int C = 0;
+  for (int g = 0; g < G; ++g) C += grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
+  const int ldw = C + n;
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int c0 = (blockIdx.x * TW + wv) * 16;
+  if (c0 >= ldw || m == 0) return;  // the whole wave
+  const int fr = lane % 16, fk = lane / 16;
+  const int col = c0 + fr;
+  const bool cok = col < ldw;
+  const double* A = P.fslab + P.fLU[b];
+  const int* perm = P.fpiv + P.fpiv_off[b];
+  double* W = P.fslab + P.fW[b];
+  double* X = tws + (size_t)blockIdx.y * tstride;
+  __shared__ double xs_all[TW][16][17], ls_all[TW][16][17];
+  double(*xs)[17] = xs_all[wv];
+  double(*ls)[17] = ls_all[wv];
+  const int nblk = (m + 15) / 16;
+  // nsteps MFMA steps onto acc; operands of step s from fa(s) / fb(s), eight steps loaded ahead
+  constexpr int KC = 8;
+  auto gemm = [&](dbl4& acc, int nsteps, auto fa, auto fb) {
+    double pa[KC], pb[KC];
+#pragma unroll
+    for (int u = 0; u < KC; ++u) {
+      pa[u] = u < nsteps ? fa(u) : 0.0;
+      pb[u] = u < nsteps ? fb(u) : 0.0;
+    }
+    for (int s0 = 0; s0 < nsteps; s0 += KC) {
+      double ca[KC], cb[KC];
+#pragma unroll
+      for (int u = 0; u < KC; ++u) {
+        ca[u] = pa[u];
+        cb[u] = pb[u];
+      }
+      if (s0 + KC < nsteps) {
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+          int s = s0 + KC + u;
+          pa[u] = s < nsteps ? fa(s) : 0.0;
+          pb[u] = s < nsteps ? fb(s) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KC; ++u)
+        if (s0 + u < nsteps) acc = mfma16(ca[u], cb[u], acc);
+    }
+  };
+  // the block's rows and the diagonal 16 x 16 block of the factors, staged in the wave's LDS
+  auto stage = [&](const dbl4& acc, int R0, int nr) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xs[fk + 4 * q][fr] = acc[q];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int idx = lane + WAVE * u, i = idx / 16, t = idx % 16;
+      ls[i][t] = (i < nr && t < nr) ? A[(size_t)(R0 + i) * m + R0 + t] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
+  for (int j = 0; j < nblk; ++j) {
+    const int R0 = 16 * j, nr = min(16, m - R0);
+    dbl4 acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int r = R0 + fk + 4 * q;
+      acc[q] = (r < m && cok) ? W[(size_t)perm[r] * ldw + col] : 0.0;
+    }
+    const bool aok = R0 + fr < m;
+    const double* Ar = A + (size_t)(R0 + fr) * m;
+    // earlier rows t = 0 .. R0-1: step s, slot fk takes t = 4 s + fk
+    gemm(acc, R0 / 4, [&](int s) { return aok ? -Ar[4 * s + fk] : 0.0; },
+         [&](int s) { return cok ? X[(size_t)(4 * s + fk) * ldw + col] : 0.0; });
+    stage(acc, R0, nr);
+    if (lane < 16) {
+      double x[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = xs[r][lane];
+#pragma unroll
+      for (int r = 1; r < 16; ++r)
+#pragma unroll
+        for (int t = 0; t < r; ++t)
+          if (r < nr) x[r] = fma(-ls[r][t], x[t], x[r]);
+      if (cok)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (r < nr) X[(size_t)(R0 + r) * ldw + col] = x[r];
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int j = nblk - 1; j >= 0; --j) {
+    const int R0 = 16 * j, R1 = min(R0 + 16, m), nr = R1 - R0;
+    dbl4 acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int r = R0 + fk + 4 * q;
+      acc[q] = (r < m && cok) ? X[(size_t)r * ldw + col] : 0.0;
+    }
+    const bool aok = R0 + fr < m;
+    const double* Ar = A + (size_t)(R0 + fr) * m;
+    // later rows t = m-1 down to R1: step s, slot fk takes t = m - 1 - 4 s - fk
+    gemm(acc, (m - R1 + 3) / 4,
+         [&](int s) {
+           int t = m - 1 - 4 * s - fk;
+           return (aok && t >= R1) ? -Ar[t] : 0.0;
+         },
+         [&](int s) {
+           int t = m - 1 - 4 * s - fk;
+           return (cok && t >= R1) ? W[(size_t)t * ldw + col] : 0.0;
+         });
+    stage(acc, R0, nr);
+    if (lane < 16) {
+      double x[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = xs[r][lane];
+#pragma unroll
+      for (int r = 15; r >= 0; --r)
+        if (r < nr) {
+          double v = x[r];
+#pragma unroll
+          for (int t = 15; t > r; --t)
+            if (t < nr) v = fma(-ls[r][t], x[t], v);
+          x[r] = v / ls[r][r];
+        }
+      if (cok)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (r < nr) W[(size_t)(R0 + r) * ldw + col] = x[r];
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -1175,6 +1312,19 @@ static void factor_levels(aifmm_system& s) {
     DBuf<double> ws, scratch;
     ws.alloc((size_t)maxcol * wsz);
     scratch.alloc((size_t)XG * sstride);
+    // forward results of the pivot-block solves of one colour (a W-sized block per box) and the
+    // LDS of the row permutation of each pivot-block LU
+    int64_t tstride = 2;
+    int maxmc = 1;
+    for (int b = 0; b < lv.nb; ++b) {
+      tstride = std::max(tstride, (int64_t)2 * lv.n[b] * (lv.Ccap[b] + lv.n[b]));
+      maxmc = std::max(maxmc, 2 * lv.n[b]);
+    }
+    DBuf<double> tws;
+    tws.alloc((size_t)maxcol * tstride);
+    const size_t lu_shm = (size_t)2 * maxmc * sizeof(int);
+    if (lu_shm > 128 * 1024) throw Error{AIFMM_ERR_CAPACITY, "pivot block too large for the LU kernel"};
+    AIFMM_HIP(hipFuncSetAttribute((const void*)k_elim_lu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lu_shm));
     lv.d_order.upload(Pl.order, st);
     DBuf<int>& d_order = lv.d_order;
     // static round and transform lists of the whole level
@@ -1338,8 +1488,9 @@ static void factor_levels(aifmm_system& s) {
       int nbox = Pl.col_off[c + 1] - Pl.col_off[c];
       const int* boxes = d_order.p + Pl.col_off[c];
       hipLaunchKernelGGL(k_elim_gather, dim3(nbox), dim3(WG), 0, st, P, boxes);
-      hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
-      hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, WG), nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
+      hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), lu_shm, st, P, boxes, s.d_flag.p);
+      hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes, s.d_flag.p,
+                         tws.p, tstride);
       int tiles_c = cdiv(lv.Cmax, ST), tiles_r = cdiv(std::max(1, lv.Rmax), ST);
       int tiles_x = 8 * cdiv((int64_t)tiles_r * tiles_c, 8);
       auto se = ev_pair(sch_ev);
