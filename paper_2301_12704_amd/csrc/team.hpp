@@ -107,20 +107,83 @@ __device__ inline void t_zero(Team<NT>& T, int M, int N, TD* C, int ldc) {
   }
   T.sync();
 }
-// C = alpha op(A) op(B) + beta C, each element accumulated in ascending k in the precision of
-// C (as wg_gemm).
+// C = alpha op(A) op(B) + beta C, each element accumulated from zero in ascending k in the
+// precision of C, then scaled and added (as wg_gemm).  In FP64 the team's waves take 16 x 16
+// output tiles on FP64 MFMA 16x16x4, which adds its four products one fused multiply-add at a
+// time in ascending k (the slots past K add exact zeros at the end of the chain), so the
+// results are those of the sequential chains; other precisions take one element per thread.
 template <int NT, class TA, class TB, class TC>
 __device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, const TA* __restrict__ A, int lda,
                               bool ta, const TB* __restrict__ B, int ldb, bool tb, double beta, TC* C, int ldc) {
-  for (int idx = T.gtid; idx < M * N; idx += T.GT) {
-    int r = idx / N, c = idx - r * N;
-    const TA* pa = ta ? A + r : A + (size_t)r * lda;
-    const TB* pb = tb ? B + (size_t)c * ldb : B + c;
-    size_t sa = ta ? (size_t)lda : 1, sb = tb ? 1 : (size_t)ldb;
-    TC acc = seq_dot(K, [&](int k) { return (TC)pa[k * sa]; }, [&](int k) { return (TC)pb[k * sb]; }, (TC)0);
-    TC v = (TC)alpha * acc;
-    if (beta != 0.0) v += (TC)beta * C[(size_t)r * ldc + c];
-    C[(size_t)r * ldc + c] = v;
+  if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr int KC = 8;
+    const int lane = (int)threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
+    const int wid = T.member * (NT / WAVE) + (int)threadIdx.x / WAVE, nwv = T.G * (NT / WAVE);
+    const int tm = (M + 15) / 16, tn = (N + 15) / 16, nsteps = (K + 3) / 4;
+    const size_t ai = ta ? 1 : (size_t)lda, ak = ta ? (size_t)lda : 1;
+    const size_t bk = tb ? 1 : (size_t)ldb, bj = tb ? (size_t)ldb : 1;
+    for (int tile = wid; tile < tm * tn; tile += nwv) {
+      const int R0 = (tile / tn) * 16, C0 = (tile % tn) * 16;
+      const bool aok = R0 + fr < M, bok = C0 + fr < N;
+      const TA* Ar = A + (size_t)(R0 + fr) * ai;
+      const TB* Bc = B + (size_t)(C0 + fr) * bj;
+      auto fa = [&](int s) {
+        int k = 4 * s + fk;
+        return (aok && k < K) ? (double)Ar[(size_t)k * ak] : 0.0;
+      };
+      auto fb = [&](int s) {
+        int k = 4 * s + fk;
+        return (bok && k < K) ? (double)Bc[(size_t)k * bk] : 0.0;
+      };
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      double pa[KC], pb[KC];
+#pragma unroll
+      for (int u = 0; u < KC; ++u) {
+        pa[u] = u < nsteps ? fa(u) : 0.0;
+        pb[u] = u < nsteps ? fb(u) : 0.0;
+      }
+      for (int s0 = 0; s0 < nsteps; s0 += KC) {
+        double ca[KC], cb[KC];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+          ca[u] = pa[u];
+          cb[u] = pb[u];
+        }
+        if (s0 + KC < nsteps) {
+#pragma unroll
+          for (int u = 0; u < KC; ++u) {
+            int s = s0 + KC + u;
+            pa[u] = s < nsteps ? fa(s) : 0.0;
+            pb[u] = s < nsteps ? fb(s) : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < KC; ++u)
+          if (s0 + u < nsteps) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u], cb[u], acc, 0, 0, 0);
+      }
+      // output (lane, q): row R0 + lane / 16 + 4 q, column C0 + lane % 16
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = R0 + fk + 4 * q, c = C0 + fr;
+        if (r < M && c < N) {
+          double v = alpha * acc[q];
+          if (beta != 0.0) v += beta * (double)C[(size_t)r * ldc + c];
+          C[(size_t)r * ldc + c] = (TC)v;
+        }
+      }
+    }
+  } else {
+    for (int idx = T.gtid; idx < M * N; idx += T.GT) {
+      int r = idx / N, c = idx - r * N;
+      const TA* pa = ta ? A + r : A + (size_t)r * lda;
+      const TB* pb = tb ? B + (size_t)c * ldb : B + c;
+      size_t sa = ta ? (size_t)lda : 1, sb = tb ? 1 : (size_t)ldb;
+      TC acc = seq_dot(K, [&](int k) { return (TC)pa[k * sa]; }, [&](int k) { return (TC)pb[k * sb]; }, (TC)0);
+      TC v = (TC)alpha * acc;
+      if (beta != 0.0) v += (TC)beta * C[(size_t)r * ldc + c];
+      C[(size_t)r * ldc + c] = v;
+    }
   }
   T.sync();
 }
