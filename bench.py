@@ -294,6 +294,16 @@ def main():
         "compress_kernel_s": round(st["compress_kernel_s"], 4),
         "schur_kernel_s": round(schur_s, 5),
     }
+    # the whole Schur phase of the elimination: pivot-block solves (k_elim_trsm) and the fill-in
+    # update (k_elim_schur), both FP64 MFMA contractions, event-timed per launch
+    trsm_flops, trsm_s = st["trsm_flops"], st["trsm_kernel_s"]
+    if trsm_s > 0 and schur_s > 0:
+        ph = (schur_flops + trsm_flops) / (schur_s + trsm_s) / 1e12
+        out["schur_phase"] = {"kernels": "k_elim_trsm + k_elim_schur", "bound": "mfma",
+                              "achieved": round(ph, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(ph / FP64_PEAK_TFLOPS, 4),
+                              "trsm_flops": trsm_flops, "trsm_kernel_s": round(trsm_s, 5),
+                              "trsm_tflops": round(trsm_flops / trsm_s / 1e12, 3)}
     if not args.no_serve:
         out["served"] = serve(A)
     if not args.no_batch:

@@ -91,13 +91,14 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   int* tr = P.trace + (tbase + e) * 6;
   double* trr = P.trace_ratio + (tbase + e) * 8;
   __shared__ ValIdx shv[CT / WAVE + 1];
-  extern __shared__ double shm[];  // one reflector (cap entries), then pivot positions (2 x 2cap ints)
+  extern __shared__ double shm[];  // one reflector (cap), pivot positions (2 x 2cap ints), own norms (2cap)
   RT* vsh = (RT*)shm;
   int* pos = (int*)(vsh + cap);
   int* at = pos + 2 * cap;
   // columns of the pivoted QRs and Q formations kept in LDS (lds_cols per member), the
   // members' candidate pivot columns published in pub (2 x G x cap entries per compression)
-  RT* lcol = lds_cols > 0 ? (RT*)(at + 2 * cap) : nullptr;
+  RT* lnr = (RT*)(at + 2 * cap);  // the member's own columns' norms (2 cap entries)
+  RT* lcol = lds_cols > 0 ? lnr + 2 * cap : nullptr;
   RT* pub = (RT*)pubbuf + (size_t)e * 2 * G * cap;
   RT* w = (RT*)(ws + (size_t)e * wsz);
   size_t c2 = (size_t)cap * cap;
@@ -135,24 +136,24 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     int ld = ki + nj;
     t_copy(T, ni, ki, U_i, ni, M, ld);
     t_copy(T, ni, nj, Fij, nj, M + ki, ld);
-    int r1 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr, lcol, pub, t1);
+    int r1 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, pub, t1);
     // RRQR2: [U_j | P2P_ji] = U~_j L_ji
     ld = kj + ni;
     t_copy(T, nj, kj, U_j, nj, M, ld);
     t_copy(T, nj, ni, Fji, ni, M + kj, ld);
-    int r2 = t_cpqr(T, nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2, lcol, pub, t1);
+    int r2 = t_cpqr(T, nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, lnr, shv, vsh, pos, at, trr + 2, lcol, pub, t1);
     // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
     t_formq(T, ni, r1, r1, V1, cap, tau, nU, cap, vsh, 0, lcol, t1);
     ld = kj + r1;
     t_copy(T, nj, kj, V_j, nj, M, ld);
     t_gemm(T, nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
-    int r3 = t_cpqr(T, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, shv, vsh, pos, at, trr + 4, lcol, pub, t1);
+    int r3 = t_cpqr(T, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, lnr, shv, vsh, pos, at, trr + 4, lcol, pub, t1);
     // RRQR4: [V_i | L~_ji^*]
     t_formq(T, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh, 0, lcol, t1);
     ld = ki + r2;
     t_copy(T, ni, ki, V_i, ni, M, ld);
     t_gemm(T, ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, M + ki, ld);
-    int r4 = t_cpqr(T, ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, shv, vsh, pos, at, trr + 6, lcol, pub, t1);
+    int r4 = t_cpqr(T, ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, lnr, shv, vsh, pos, at, trr + 6, lcol, pub, t1);
     int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
     // new orthonormal bases: columns beyond a tolerance rank are further columns of the same
     // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed)
@@ -213,11 +214,11 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
     }
     T.sync();
-    int r5 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, shv, vsh, pos, at, trr, lcol, pub, t1);
+    int r5 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, pub, t1);
     // RRQR: [U_i | M2P_ir] = U~_i L_ir
     t_copy(T, ni, ki, U_i, ni, M, ld);
     t_copy(T, ni, kr, M2P, nr, M + ki, ld);
-    int r6 = t_cpqr(T, ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, shv, vsh, pos, at, trr + 2, lcol, pub, t1);
+    int r6 = t_cpqr(T, ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, lnr, shv, vsh, pos, at, trr + 2, lcol, pub, t1);
     int kin = r5 > r6 ? r5 : r6;
     t_formq(T, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol, t1);
     t_formq(T, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, t1);
@@ -331,6 +332,7 @@ __device__ inline int64_t near_entry(const LevelPtrs& P, int p, int q) {
 
 // Pivot block [[K_bb, U_b],[V_b^*, 0]], right-hand sides [A[X_b, O_c] | E | I] and the
 // coupled column blocks A[O_r, x_b] of box b (one workgroup per box).
+constexpr int GS = 16;  // workgroups per box of k_elim_gather
 __global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __restrict__ boxes) {
   int b = boxes[blockIdx.x];
   int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
@@ -338,57 +340,73 @@ __global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __re
   double* Piv = P.fslab + P.fLU[b];
   double* W = P.fslab + P.fW[b];
   double* Cb = P.fslab + P.fC[b];
-  int C = 0;
-  for (int g = 0; g < G; ++g) C += grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
-  int ldw = C + n;
-  if (threadIdx.x == 0) {  // group offsets for the Schur update: rows (all but y_b's group), columns
-    int* rc = P.grc + (size_t)b * 56;
-    int ro = 0, co = 0;
+  // column (co) and coupled-row (ro) offsets of the groups, the group sizes and source blocks
+  __shared__ int co[29], ro[29], cdim[28];
+  __shared__ int64_t src_bq[28], src_qb[28];
+  __shared__ int ldq[28];
+  if (threadIdx.x == 0) {
+    int r0 = 0, c0 = 0;
     for (int g = 0; g < G; ++g) {
-      int cd = grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
-      rc[g] = ro;
-      rc[28 + g] = co;
-      if (g < G - 1) ro += cd;
-      co += cd;
+      int q = P.grp_box[g0 + g];
+      int cd = grp_rows(P, g, G, b, q, P.grp_elim[g0 + g]);
+      co[g] = c0;
+      ro[g] = r0;
+      cdim[g] = cd;
+      if (g < G - 1) {
+        src_bq[g] = near_entry(P, b, q);  // (X_b, x_q | y_q), ld n_q
+        src_qb[g] = near_entry(P, q, b);  // (X_q | Z_q, x_b), ld n_b
+        ldq[g] = P.n[q];
+        r0 += cd;
+      }
+      c0 += cd;
     }
-    rc[G] = ro;
-    rc[28 + G] = co;
+    co[G] = c0;
+    ro[G] = r0;
+    if (blockIdx.y == 0) {  // group offsets for the Schur update: rows (all but y_b's group), columns
+      int* rc = P.grc + (size_t)b * 56;
+      for (int g = 0; g <= G; ++g) {
+        rc[g] = ro[g];
+        rc[28 + g] = co[g];
+      }
+    }
   }
+  __syncthreads();
+  const int C = co[G], ldw = C + n;
   const double* Kbb = P.slab + near_entry(P, b, b);
   const double* Ub = P.slab + P.U_off[b];
   const double* Vb = P.slab + P.V_off[b];
-  for (int idx = threadIdx.x; idx < m * m; idx += WG) {
+  const int gt = blockIdx.y * WG + threadIdx.x;
+  for (int idx = gt; idx < m * m; idx += GS * WG) {
     int r = idx / m, c = idx - r * m;
     double v = 0.0;
     if (r < n) v = c < n ? Kbb[(size_t)r * n + c] : Ub[(size_t)r * n + (c - n)];
     else if (c < n) v = Vb[(size_t)c * n + (r - n)];
     Piv[idx] = v;
   }
-  for (int idx = threadIdx.x; idx < m * ldw; idx += WG) W[idx] = 0.0;
-  __syncthreads();
-  int co = 0, ro = 0;
-  for (int g = 0; g < G; ++g) {
-    int q = P.grp_box[g0 + g], qe = P.grp_elim[g0 + g];
-    int cd = grp_rows(P, g, G, b, q, qe);
-    if (g < G - 1) {
-      const double* Bbq = P.slab + near_entry(P, b, q);  // (X_b, x_q | y_q), ld n_q
-      int ldq = P.n[q];
-      for (int idx = threadIdx.x; idx < n * cd; idx += WG) {
-        int r = idx / cd, c = idx - r * cd;
-        W[(size_t)r * ldw + co + c] = Bbq[(size_t)r * ldq + c];
-      }
-      const double* Bqb = P.slab + near_entry(P, q, b);  // (X_q | Z_q, x_b), ld n_b
-      for (int idx = threadIdx.x; idx < cd * n; idx += WG) {
-        int r = idx / n, c = idx - r * n;
-        Cb[(size_t)(ro + r) * n + c] = Bqb[(size_t)r * n + c];
-      }
-      ro += cd;
+  // every element of W written once: one wave per (row, segment); segments g < G are the
+  // column groups, segment G the extension columns C .. C+n-1 (Piv^{-1}[:, x_b])
+  const int lane = threadIdx.x % WAVE;
+  const int wid = blockIdx.y * (WG / WAVE) + threadIdx.x / WAVE, nwv = GS * (WG / WAVE);
+  for (int it = wid; it < m * (G + 1); it += nwv) {
+    const int r = it / (G + 1), g = it - r * (G + 1);
+    double* Wr = W + (size_t)r * ldw;
+    if (g == G) {
+      for (int c = lane; c < n; c += WAVE) Wr[C + c] = (r < n && c == r) ? 1.0 : 0.0;
+    } else if (g == G - 1) {  // (Y_b, y_b) = -I
+      for (int c = lane; c < cdim[g]; c += WAVE) Wr[co[g] + c] = (r >= n && c == r - n) ? -1.0 : 0.0;
     } else {
-      for (int r = threadIdx.x; r < k; r += WG) W[(size_t)(n + r) * ldw + co + r] = -1.0;  // (Y_b, y_b) = -I
+      const double* Bbq = P.slab + src_bq[g] + (size_t)r * ldq[g];
+      for (int c = lane; c < cdim[g]; c += WAVE) Wr[co[g] + c] = r < n ? Bbq[c] : 0.0;
     }
-    co += cd;
   }
-  for (int r = threadIdx.x; r < n; r += WG) W[(size_t)r * ldw + C + r] = 1.0;  // extension: Piv^{-1}[:, x_b]
+  // coupled column blocks A[O_r, x_b]: one wave per row
+  const int R = ro[G > 0 ? G - 1 : 0];
+  for (int rr = wid; rr < R; rr += nwv) {
+    int g = 0;
+    while (ro[g + 1] <= rr) ++g;
+    const double* Bqb = P.slab + src_qb[g] + (size_t)(rr - ro[g]) * n;
+    for (int c = lane; c < n; c += WAVE) Cb[(size_t)rr * n + c] = Bqb[c];
+  }
 }
 
 constexpr int LU_NB = 16;
@@ -1433,6 +1451,7 @@ static void factor_levels(aifmm_system& s) {
   int L = s.L;
   s.stats.schur_flops = s.stats.schur_bytes = s.stats.trsm_flops = s.stats.lu_flops = 0;
   s.stats.schur_kernel_s = s.stats.compress_kernel_s = s.stats.schur_launches = s.stats.compress_launches = 0;
+  s.stats.trsm_kernel_s = s.stats.trsm_launches = 0;
   s.trace.clear();
   s.sc = SolveCache{};
   s.d_flag.zero(st);
@@ -1527,7 +1546,8 @@ static void factor_levels(aifmm_system& s) {
     const bool f32 = s.prec == AIFMM_FP32;
     const size_t rs = f32 ? sizeof(float) : sizeof(double);
     const void* kcomp = f32 ? (const void*)k_compress<float> : (const void*)k_compress<double>;
-    const size_t base = (size_t)cap * rs + (size_t)4 * cap * sizeof(int);  // reflector + pivot positions
+    // reflector, pivot positions, own column norms
+    const size_t base = (size_t)cap * rs + (size_t)4 * cap * sizeof(int) + (size_t)2 * cap * rs;
     const size_t lds_max = 152 * 1024;
     if (base > lds_max) throw Error{AIFMM_ERR_CAPACITY, "box size too large for the compression kernel"};
     AIFMM_HIP(hipFuncSetAttribute(kcomp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
@@ -1578,7 +1598,7 @@ static void factor_levels(aifmm_system& s) {
     d_abort.zero(st);
     hipEvent_t ev[4];
     for (auto& e : ev) AIFMM_HIP(hipEventCreate(&e));
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> sch_ev, cmp_ev;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> sch_ev, cmp_ev, trs_ev;
     auto ev_pair = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
       hipEvent_t a, b;
       AIFMM_HIP(hipEventCreate(&a));
@@ -1638,10 +1658,13 @@ static void factor_levels(aifmm_system& s) {
       }
       int nbox = Pl.col_off[c + 1] - Pl.col_off[c];
       const int* boxes = d_order.p + Pl.col_off[c];
-      hipLaunchKernelGGL(k_elim_gather, dim3(nbox), dim3(WG), 0, st, P, boxes);
+      hipLaunchKernelGGL(k_elim_gather, dim3(nbox, GS), dim3(WG), 0, st, P, boxes);
       hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), lu_shm, st, P, boxes, s.d_flag.p);
+      auto te = ev_pair(trs_ev);
+      AIFMM_HIP(hipEventRecord(te.first, st));
       hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes, s.d_flag.p,
                          tws.p, tstride);
+      AIFMM_HIP(hipEventRecord(te.second, st));
       int tiles_c = cdiv(lv.Cmax, ST), tiles_r = cdiv(std::max(1, lv.Rmax), ST);
       int tiles_x = 8 * cdiv((int64_t)tiles_r * tiles_c, 8);
       auto se = ev_pair(sch_ev);
@@ -1664,6 +1687,14 @@ static void factor_levels(aifmm_system& s) {
       AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
       s.stats.schur_kernel_s += ms * 1e-3;
       s.stats.schur_launches += 1;
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    for (auto& pr : trs_ev) {
+      float ms = 0;
+      AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      s.stats.trsm_kernel_s += ms * 1e-3;
+      s.stats.trsm_launches += 1;
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
     }

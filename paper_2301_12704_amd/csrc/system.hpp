@@ -249,6 +249,7 @@ struct Stats {
   double schur_flops = 0, schur_bytes = 0, trsm_flops = 0, lu_flops = 0;
   double schur_kernel_s = 0, compress_kernel_s = 0;   // event-timed device time of the last factor
   double schur_launches = 0, compress_launches = 0;
+  double trsm_kernel_s = 0, trsm_launches = 0;
   double gmres_s = 0, gmres_iters = 0;
 };
 

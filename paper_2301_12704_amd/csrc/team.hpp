@@ -188,6 +188,20 @@ __device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, co
   T.sync();
 }
 
+// A value of another lane of the same 16-lane DPP row (v_mov_b32_dpp with control CTRL, all
+// rows and banks); 64-bit values move as two halves.
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // Pivot candidate state for one pass over the live columns: the largest norm mx, the lowest
 // position p among the columns whose norm is >= keep * mx, that column's norm nv, and amb set
 // when merging lost the information needed to know p exactly (a column within the band of a
@@ -217,15 +231,31 @@ __device__ inline PivState piv_merge(const PivState& a, const PivState& b, R kee
   }
   return r;
 }
-// Workgroup-wide merge of the per-thread states (the same result on every thread).
+// Workgroup-wide merge of the per-thread states (the same result on every thread).  The merge
+// is commutative and associative, so any pairing gives the same state: inside each 16-lane row
+// the partners come through DPP moves (lane ^ 1, lane ^ 2, the other quad, the other half row,
+// as in lane_sum16), then across the wave's four rows through two lane exchanges.
+template <int CTRL>
+__device__ inline PivState dpp_piv(const PivState& x) {
+  PivState o;
+  o.mx = dpp_mov<CTRL>(x.mx);
+  o.nv = dpp_mov<CTRL>(x.nv);
+  o.p = __builtin_amdgcn_mov_dpp(x.p, CTRL, 0xF, 0xF, false);
+  o.amb = __builtin_amdgcn_mov_dpp(x.amb, CTRL, 0xF, 0xF, false);
+  return o;
+}
 template <int NT, class R>
 __device__ inline PivState wg_pivmerge(PivState x, R keep, PivState* sh) {
-  for (int off = WAVE / 2; off > 0; off >>= 1) {
+  x = piv_merge(x, dpp_piv<0xB1>(x), keep);
+  x = piv_merge(x, dpp_piv<0x4E>(x), keep);
+  x = piv_merge(x, dpp_piv<0x141>(x), keep);
+  x = piv_merge(x, dpp_piv<0x140>(x), keep);
+  for (int off = 16; off < WAVE; off <<= 1) {
     PivState o;
-    o.mx = __shfl_down(x.mx, off, WAVE);
-    o.nv = __shfl_down(x.nv, off, WAVE);
-    o.p = __shfl_down(x.p, off, WAVE);
-    o.amb = __shfl_down(x.amb, off, WAVE);
+    o.mx = __shfl_xor(x.mx, off, WAVE);
+    o.nv = __shfl_xor(x.nv, off, WAVE);
+    o.p = __shfl_xor(x.p, off, WAVE);
+    o.amb = __shfl_xor(x.amb, off, WAVE);
     x = piv_merge(x, o, keep);
   }
   int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
@@ -245,16 +275,20 @@ __device__ inline PivState wg_pivmerge(PivState x, R keep, PivState* sh) {
 // Row sums of the pivoted QR and of the Q formation are taken in one fixed order: sixteen
 // partial fused multiply-add chains over the rows, chain q holding the rows i = q (mod 16) in
 // ascending order, then the pairwise tree ((t0 + t1) + (t2 + t3)) + ... over the chains.  A
-// group of PL = 16 lanes owns a column: lane q runs chain q, and the butterfly of lane_sum16
-// leaves the tree's sum on all 16 lanes (IEEE addition is commutative, so both lanes of a
-// pair form the same bits).  A column's dependent chain is then m / 16 terms long instead of m.
+// group of PL = 16 lanes (one DPP row of the wave) owns a column: lane q runs chain q, and
+// lane_sum16 leaves the tree's sum on all 16 lanes.  Each level adds the value of the partner
+// lane through a DPP move within the row: lane ^ 1 and lane ^ 2 (quad permutations), then the
+// other quad of the half row (half-row mirror) and the other half row (row mirror); after a
+// level every lane of a pair, quad or half row holds the same value (IEEE addition is
+// commutative), so the mirrors pair exactly the subtrees of the tree.  A column's dependent
+// chain is m / 16 terms long instead of m.
 constexpr int PL = 16;
 template <class R>
 __device__ inline R lane_sum16(R t) {
-  t = t + __shfl_xor(t, 1, PL);
-  t = t + __shfl_xor(t, 2, PL);
-  t = t + __shfl_xor(t, 4, PL);
-  t = t + __shfl_xor(t, 8, PL);
+  t = t + dpp_mov<0xB1>(t);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  t = t + dpp_mov<0x4E>(t);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  t = t + dpp_mov<0x141>(t);  // row_half_mirror: the other quad of the half row
+  t = t + dpp_mov<0x140>(t);  // row_mirror: the other half row
   return t;
 }
 // loads in flight per lane in the column passes
@@ -274,13 +308,14 @@ constexpr int COL_B = 4;
 // gcol + c m, m n entries).  With LDS columns in a team each member publishes its candidate
 // column in pub before the exchange.  The pivot column is read by every member to form the
 // reflector (vsh: m entries of LDS).  Reflector s is written to row s of V (ldv) with
-// V[s][s] = 1, its scale to tau[s]; nrm (device memory, n) holds each column's trailing norm.
+// V[s][s] = 1, its scale to tau[s]; nrm (device memory, n) holds each column's trailing norm
+// and lnr (LDS, n / G entries) the member's own columns' norms (column c at lnr[c / G]).
 // M is left unchanged (R is not formed).  Returns the rank; ratio (if given) receives
 // |R_kk| / (tol |R_11|) of the last kept and of the first rejected pivot.
 template <int NT, class R>
 __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, double tol, R* V, int ldv, R* tau,
-                             R* nrm, ValIdx* shv, R* vsh, int* pos, int* at, double* ratio, R* lcol, R* pub,
-                             R* gcol) {
+                             R* nrm, R* lnr, ValIdx* shv, R* vsh, int* pos, int* at, double* ratio, R* lcol,
+                             R* pub, R* gcol) {
   __shared__ PivState psh[NT / WAVE + 1];
   constexpr int NGW = NT / PL;  // lane groups per workgroup
   // pivot ties: norms within a relative band of the largest (1e-11 in FP64, 2e-6 in FP32)
@@ -316,7 +351,11 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       }
     }
     t = lane_sum16(t);
-    if (lane == 0) nrm[c] = sqrt(t);
+    if (lane == 0) {
+      R v = sqrt(t);
+      nrm[c] = v;
+      lnr[lc] = v;
+    }
   }
   for (int c = threadIdx.x; c < n; c += NT) {
     pos[c] = c;
@@ -330,7 +369,10 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     // only when a merge reports an ambiguity
     PivState ps{-1.0, -1.0, INT_MAX, 0};
     for (int c = T.cid; c < n; c += T.GT)
-      if (pos[c] >= s) ps = piv_merge(ps, PivState{(double)nrm[c], (double)nrm[c], pos[c], 0}, keep);
+      if (pos[c] >= s) {
+        const double v = (double)lnr[c / T.G];
+        ps = piv_merge(ps, PivState{v, v, pos[c], 0}, keep);
+      }
     ps = wg_pivmerge<NT>(ps, keep, psh);
     // LDS columns of a team: each member publishes its candidate column (rows s..m-1) before
     // the exchange, in a buffer alternating with the step parity
@@ -351,18 +393,20 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       ValIdx mx{-1.0, INT_MAX};
       for (int c = T.cid; c < n; c += T.GT)
         if (pos[c] >= s) {
-          ValIdx x{(double)nrm[c], pos[c]};
+          ValIdx x{(double)lnr[c / T.G], pos[c]};
           if (vi_better(x, mx)) mx = x;
         }
       mx = T.argmax(mx, shv);
       R thr = (R)mx.v * keep;
       ValIdx b2{-1.0, INT_MAX};
       for (int c = T.cid; c < n; c += T.GT)
-        if (pos[c] >= s && nrm[c] >= thr && pos[c] < b2.i) b2 = ValIdx{0.0, pos[c]};
+        if (pos[c] >= s && lnr[c / T.G] >= thr && pos[c] < b2.i) b2 = ValIdx{0.0, pos[c]};
       pp = T.argmax(b2, shv).i;
     }
     const int cp = at[pp];
-    const R bv = nrm[cp];
+    // the pivot's norm: carried by the merged candidate state (its nv is the norm of the column
+    // at position p); the exact fallback reads the owner's copy in device memory
+    const R bv = amb ? nrm[cp] : (R)ps.nv;
     if (s == 0) {
       r11 = bv;
       if (r11 == R(0)) break;
@@ -447,7 +491,11 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
         }
       }
       t = lane_sum16(t);
-      if (lane == 0) nrm[c] = sqrt(t);
+      if (lane == 0) {
+        R v = sqrt(t);
+        nrm[c] = v;
+        lnr[lc] = v;
+      }
     }
     __syncthreads();
   }
