@@ -11,6 +11,18 @@
 
 namespace aifmm {
 
+// 1 / sqrt(x) for x > 0: the hardware estimate refined by two Newton steps on 1 - x y^2
+// (about one ulp; the operator's entries need not match the factorization's bit for bit).
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // y[i, c] = sum_j A_ij x[j, c] for the points in tree order; x, y row-major (N x nr).
 // One target per thread; sources staged through LDS in tiles; every entry evaluated.
 constexpr int MV_T = 256, MV_S = 256, MV_R = 16;
@@ -43,7 +55,7 @@ __global__ void __launch_bounds__(MV_T) k_matvec(KernelDesc K, const double* __r
           double z = pi[t] - sp[jj * d + t];
           r2 = fma(z, z, r2);
         }
-        double v = K.kind == 0 ? dexp(-sqrt(r2) / K.scale) : 1.0 / sqrt(r2 + s2);
+        double v = K.kind == 0 ? dexp(-sqrt(r2) / K.scale) : rsqrt_nr(r2 + s2);
         if (j0 + jj == i) v += K.shift;
 #pragma unroll
         for (int c = 0; c < MV_R; ++c) acc[c] = fma(v, sx[jj * MV_R + c], acc[c]);
@@ -192,11 +204,14 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
     hipLaunchKernelGGL(k_scale_cols, dim3(cdiv(vec, WG)), dim3(WG), 0, st, N, nr, dalpha.p, xx, yy);
   };
   int total = 0;
+  bool x_zero = true;  // x is still the zero start, so A x = 0 and r = b exactly
   while (true) {
     // true residual r = b - A x
-    matvec_tree(s, xt.p, nr, w.p);
     AIFMM_HIP(hipMemcpyAsync(r.p, bt.p, sizeof(double) * vec, hipMemcpyDeviceToDevice, st));
-    axpy(std::vector<double>(nr, -1.0), w.p, r.p);
+    if (!x_zero) {
+      matvec_tree(s, xt.p, nr, w.p);
+      axpy(std::vector<double>(nr, -1.0), w.p, r.p);
+    }
     std::vector<double> beta = coldots(s, r.p, r.p, nr, part);
     bool all = true;
     for (int c = 0; c < nr; ++c) {
@@ -269,6 +284,7 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
       for (int c = 0; c < nr; ++c) a[c] = done[c] ? 0.0 : H[(size_t)i * m][c];
       axpy(a, Z[i].p, xt.p);
     }
+    if (j > 0) x_zero = false;
   }
   for (int c = 0; c < nr; ++c) {
     if (iters) iters[c] = its[c];

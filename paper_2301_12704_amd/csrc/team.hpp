@@ -291,8 +291,53 @@ __device__ inline R lane_sum16(R t) {
   t = t + dpp_mov<0x140>(t);  // row_mirror: the other half row
   return t;
 }
-// loads in flight per lane in the column passes
-constexpr int COL_B = 4;
+// loads in flight per lane in the column passes: LDS columns, and workspace columns (which
+// come from L2 at a much longer latency)
+constexpr int COL_B = 4, COL_BG = 16;
+
+// The passes of one column by its 16-lane group; lane r0 % 16 takes the rows r0, r0 + 16, ...
+// below m, B loads in flight.  grp_dot: the lane's partial chain of sum v_i a_i.
+template <int B, class R>
+__device__ inline R grp_dot(const R* col, const R* v, int r0, int m) {
+  R acc = 0;
+  for (int i0 = r0; i0 < m; i0 += PL * B) {
+    R a[B], b[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      int i = i0 + PL * u;
+      a[u] = i < m ? col[i] : R(0);
+      b[u] = i < m ? v[i] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (i0 + PL * u < m) acc = fma(b[u], a[u], acc);
+  }
+  return acc;
+}
+// a_i -= w v_i; returns the lane's partial chain of sum a_i^2 over the rows above s (with
+// norm), else 0
+template <int B, bool NORM, class R>
+__device__ inline R grp_axpy(R* col, const R* v, int r0, int m, int s, R w) {
+  R t = 0;
+  for (int i0 = r0; i0 < m; i0 += PL * B) {
+    R a[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      int i = i0 + PL * u;
+      a[u] = i < m ? col[i] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      int i = i0 + PL * u;
+      if (i < m) {
+        R x = fma(-w, v[i], a[u]);
+        col[i] = x;
+        if (NORM && i > s) t = fma(x, x, t);
+      }
+    }
+  }
+  return t;
+}
 
 // Householder QR with column pivoting of the m x n row-major M, truncated at the first step
 // whose pivot column norm is <= tol times the first one (RRQR with threshold eps_A of
@@ -334,15 +379,15 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     const int c = T.member + T.G * lc;
     R* d = colp(c);
     R t = 0;
-    for (int i0 = lane; i0 < m; i0 += PL * COL_B) {
-      R a[COL_B];
+    for (int i0 = lane; i0 < m; i0 += PL * COL_BG) {
+      R a[COL_BG];
 #pragma unroll
-      for (int u = 0; u < COL_B; ++u) {
+      for (int u = 0; u < COL_BG; ++u) {
         int i = i0 + PL * u;
         a[u] = i < m ? M[(size_t)i * ldm + c] : R(0);
       }
 #pragma unroll
-      for (int u = 0; u < COL_B; ++u) {
+      for (int u = 0; u < COL_BG; ++u) {
         int i = i0 + PL * u;
         if (i < m) {
           d[i] = a[u];
@@ -458,38 +503,9 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       const int c = T.member + T.G * lc;
       if (pos[c] <= s) continue;
       R* col = colp(c);
-      R acc = 0;
-      for (int i0 = r0; i0 < m; i0 += PL * COL_B) {
-        R a[COL_B], v[COL_B];
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u) {
-          int i = i0 + PL * u;
-          a[u] = i < m ? col[i] : R(0);
-          v[u] = i < m ? vsh[i] : R(0);
-        }
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u)
-          if (i0 + PL * u < m) acc = fma(v[u], a[u], acc);
-      }
+      const R acc = lds ? grp_dot<COL_B>(col, vsh, r0, m) : grp_dot<COL_BG>(col, vsh, r0, m);
       const R w = lane_sum16(acc) * tv;
-      R t = 0;
-      for (int i0 = r0; i0 < m; i0 += PL * COL_B) {
-        R a[COL_B];
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u) {
-          int i = i0 + PL * u;
-          a[u] = i < m ? col[i] : R(0);
-        }
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u) {
-          int i = i0 + PL * u;
-          if (i < m) {
-            R x = fma(-w, vsh[i], a[u]);
-            col[i] = x;
-            if (i > s) t = fma(x, x, t);
-          }
-        }
-      }
+      R t = lds ? grp_axpy<COL_B, true>(col, vsh, r0, m, s, w) : grp_axpy<COL_BG, true>(col, vsh, r0, m, s, w);
       t = lane_sum16(t);
       if (lane == 0) {
         R v = sqrt(t);
@@ -540,33 +556,10 @@ __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, 
       const int j = c0 + T.member + T.G * lj;
       if (j < j0) continue;
       R* col = colp(lj, j);
-      R acc = 0;
-      for (int i0 = r0; i0 < m; i0 += PL * COL_B) {
-        R a[COL_B], v[COL_B];
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u) {
-          int i = i0 + PL * u;
-          a[u] = i < m ? col[i] : R(0);
-          v[u] = i < m ? vsh[i] : R(0);
-        }
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u)
-          if (i0 + PL * u < m) acc = fma(v[u], a[u], acc);
-      }
+      const R acc = lds ? grp_dot<COL_B>(col, vsh, r0, m) : grp_dot<COL_BG>(col, vsh, r0, m);
       const R w = lane_sum16(acc) * tv;
-      for (int i0 = r0; i0 < m; i0 += PL * COL_B) {
-        R a[COL_B];
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u) {
-          int i = i0 + PL * u;
-          a[u] = i < m ? col[i] : R(0);
-        }
-#pragma unroll
-        for (int u = 0; u < COL_B; ++u) {
-          int i = i0 + PL * u;
-          if (i < m) col[i] = fma(-w, vsh[i], a[u]);
-        }
-      }
+      if (lds) grp_axpy<COL_B, false>(col, vsh, r0, m, s, w);
+      else grp_axpy<COL_BG, false>(col, vsh, r0, m, s, w);
     }
   }
   __syncthreads();
