@@ -86,7 +86,17 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   int e = blockIdx.x / G;
   if (e >= nent) return;
   Team<CT> T;
-  T.init(blockIdx.x - e * G, G, ctr + e, part + (size_t)e * 2 * G, abort);
+  T.init(blockIdx.x - e * G, G, ctr + e, part + (size_t)e * 4 * G, abort);
+  // a team of two or more runs the independent pivoted QRs of the compression concurrently on
+  // its two halves (sub-teams A: members 0 .. GA-1 and B: the rest), each with its own barrier
+  // counter, exchange slots, publication slots and workspace, and joins them with a team barrier
+  const bool split = G > 1;
+  const int GA = G / 2;
+  const bool inA = T.member < GA;
+  Team<CT> S;
+  if (split)
+    S.init(inA ? T.member : T.member - GA, inA ? GA : G - GA, ctr + nent + 2 * e + (inA ? 0 : 1),
+           part + (size_t)e * 4 * G + 2 * G + (inA ? 0 : 2 * GA), abort);
   RoundEntry R = ent[e];
   int* tr = P.trace + (tbase + e) * 6;
   double* trr = P.trace_ratio + (tbase + e) * 8;
@@ -100,6 +110,7 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   RT* lnr = (RT*)(at + 2 * cap);  // the member's own columns' norms (2 cap entries)
   RT* lcol = lds_cols > 0 ? lnr + 2 * cap : nullptr;
   RT* pub = (RT*)pubbuf + (size_t)e * 2 * G * cap;
+  RT* pubS = pub + (split && !inA ? (size_t)2 * GA * cap : 0);  // the sub-team's publication slots
   RT* w = (RT*)(ws + (size_t)e * wsz);
   size_t c2 = (size_t)cap * cap;
   RT* Lb_i = w;
@@ -119,6 +130,9 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   RT* t2 = w + 16 * c2;
   RT* tau = w + 17 * c2;     // 4 * cap
   RT* nrm = tau + 4 * cap;   // 2 * cap
+  RT* Mb = nrm + 2 * cap;    // sub-team B: input matrix (cap x 2cap), column storage, norms
+  RT* t1b = Mb + 2 * c2;
+  RT* nrmb = t1b + 2 * c2;
   const double* U_i = P.slab + P.U_off[R.i];
   const double* V_i = P.slab + P.V_off[R.i];
   int i = R.i, ni = P.n[i], ki = P.k[i];
@@ -132,28 +146,56 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     double* Fji = P.slab + P.p2_slot[R.f_ji];  // (X_j, x_i): nj x ni, ld ni
     double* Aij = P.slab + P.il_slot[R.e_ij];  // (Z_i, y_j): ki x kj, ld nj
     double* Aji = P.slab + P.il_slot[R.e_ji];  // (Z_j, y_i): kj x ki, ld ni
-    // RRQR1: [U_i | P2P_ij] = U~_i L_ij
-    int ld = ki + nj;
-    t_copy(T, ni, ki, U_i, ni, M, ld);
-    t_copy(T, ni, nj, Fij, nj, M + ki, ld);
-    int r1 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, pub, t1);
-    // RRQR2: [U_j | P2P_ji] = U~_j L_ji
-    ld = kj + ni;
-    t_copy(T, nj, kj, U_j, nj, M, ld);
-    t_copy(T, nj, ni, Fji, ni, M + kj, ld);
-    int r2 = t_cpqr(T, nj, ld, M, ld, tol, V2, cap, tau + cap, nrm, lnr, shv, vsh, pos, at, trr + 2, lcol, pub, t1);
-    // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
-    t_formq(T, ni, r1, r1, V1, cap, tau, nU, cap, vsh, 0, lcol, t1);
-    ld = kj + r1;
-    t_copy(T, nj, kj, V_j, nj, M, ld);
-    t_gemm(T, nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
-    int r3 = t_cpqr(T, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, lnr, shv, vsh, pos, at, trr + 4, lcol, pub, t1);
-    // RRQR4: [V_i | L~_ji^*]
-    t_formq(T, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh, 0, lcol, t1);
-    ld = ki + r2;
-    t_copy(T, ni, ki, V_i, ni, M, ld);
-    t_gemm(T, ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, M + ki, ld);
-    int r4 = t_cpqr(T, ni, ld, M, ld, tol, V4, cap, tau + 3 * cap, nrm, lnr, shv, vsh, pos, at, trr + 6, lcol, pub, t1);
+    // two chains: RRQR1 -> Q1 -> RRQR3 and RRQR2 -> Q2 -> RRQR4 (sub-teams A and B, or one
+    // after the other on a lone workgroup)
+    int r1 = 0, r2 = 0, r3 = 0, r4 = 0;
+    // the team that runs a chain: a copy (without a split the team is a lone workgroup, whose
+    // barrier keeps no state; with one, only the half-team runs the chain)
+    Team<CT> C = split ? S : T;
+    if (!split || inA) {
+      // RRQR1: [U_i | P2P_ij] = U~_i L_ij
+      int ld = ki + nj;
+      t_copy(C, ni, ki, U_i, ni, M, ld);
+      t_copy(C, ni, nj, Fij, nj, M + ki, ld);
+      r1 = t_cpqr(C, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, pubS, t1);
+      // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
+      t_formq(C, ni, r1, r1, V1, cap, tau, nU, cap, vsh, 0, lcol, t1);
+      ld = kj + r1;
+      t_copy(C, nj, kj, V_j, nj, M, ld);
+      t_gemm(C, nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
+      r3 = t_cpqr(C, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, lnr, shv, vsh, pos, at, trr + 4, lcol, pubS, t1);
+      if (C.gtid == 0) {
+        tr[0] = r1;
+        tr[2] = r3;
+      }
+    }
+    if (!split || !inA) {
+      RT* Mc = split ? Mb : M;
+      RT* gc = split ? t1b : t1;
+      RT* nc = split ? nrmb : nrm;
+      // RRQR2: [U_j | P2P_ji] = U~_j L_ji
+      int ld = kj + ni;
+      t_copy(C, nj, kj, U_j, nj, Mc, ld);
+      t_copy(C, nj, ni, Fji, ni, Mc + kj, ld);
+      r2 = t_cpqr(C, nj, ld, Mc, ld, tol, V2, cap, tau + cap, nc, lnr, shv, vsh, pos, at, trr + 2, lcol, pubS, gc);
+      // RRQR4: [V_i | L~_ji^*]
+      t_formq(C, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh, 0, lcol, gc);
+      ld = ki + r2;
+      t_copy(C, ni, ki, V_i, ni, Mc, ld);
+      t_gemm(C, ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, Mc + ki, ld);
+      r4 = t_cpqr(C, ni, ld, Mc, ld, tol, V4, cap, tau + 3 * cap, nc, lnr, shv, vsh, pos, at, trr + 6, lcol, pubS, gc);
+      if (C.gtid == 0) {
+        tr[1] = r2;
+        tr[3] = r4;
+      }
+    }
+    if (split) {  // join (waits for a whole chain: a longer bound); every member takes the ranks
+      T.sync(1u << 28);
+      r1 = tr[0];
+      r2 = tr[1];
+      r3 = tr[2];
+      r4 = tr[3];
+    }
     int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
     // new orthonormal bases: columns beyond a tolerance rank are further columns of the same
     // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed)
@@ -207,18 +249,35 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     double* Air = P.slab + P.il_slot[R.e_ij];  // (Z_i, y_r): ki x kr, ld nr
     double* Ari = P.slab + P.il_slot[R.e_ji];  // (Z_r, y_i): kr x ki, ld ni
     int ld = ki + kr;
-    // RRQR: [V_i | P2L_ri^*] = V~_i R_ri
-    t_copy(T, ni, ki, V_i, ni, M, ld);
-    for (int idx = T.gtid; idx < ni * kr; idx += T.GT) {
-      int a = idx / kr, c = idx - a * kr;
-      M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
+    int r5 = 0, r6 = 0;
+    // the team that runs a chain: a copy (without a split the team is a lone workgroup, whose
+    // barrier keeps no state; with one, only the half-team runs the chain)
+    Team<CT> C = split ? S : T;
+    if (!split || inA) {
+      // RRQR: [V_i | P2L_ri^*] = V~_i R_ri
+      t_copy(C, ni, ki, V_i, ni, M, ld);
+      for (int idx = C.gtid; idx < ni * kr; idx += C.GT) {
+        int a = idx / kr, c = idx - a * kr;
+        M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
+      }
+      C.sync();
+      r5 = t_cpqr(C, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, pubS, t1);
+      if (C.gtid == 0) tr[0] = r5;
     }
-    T.sync();
-    int r5 = t_cpqr(T, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, pub, t1);
-    // RRQR: [U_i | M2P_ir] = U~_i L_ir
-    t_copy(T, ni, ki, U_i, ni, M, ld);
-    t_copy(T, ni, kr, M2P, nr, M + ki, ld);
-    int r6 = t_cpqr(T, ni, ld, M, ld, tol, V2, cap, tau + cap, nrm, lnr, shv, vsh, pos, at, trr + 2, lcol, pub, t1);
+    if (!split || !inA) {
+      RT* Mc = split ? Mb : M;
+      // RRQR: [U_i | M2P_ir] = U~_i L_ir
+      t_copy(C, ni, ki, U_i, ni, Mc, ld);
+      t_copy(C, ni, kr, M2P, nr, Mc + ki, ld);
+      r6 = t_cpqr(C, ni, ld, Mc, ld, tol, V2, cap, tau + cap, split ? nrmb : nrm, lnr, shv, vsh, pos, at, trr + 2,
+                  lcol, pubS, split ? t1b : t1);
+      if (C.gtid == 0) tr[1] = r6;
+    }
+    if (split) {
+      T.sync(1u << 28);
+      r5 = tr[0];
+      r6 = tr[1];
+    }
     int kin = r5 > r6 ? r5 : r6;
     t_formq(T, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol, t1);
     t_formq(T, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, t1);
@@ -1396,17 +1455,25 @@ static void count_flops(aifmm_system& s, int l) {
   }
 }
 
+// largest half-team whose pivoted-QR columns live in LDS (a whole team has at most 128 members)
 static int lds_gmax() {
   const char* v = getenv("AIFMM_LDS_TEAM_MAX");
   int g = v && *v ? atoi(v) : 24;
-  return std::max(1, std::min(128, g));
+  return std::max(1, std::min(64, g));
 }
 
-// largest team whose pivoted-QR columns live in the workspace
+// least pivoted-QR matrix entries per member of a workspace half-team
+static int team_elems() {
+  const char* v = getenv("AIFMM_TEAM_ELEMS");
+  int e = v && *v ? atoi(v) : 49152;
+  return std::max(1024, e);
+}
+
+// largest half-team whose pivoted-QR columns live in the workspace
 static int glob_gmax() {
   const char* v = getenv("AIFMM_TEAM_MAX");
   int g = v && *v ? atoi(v) : 32;
-  return std::max(1, std::min(128, g));
+  return std::max(1, std::min(64, g));
 }
 
 static bool lds_off() {
@@ -1464,7 +1531,7 @@ static void factor_levels(aifmm_system& s) {
     if (l < L) s.lev[l + 1].slab.release();
     LevelPtrs P = ptrs(s, l);
     int cap = lv.nmax;
-    int64_t wsz = 18 * (int64_t)cap * cap + 8 * cap + 16;
+    int64_t wsz = 22 * (int64_t)cap * cap + 10 * cap + 16;
     int maxcol = 0;
     for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) maxcol = std::max(maxcol, Pl.col_off[c + 1] - Pl.col_off[c]);
     const int XG = 1024;
@@ -1569,30 +1636,39 @@ static void factor_levels(aifmm_system& s) {
       G = 1;
       lcols = 0;
       shm = base;
-      // the smallest team whose share of the columns fits in LDS, up to 24 members: a pivot step
-      // of a larger team costs more in barriers than LDS columns save over workspace columns
-      if (!lds_off())
-        for (int g = 1; g <= lds_gmax(); ++g) {
-          if (g > 1 && (coop_l == 0 || (int64_t)ne * g > coop_l)) break;
-          int cols = (2 * cap + g - 1) / g;
-          size_t need = base + (size_t)cols * (cap | 1) * rs;
-          if (need <= lds_max) {
-            G = g;
-            lcols = cols;
-            shm = need;
-            return;
+      // LDS bytes when each member holds a 1 / per share of one pivoted QR's columns
+      auto lds_need = [&](int per) { return base + (size_t)cdiv(2 * cap, per) * (cap | 1) * rs; };
+      if (!lds_off()) {
+        // the smallest even team whose halves (one pivoted QR each) keep their columns in LDS,
+        // halves of up to lds_gmax members: a pivot step of a larger half costs more in
+        // barriers than LDS columns save over workspace columns
+        if (coop_l > 0)
+          for (int g = 2; g <= 2 * lds_gmax(); g += 2) {
+            if ((int64_t)ne * g > coop_l) break;
+            if (lds_need(g / 2) <= lds_max) {
+              G = g;
+              lcols = cdiv(2 * cap, g / 2);
+              shm = lds_need(g / 2);
+              return;
+            }
           }
+        if (lds_need(1) <= lds_max) {  // a lone workgroup, QRs one after the other
+          lcols = 2 * cap;
+          shm = lds_need(1);
+          return;
         }
+      }
+      // workspace columns: two halves of up to glob_gmax members each
       if (coop_g > 0 && ne > 0)
-        G = std::max(1, std::min({glob_gmax(), coop_g / ne, (int)((int64_t)2 * cap * cap / 49152)}));
+        G = std::max(1, std::min({2 * glob_gmax(), coop_g / ne, 2 * (int)((int64_t)2 * cap * cap / team_elems())}));
     };
     std::map<std::pair<int, int>, int> team_hist;  // (team size, LDS columns) -> rounds
     DBuf<unsigned> d_ctr;
     DBuf<Cand> d_part;
     DBuf<int> d_abort;
     DBuf<double> d_pub;
-    d_ctr.alloc(std::max(1, maxcol));
-    d_part.alloc((size_t)std::max(1, maxcol) * 2 * GMAX);
+    d_ctr.alloc((size_t)3 * std::max(1, maxcol));  // a team's counter, then two per compression for its halves
+    d_part.alloc((size_t)std::max(1, maxcol) * 4 * GMAX);
     d_pub.alloc((size_t)std::max(1, maxcol) * 2 * GMAX * cap);
     d_abort.alloc(1);
     d_abort.zero(st);
@@ -1628,7 +1704,7 @@ static void factor_levels(aifmm_system& s) {
             hipLaunchKernelGGL(k_compress<double>, dim3(ne), dim3(CT), shm, st, P, er, ne, ws.p, wsz, cap, s.tol,
                                r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p, lcols, d_pub.p);
         } else {
-          AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * ne, st));
+          AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * 3 * ne, st));
           int64_t tb = r_off[rix];
           double tol = s.tol;
           Cand* partp = d_part.p;

@@ -43,10 +43,10 @@ struct Team {
 
   // Wait for every member.  The workgroup barrier orders this workgroup's writes before thread
   // 0's agent-scope release; thread 0's acquire after the wait makes the other members' writes
-  // visible to the whole workgroup.  The wait is bounded (a few seconds of polling): on expiry
-  // the abort flag is raised and the team falls through, so every workgroup still runs to its
-  // end and the host reports the failure.
-  __device__ void sync() {
+  // visible to the whole workgroup.  The wait is bounded (max_spins polls, a few seconds by
+  // default): on expiry the abort flag is raised and the team falls through, so every
+  // workgroup still runs to its end and the host reports the failure.
+  __device__ void sync(unsigned max_spins = 1u << 24) {
     __syncthreads();
     if (G == 1) return;
     if (threadIdx.x == 0) {
@@ -58,7 +58,7 @@ struct Team {
       while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1u << 24)) {
+        if (++spins > max_spins) {
           atomicExch(abort, 1);
           break;
         }
