@@ -198,37 +198,51 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     }
     int kin = r1 > r4 ? r1 : r4, kjn = r2 > r3 ? r2 : r3;
     // new orthonormal bases: columns beyond a tolerance rank are further columns of the same
-    // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed)
-    t_formq(T, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1, lcol, t1);
-    t_formq(T, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh, 0, lcol, t1);
-    t_formq(T, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2, lcol, t1);
-    t_formq(T, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh, 0, lcol, t1);
-    // coefficients by projection: U_i = U~_i L_i, V_i = V~_i R_i, ...
-    t_gemm(T, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
-    t_gemm(T, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
-    t_gemm(T, kjn, kj, nj, 1.0, nUj, cap, true, U_j, nj, false, 0.0, Lb_j, kj1);
-    t_gemm(T, kjn, kj, nj, 1.0, nVj, cap, true, V_j, nj, false, 0.0, Rb_j, kj1);
-    // A_ij := L_i A_ij R_j^* + R~_ij^*,  L~_ij = U~_i^* P2P_ij (kin x nj), R~_ij = V~_j^* L~_ij^*
+    // Householder Q (the first r1 / r2 columns of U~_i / U~_j are already formed), then the
+    // coefficients by projection, U_i = U~_i L_i, V_i = V~_i R_i, ...: the i side on half A,
+    // the j side on half B
+    if (!split || inA) {
+      t_formq(C, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1, lcol, t1);
+      t_formq(C, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh, 0, lcol, t1);
+      t_gemm(C, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
+      t_gemm(C, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
+    }
+    if (!split || !inA) {
+      RT* gc = split ? t1b : t1;
+      t_formq(C, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2, lcol, gc);
+      t_formq(C, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh, 0, lcol, gc);
+      t_gemm(C, kjn, kj, nj, 1.0, nUj, cap, true, U_j, nj, false, 0.0, Lb_j, kj1);
+      t_gemm(C, kjn, kj, nj, 1.0, nVj, cap, true, V_j, nj, false, 0.0, Rb_j, kj1);
+    }
+    if (split) T.sync(1u << 28);
     int nj1 = nj > 0 ? nj : 1, ni1 = ni > 0 ? ni : 1;
-    t_gemm(T, kin, nj, ni, 1.0, nU, cap, true, Fij, nj, false, 0.0, t1, nj1);
-    t_gemm(T, kjn, kin, nj, 1.0, nVj, cap, true, t1, nj1, true, 0.0, t2, cap);   // R~_ij
-    t_gemm(T, kin, kj, ki, 1.0, Lb_i, ki1, false, Aij, nj, false, 0.0, t1, kj1);  // L_i A_ij
-    for (int idx = T.gtid; idx < kin * kjn; idx += T.GT) {
-      int r = idx / kjn, c = idx - r * kjn;
-      Aij[(size_t)r * nj + c] = t2[(size_t)c * cap + r];
+    if (!split || inA) {
+      // A_ij := L_i A_ij R_j^* + R~_ij^*,  L~_ij = U~_i^* P2P_ij (kin x nj), R~_ij = V~_j^* L~_ij^*
+      t_gemm(C, kin, nj, ni, 1.0, nU, cap, true, Fij, nj, false, 0.0, t1, nj1);
+      t_gemm(C, kjn, kin, nj, 1.0, nVj, cap, true, t1, nj1, true, 0.0, t2, cap);   // R~_ij
+      t_gemm(C, kin, kj, ki, 1.0, Lb_i, ki1, false, Aij, nj, false, 0.0, t1, kj1);  // L_i A_ij
+      for (int idx = C.gtid; idx < kin * kjn; idx += C.GT) {
+        int r = idx / kjn, c = idx - r * kjn;
+        Aij[(size_t)r * nj + c] = t2[(size_t)c * cap + r];
+      }
+      C.sync();
+      t_gemm(C, kin, kjn, kj, 1.0, t1, kj1, false, Rb_j, kj1, true, 1.0, Aij, nj);
     }
-    T.sync();
-    t_gemm(T, kin, kjn, kj, 1.0, t1, kj1, false, Rb_j, kj1, true, 1.0, Aij, nj);
-    // A_ji := L_j A_ji R_i^* + R~_ji^*
-    t_gemm(T, kjn, ni, nj, 1.0, nUj, cap, true, Fji, ni, false, 0.0, t1, ni1);
-    t_gemm(T, kin, kjn, ni, 1.0, nV, cap, true, t1, ni1, true, 0.0, t2, cap);    // R~_ji
-    t_gemm(T, kjn, ki, kj, 1.0, Lb_j, kj1, false, Aji, ni, false, 0.0, t1, ki1);
-    for (int idx = T.gtid; idx < kjn * kin; idx += T.GT) {
-      int r = idx / kin, c = idx - r * kin;
-      Aji[(size_t)r * ni + c] = t2[(size_t)c * cap + r];
+    if (!split || !inA) {
+      // A_ji := L_j A_ji R_i^* + R~_ji^*  (half B: temporaries in its own workspace)
+      RT* u1 = split ? t1b : t1;
+      RT* u2 = split ? Mb : t2;
+      t_gemm(C, kjn, ni, nj, 1.0, nUj, cap, true, Fji, ni, false, 0.0, u1, ni1);
+      t_gemm(C, kin, kjn, ni, 1.0, nV, cap, true, u1, ni1, true, 0.0, u2, cap);    // R~_ji
+      t_gemm(C, kjn, ki, kj, 1.0, Lb_j, kj1, false, Aji, ni, false, 0.0, u1, ki1);
+      for (int idx = C.gtid; idx < kjn * kin; idx += C.GT) {
+        int r = idx / kin, c = idx - r * kin;
+        Aji[(size_t)r * ni + c] = u2[(size_t)c * cap + r];
+      }
+      C.sync();
+      t_gemm(C, kjn, kin, ki, 1.0, u1, ki1, false, Rb_i, ki1, true, 1.0, Aji, ni);
     }
-    T.sync();
-    t_gemm(T, kjn, kin, ki, 1.0, t1, ki1, false, Rb_i, ki1, true, 1.0, Aji, ni);
+    if (split) T.sync(1u << 28);
     // bases, fill-ins, ranks
     t_copy(T, ni, kin, nU, cap, (double*)U_i, ni);
     t_copy(T, ni, kin, nV, cap, (double*)V_i, ni);
@@ -279,16 +293,22 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       r6 = tr[1];
     }
     int kin = r5 > r6 ? r5 : r6;
-    t_formq(T, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol, t1);
-    t_formq(T, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, t1);
-    t_gemm(T, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
-    t_gemm(T, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
-    // A_ri := A_ri R_i^* + P2L_ri V~_i
-    t_gemm(T, kr, kin, ki, 1.0, Ari, ni, false, Rb_i, ki1, true, 0.0, t1, cap);
-    t_gemm(T, kr, kin, ni, 1.0, P2L, ni, false, nV, cap, false, 1.0, t1, cap);
-    // A_ir := L_i A_ir + U~_i^* M2P_ir
-    t_gemm(T, kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
-    t_gemm(T, kin, kr, ni, 1.0, nU, cap, true, M2P, nr, false, 1.0, t2, kr1);
+    // the V side (A_ri) on half A, the U side (A_ir) on half B
+    if (!split || inA) {
+      t_formq(C, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol, t1);
+      t_gemm(C, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
+      // A_ri := A_ri R_i^* + P2L_ri V~_i
+      t_gemm(C, kr, kin, ki, 1.0, Ari, ni, false, Rb_i, ki1, true, 0.0, t1, cap);
+      t_gemm(C, kr, kin, ni, 1.0, P2L, ni, false, nV, cap, false, 1.0, t1, cap);
+    }
+    if (!split || !inA) {
+      t_formq(C, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, split ? t1b : t1);
+      t_gemm(C, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
+      // A_ir := L_i A_ir + U~_i^* M2P_ir
+      t_gemm(C, kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
+      t_gemm(C, kin, kr, ni, 1.0, nU, cap, true, M2P, nr, false, 1.0, t2, kr1);
+    }
+    if (split) T.sync(1u << 28);
     t_copy(T, kr, kin, t1, cap, Ari, ni);
     t_copy(T, kin, kr, t2, kr1, Air, nr);
     t_copy(T, ni, kin, nU, cap, (double*)U_i, ni);
