@@ -207,10 +207,13 @@ __device__ inline int wg_lu(int m, double* A, int lda, int* ipiv, ValIdx* shv) {
 // row, the row's panel entries loaded together); row swaps outside the panel are applied
 // after it in step order; then the U12 rows are solved column by column and the trailing
 // matrix is updated in 64 x 64 tiles staged through LDS.  sh: LDS of at least
-// NB + 64 (NB + 1) + 65 NB doubles; ipv: NB ints of LDS.
+// NB + 64 (NB + 1) + 65 NB doubles; ipv: NB ints of LDS.  With pl (LDS of m (NB + 1) doubles)
+// each panel is factored in LDS (rows k0 .. m-1 of its columns, row stride NB + 1) and written
+// back once, so the column steps touch no device memory.
 typedef double lu_dbl4 __attribute__((ext_vector_type(4)));
 template <int NB>
-__device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx* shv, double* sh, int* ipv) {
+__device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx* shv, double* sh, int* ipv,
+                                    double* pl = nullptr) {
   constexpr int NT = WG;
   const int tid = threadIdx.x;
   double* prow = sh;
@@ -218,11 +221,23 @@ __device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx
   double* Us = Ls + 64 * (NB + 1);     // [NB][65]
   for (int k0 = 0; k0 < m; k0 += NB) {
     const int nb = min(NB, m - k0);
+    // panel element (row i >= k0, column k0 + j)
+    const bool lp = pl != nullptr;
+    auto el = [&](int i, int j) -> double* {
+      return lp ? pl + (size_t)(i - k0) * (NB + 1) + j : A + (size_t)i * lda + k0 + j;
+    };
+    if (lp) {
+      for (int idx = tid; idx < (m - k0) * nb; idx += NT) {
+        int r = idx / nb, j = idx - r * nb;
+        pl[(size_t)r * (NB + 1) + j] = A[(size_t)(k0 + r) * lda + k0 + j];
+      }
+      __syncthreads();
+    }
     for (int s = 0; s < nb; ++s) {
       const int k = k0 + s;
       ValIdx best{-1.0, INT_MAX};
       for (int i = k + tid; i < m; i += NT) {
-        ValIdx c{fabs(A[(size_t)i * lda + k]), i};
+        ValIdx c{fabs(*el(i, s)), i};
         if (vi_better(c, best)) best = c;
       }
       best = wg_argmax<NT>(best, shv);
@@ -231,16 +246,16 @@ __device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx
       if (tid == 0) { ipiv[k] = p; ipv[s] = p; }
       if (p != k)
         for (int j = tid; j < nb; j += NT) {
-          double t = A[(size_t)k * lda + k0 + j];
-          A[(size_t)k * lda + k0 + j] = A[(size_t)p * lda + k0 + j];
-          A[(size_t)p * lda + k0 + j] = t;
+          double t = *el(k, j);
+          *el(k, j) = *el(p, j);
+          *el(p, j) = t;
         }
       __syncthreads();
-      for (int j = tid; j < nb; j += NT) prow[j] = A[(size_t)k * lda + k0 + j];
+      for (int j = tid; j < nb; j += NT) prow[j] = *el(k, j);
       __syncthreads();
       const double piv = prow[s];
       for (int i = k + 1 + tid; i < m; i += NT) {
-        double* row = A + (size_t)i * lda + k0;
+        double* row = el(i, 0);
         double as = row[s];
         double v[NB];
 #pragma unroll
@@ -250,6 +265,13 @@ __device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx
 #pragma unroll
         for (int j = 0; j < NB; ++j)
           if (j > s && j < nb) row[j] = fma(-l, prow[j], v[j]);
+      }
+      __syncthreads();
+    }
+    if (lp) {
+      for (int idx = tid; idx < (m - k0) * nb; idx += NT) {
+        int r = idx / nb, j = idx - r * nb;
+        A[(size_t)(k0 + r) * lda + k0 + j] = pl[(size_t)r * (NB + 1) + j];
       }
       __syncthreads();
     }

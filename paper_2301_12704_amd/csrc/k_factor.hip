@@ -489,15 +489,21 @@ __global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __re
 }
 
 constexpr int LU_NB = 16;
-__global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restrict__ boxes, int* flag) {
+__global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restrict__ boxes, int* flag,
+                                                int64_t dyn_bytes) {
   int b = boxes[blockIdx.x];
   int m = P.n[b] + P.k[b];
   __shared__ ValIdx shv[WG / WAVE + 1];
   __shared__ double sh[LU_NB + 64 * (LU_NB + 1) + LU_NB * 65];
   __shared__ int ipv[LU_NB];
-  extern __shared__ int pm[];  // 2 m: the row swaps, then the row permutation
+  // dynamic LDS (dyn_bytes): the panels of the factorization when m (LU_NB + 1) doubles fit,
+  // afterwards 2 m ints: the row swaps, then the row permutation
+  extern __shared__ double dyn[];
+  int* pm = (int*)dyn;
   int* piv = P.fpiv + P.fpiv_off[b];
-  int st = wg_lu_blocked<LU_NB>(m, P.fslab + P.fLU[b], m, piv, shv, sh, ipv);
+  const bool lp = (int64_t)m * (LU_NB + 1) * (int64_t)sizeof(double) <= dyn_bytes;
+  int st = wg_lu_blocked<LU_NB>(m, P.fslab + P.fLU[b], m, piv, shv, sh, ipv, lp ? dyn : nullptr);
+  __syncthreads();
   if (st) {
     if (threadIdx.x == 0) {
       flag[0] = 1;
@@ -1576,8 +1582,11 @@ static void factor_levels(aifmm_system& s) {
     }
     DBuf<double> tws;
     tws.alloc((size_t)maxcol * tstride);
-    const size_t lu_shm = (size_t)2 * maxmc * sizeof(int);
-    if (lu_shm > 128 * 1024) throw Error{AIFMM_ERR_CAPACITY, "pivot block too large for the LU kernel"};
+    // LU: LDS panels where they fit (up to 140 KB beside the kernel's static LDS), and the
+    // permutation
+    const size_t lu_perm = (size_t)2 * maxmc * sizeof(int);
+    if (lu_perm > 128 * 1024) throw Error{AIFMM_ERR_CAPACITY, "pivot block too large for the LU kernel"};
+    const size_t lu_shm = std::max(lu_perm, std::min<size_t>(140 * 1024, (size_t)maxmc * (LU_NB + 1) * sizeof(double)));
     AIFMM_HIP(hipFuncSetAttribute((const void*)k_elim_lu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lu_shm));
     lv.d_order.upload(Pl.order, st);
     DBuf<int>& d_order = lv.d_order;
@@ -1755,7 +1764,7 @@ static void factor_levels(aifmm_system& s) {
       int nbox = Pl.col_off[c + 1] - Pl.col_off[c];
       const int* boxes = d_order.p + Pl.col_off[c];
       hipLaunchKernelGGL(k_elim_gather, dim3(nbox, GS), dim3(WG), 0, st, P, boxes);
-      hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), lu_shm, st, P, boxes, s.d_flag.p);
+      hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), lu_shm, st, P, boxes, s.d_flag.p, (int64_t)lu_shm);
       auto te = ev_pair(trs_ev);
       AIFMM_HIP(hipEventRecord(te.first, st));
       hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes, s.d_flag.p,
