@@ -200,169 +200,7 @@ __device__ inline int wg_lu(int m, double* A, int lda, int* ipiv, ValIdx* shv) {
 }
 
 
-// The same factorization as wg_lu, blocked in panels of NB columns for a 256-thread workgroup:
-// every element still receives its updates a = fma(-l, u, a) one at a time in ascending step
-// order and every pivot is chosen from the same fully updated column, so the factors are bit
-// for bit those of wg_lu.  Inside a panel only its NB columns are updated (one thread per
-// row, the row's panel entries loaded together); row swaps outside the panel are applied
-// after it in step order; then the U12 rows are solved column by column and the trailing
-// matrix is updated in 64 x 64 tiles staged through LDS.  sh: LDS of at least
-// NB + 64 (NB + 1) + 65 NB doubles; ipv: NB ints of LDS.  With pl (LDS of m (NB + 1) doubles)
-// each panel is factored in LDS (rows k0 .. m-1 of its columns, row stride NB + 1) and written
-// back once, so the column steps touch no device memory.
+// FP64 MFMA accumulator of the blocked LU (t_lu_blocked)
 typedef double lu_dbl4 __attribute__((ext_vector_type(4)));
-template <int NB>
-__device__ inline int wg_lu_blocked(int m, double* A, int lda, int* ipiv, ValIdx* shv, double* sh, int* ipv,
-                                    double* pl = nullptr) {
-  constexpr int NT = WG;
-  const int tid = threadIdx.x;
-  double* prow = sh;
-  double* Ls = sh + NB;                // [64][NB + 1]
-  double* Us = Ls + 64 * (NB + 1);     // [NB][65]
-  for (int k0 = 0; k0 < m; k0 += NB) {
-    const int nb = min(NB, m - k0);
-    // panel element (row i >= k0, column k0 + j)
-    const bool lp = pl != nullptr;
-    auto el = [&](int i, int j) -> double* {
-      return lp ? pl + (size_t)(i - k0) * (NB + 1) + j : A + (size_t)i * lda + k0 + j;
-    };
-    if (lp) {
-      for (int idx = tid; idx < (m - k0) * nb; idx += NT) {
-        int r = idx / nb, j = idx - r * nb;
-        pl[(size_t)r * (NB + 1) + j] = A[(size_t)(k0 + r) * lda + k0 + j];
-      }
-      __syncthreads();
-    }
-    for (int s = 0; s < nb; ++s) {
-      const int k = k0 + s;
-      ValIdx best{-1.0, INT_MAX};
-      for (int i = k + tid; i < m; i += NT) {
-        ValIdx c{fabs(*el(i, s)), i};
-        if (vi_better(c, best)) best = c;
-      }
-      best = wg_argmax<NT>(best, shv);
-      if (best.v == 0.0) return 1 + k;
-      const int p = best.i;
-      if (tid == 0) { ipiv[k] = p; ipv[s] = p; }
-      if (p != k)
-        for (int j = tid; j < nb; j += NT) {
-          double t = *el(k, j);
-          *el(k, j) = *el(p, j);
-          *el(p, j) = t;
-        }
-      __syncthreads();
-      for (int j = tid; j < nb; j += NT) prow[j] = *el(k, j);
-      __syncthreads();
-      const double piv = prow[s];
-      for (int i = k + 1 + tid; i < m; i += NT) {
-        double* row = el(i, 0);
-        double as = row[s];
-        double v[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) v[j] = (j > s && j < nb) ? row[j] : 0.0;
-        double l = as / piv;
-        row[s] = l;
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j > s && j < nb) row[j] = fma(-l, prow[j], v[j]);
-      }
-      __syncthreads();
-    }
-    if (lp) {
-      for (int idx = tid; idx < (m - k0) * nb; idx += NT) {
-        int r = idx / nb, j = idx - r * nb;
-        A[(size_t)(k0 + r) * lda + k0 + j] = pl[(size_t)r * (NB + 1) + j];
-      }
-      __syncthreads();
-    }
-    // the panel's row swaps on every other column, in step order
-    for (int c = tid; c < m; c += NT) {
-      if (c >= k0 && c < k0 + nb) continue;
-      for (int s = 0; s < nb; ++s) {
-        int r = k0 + s, p = ipv[s];
-        if (p != r) {
-          double t = A[(size_t)r * lda + c];
-          A[(size_t)r * lda + c] = A[(size_t)p * lda + c];
-          A[(size_t)p * lda + c] = t;
-        }
-      }
-    }
-    __syncthreads();
-    const int c1 = k0 + nb;
-    if (c1 >= m) break;
-    // U12: rows k0 .. c1-1 of the columns right of the panel (unit-lower L11 from the panel)
-    for (int idx = tid; idx < nb * nb; idx += NT) {
-      int r = idx / nb, t = idx - r * nb;
-      Ls[r * (NB + 1) + t] = A[(size_t)(k0 + r) * lda + k0 + t];
-    }
-    __syncthreads();
-    for (int c = c1 + tid; c < m; c += NT) {
-      double u[NB];
-#pragma unroll
-      for (int t = 0; t < NB; ++t) u[t] = t < nb ? A[(size_t)(k0 + t) * lda + c] : 0.0;
-#pragma unroll
-      for (int r = 1; r < NB; ++r)
-#pragma unroll
-        for (int t = 0; t < r; ++t)
-          if (r < nb) u[r] = fma(-Ls[r * (NB + 1) + t], u[t], u[r]);
-#pragma unroll
-      for (int t = 1; t < NB; ++t)
-        if (t < nb) A[(size_t)(k0 + t) * lda + c] = u[t];
-    }
-    __syncthreads();
-    // A22 -= L21 U12 in 64 x 64 tiles, each wave a 32 x 32 quarter as 2 x 2 FP64 MFMA 16x16x4
-    // blocks accumulating onto the current entries: an MFMA adds its four products one fused
-    // multiply-add at a time in ascending step order, as the unblocked update does
-    const int rem = m - c1;
-    const int tiles = (rem + 63) / 64;
-    const int lane = tid % WAVE, wv = tid / WAVE;
-    const int wr = (wv / 2) * 32, wc = (wv % 2) * 32;
-    const int fr = lane % 16, fk = lane / 16;
-    for (int tt = 0; tt < tiles * tiles; ++tt) {
-      int r0 = c1 + (tt / tiles) * 64, cc0 = c1 + (tt % tiles) * 64;
-      for (int idx = tid; idx < 64 * NB; idx += NT) {
-        int r = idx / NB, t = idx - r * NB;
-        int gr = r0 + r;
-        Ls[r * (NB + 1) + t] = (gr < m && t < nb) ? -A[(size_t)gr * lda + k0 + t] : 0.0;
-      }
-      for (int idx = tid; idx < NB * 64; idx += NT) {
-        int t = idx / 64, c = idx - t * 64;
-        int gc = cc0 + c;
-        Us[t * 65 + c] = (gc < m && t < nb) ? A[(size_t)(k0 + t) * lda + gc] : 0.0;
-      }
-      __syncthreads();
-      lu_dbl4 acc[2][2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            int gr = r0 + wr + 16 * i + fk + 4 * q, gc = cc0 + wc + 16 * j + fr;
-            acc[i][j][q] = (gr < m && gc < m) ? A[(size_t)gr * lda + gc] : 0.0;
-          }
-#pragma unroll
-      for (int k4 = 0; k4 < NB; k4 += 4) {
-        double a0 = Ls[(wr + fr) * (NB + 1) + k4 + fk], a1 = Ls[(wr + 16 + fr) * (NB + 1) + k4 + fk];
-        double b0 = Us[(k4 + fk) * 65 + wc + fr], b1 = Us[(k4 + fk) * 65 + wc + 16 + fr];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            int gr = r0 + wr + 16 * i + fk + 4 * q, gc = cc0 + wc + 16 * j + fr;
-            if (gr < m && gc < m) A[(size_t)gr * lda + gc] = acc[i][j][q];
-          }
-      __syncthreads();
-    }
-  }
-  return 0;
-}
 
 }  // namespace aifmm

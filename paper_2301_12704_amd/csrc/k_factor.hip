@@ -489,10 +489,16 @@ __global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __re
 }
 
 constexpr int LU_NB = 16;
+// Pivot-block LU of every box of a colour, G workgroups per box (a team, co-resident through a
+// cooperative launch when G > 1; ctr, status: one barrier counter, zero at launch, and one
+// status word per box).
 __global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restrict__ boxes, int* flag,
-                                                int64_t dyn_bytes) {
-  int b = boxes[blockIdx.x];
+                                                int64_t dyn_bytes, int G, unsigned* ctr, int* status, int* abort) {
+  const int e = blockIdx.x / G;
+  int b = boxes[e];
   int m = P.n[b] + P.k[b];
+  Team<WG> T;
+  T.init(blockIdx.x - e * G, G, ctr + e, nullptr, abort);
   __shared__ ValIdx shv[WG / WAVE + 1];
   __shared__ double sh[LU_NB + 64 * (LU_NB + 1) + LU_NB * 65];
   __shared__ int ipv[LU_NB];
@@ -502,8 +508,9 @@ __global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restri
   int* pm = (int*)dyn;
   int* piv = P.fpiv + P.fpiv_off[b];
   const bool lp = (int64_t)m * (LU_NB + 1) * (int64_t)sizeof(double) <= dyn_bytes;
-  int st = wg_lu_blocked<LU_NB>(m, P.fslab + P.fLU[b], m, piv, shv, sh, ipv, lp ? dyn : nullptr);
+  int st = t_lu_blocked<LU_NB>(T, m, P.fslab + P.fLU[b], m, piv, shv, sh, ipv, lp ? dyn : nullptr, status + e);
   __syncthreads();
+  if (T.member != 0) return;
   if (st) {
     if (threadIdx.x == 0) {
       flag[0] = 1;
@@ -1588,6 +1595,19 @@ static void factor_levels(aifmm_system& s) {
     if (lu_perm > 128 * 1024) throw Error{AIFMM_ERR_CAPACITY, "pivot block too large for the LU kernel"};
     const size_t lu_shm = std::max(lu_perm, std::min<size_t>(140 * 1024, (size_t)maxmc * (LU_NB + 1) * sizeof(double)));
     AIFMM_HIP(hipFuncSetAttribute((const void*)k_elim_lu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lu_shm));
+    int lu_coop = 0;  // co-resident LU workgroups on the device (0: no cooperative launch)
+    {
+      int dev = 0, coop = 0, ncu = 0, per = 0;
+      AIFMM_HIP(hipGetDevice(&dev));
+      AIFMM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+      AIFMM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_elim_lu, WG, lu_shm));
+      if (coop && !team_off()) lu_coop = per * ncu;
+    }
+    DBuf<unsigned> d_luctr;
+    DBuf<int> d_lust;
+    d_luctr.alloc(std::max(1, maxcol));
+    d_lust.alloc(std::max(1, maxcol));
     lv.d_order.upload(Pl.order, st);
     DBuf<int>& d_order = lv.d_order;
     // static round and transform lists of the whole level
@@ -1764,7 +1784,23 @@ static void factor_levels(aifmm_system& s) {
       int nbox = Pl.col_off[c + 1] - Pl.col_off[c];
       const int* boxes = d_order.p + Pl.col_off[c];
       hipLaunchKernelGGL(k_elim_gather, dim3(nbox, GS), dim3(WG), 0, st, P, boxes);
-      hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), lu_shm, st, P, boxes, s.d_flag.p, (int64_t)lu_shm);
+      {
+        // teams of up to 16 co-resident workgroups per pivot block
+        const int Gl = (lu_coop > 0) ? std::max(1, std::min(16, lu_coop / std::max(1, nbox))) : 1;
+        int64_t dynb = (int64_t)lu_shm;
+        int* flagp = s.d_flag.p;
+        unsigned* lctr = d_luctr.p;
+        int* lst = d_lust.p;
+        int* abortp = d_abort.p;
+        if (Gl > 1) {
+          AIFMM_HIP(hipMemsetAsync(d_luctr.p, 0, sizeof(unsigned) * nbox, st));
+          int Glv = Gl;
+          void* args[] = {&P, (void*)&boxes, &flagp, &dynb, &Glv, &lctr, &lst, &abortp};
+          AIFMM_HIP(hipLaunchCooperativeKernel((const void*)k_elim_lu, dim3(nbox * Gl), dim3(WG), args, lu_shm, st));
+        } else {
+          hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), lu_shm, st, P, boxes, flagp, dynb, 1, lctr, lst, abortp);
+        }
+      }
       auto te = ev_pair(trs_ev);
       AIFMM_HIP(hipEventRecord(te.first, st));
       hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes, s.d_flag.p,
@@ -1785,7 +1821,7 @@ static void factor_levels(aifmm_system& s) {
     lv.kfin = lv.d_k.download(st);
     AIFMM_HIP(hipStreamSynchronize(st));
     if (d_abort.download(st)[0])
-      throw Error{AIFMM_ERR_DEVICE, "level " + std::to_string(l) + ": a compression team barrier timed out"};
+      throw Error{AIFMM_ERR_DEVICE, "level " + std::to_string(l) + ": a team barrier timed out"};
     double sch_before = s.stats.schur_kernel_s;
     for (auto& pr : sch_ev) {
       float ms = 0;
