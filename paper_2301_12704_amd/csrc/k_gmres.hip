@@ -24,39 +24,46 @@ __device__ inline double rsqrt_nr(double x) {
 }
 
 // y[i, c] = sum_j A_ij x[j, c] for the points in tree order; x, y row-major (N x nr).
-// One target per thread; sources staged through LDS in tiles; every entry evaluated.
+// One target per thread; sources staged through LDS in tiles; every entry evaluated, the
+// sources of a target in ascending order.  KIND and the dimension D are template arguments so
+// the inner loop holds no branch but the diagonal's.
 constexpr int MV_T = 256, MV_S = 256, MV_R = 16;
-__global__ void __launch_bounds__(MV_T) k_matvec(KernelDesc K, const double* __restrict__ pts, int d, int64_t N,
+template <int KIND, int D>
+__global__ void __launch_bounds__(MV_T) k_matvec(KernelDesc K, const double* __restrict__ pts, int64_t N,
                                                  const double* __restrict__ x, int nr, double* __restrict__ y) {
-  __shared__ double sp[MV_S * 3];
+  __shared__ double sp[MV_S * D];
   __shared__ double sx[MV_S * MV_R];
   int64_t i = (int64_t)blockIdx.x * MV_T + threadIdx.x;
   int c0 = blockIdx.y * MV_R;
   int nc = std::min(MV_R, nr - c0);
   double acc[MV_R];
+#pragma unroll
   for (int c = 0; c < MV_R; ++c) acc[c] = 0.0;
-  double pi[3] = {0.0, 0.0, 0.0};
-  if (i < N)
-    for (int t = 0; t < d; ++t) pi[t] = pts[i * d + t];
-  double s2 = K.scale * K.scale;
+  double pi[D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) pi[t] = i < N ? pts[i * D + t] : 0.0;
+  const double s2 = K.scale * K.scale;
   for (int64_t j0 = 0; j0 < N; j0 += MV_S) {
     int cnt = (int)std::min<int64_t>(MV_S, N - j0);
     __syncthreads();
-    for (int q = threadIdx.x; q < cnt * d; q += MV_T) sp[q] = pts[j0 * d + q];
+    for (int q = threadIdx.x; q < cnt * D; q += MV_T) sp[q] = pts[j0 * D + q];
     for (int q = threadIdx.x; q < cnt * MV_R; q += MV_T) {
       int jj = q / MV_R, c = q % MV_R;
       sx[q] = c < nc ? x[(j0 + jj) * nr + c0 + c] : 0.0;
     }
     __syncthreads();
     if (i < N) {
+      const int dj = (i >= j0 && i < j0 + cnt) ? (int)(i - j0) : -1;  // the diagonal in this tile
+#pragma unroll 4
       for (int jj = 0; jj < cnt; ++jj) {
         double r2 = 0.0;
-        for (int t = 0; t < d; ++t) {
-          double z = pi[t] - sp[jj * d + t];
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+          double z = pi[t] - sp[jj * D + t];
           r2 = fma(z, z, r2);
         }
-        double v = K.kind == 0 ? dexp(-sqrt(r2) / K.scale) : rsqrt_nr(r2 + s2);
-        if (j0 + jj == i) v += K.shift;
+        double v = KIND == 0 ? dexp(-sqrt(r2) / K.scale) : rsqrt_nr(r2 + s2);
+        if (jj == dj) v += K.shift;
 #pragma unroll
         for (int c = 0; c < MV_R; ++c) acc[c] = fma(v, sx[jj * MV_R + c], acc[c]);
       }
@@ -109,7 +116,8 @@ static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1
 // y = A x for tree-ordered row-major vectors
 void matvec_tree(aifmm_system& s, const double* x, int nr, double* y) {
   dim3 grid(cdiv(s.N, MV_T), cdiv(nr, MV_R));
-  hipLaunchKernelGGL(k_matvec, grid, dim3(MV_T), 0, s.stream, s.K, s.d_pts.p, s.d, s.N, x, nr, y);
+  auto kern = s.K.kind == 0 ? (s.d == 2 ? k_matvec<0, 2> : k_matvec<0, 3>) : (s.d == 2 ? k_matvec<1, 2> : k_matvec<1, 3>);
+  hipLaunchKernelGGL(kern, grid, dim3(MV_T), 0, s.stream, s.K, s.d_pts.p, s.N, x, nr, y);
   AIFMM_HIP(hipGetLastError());
 }
 
