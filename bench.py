@@ -41,7 +41,7 @@ def schur_counters(config):
     except OSError:
         return None
     s = src.find("constexpr int ST = ")
-    e = src.find("// New rows Z_b: (Z_b, cols(q))")
+    e = src.find("// W = Piv^{-1} [rhs] for the pivot block of every box of a colour")
     if config != "c2" or s < 0 or e < 0:
         return None
     if hashlib.sha256(src[s:e].encode()).hexdigest()[:16] != rec.get("source_sha256_16"):
