@@ -1505,7 +1505,7 @@ static int team_elems() {
 // largest half-team whose pivoted-QR columns live in the workspace
 static int glob_gmax() {
   const char* v = getenv("AIFMM_TEAM_MAX");
-  int g = v && *v ? atoi(v) : 32;
+  int g = v && *v ? atoi(v) : 24;
   return std::max(1, std::min(64, g));
 }
 
