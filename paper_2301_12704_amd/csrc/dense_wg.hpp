@@ -54,27 +54,6 @@ __device__ inline double kernel_entry(const KernelDesc& K, const double* __restr
   return v;
 }
 
-// acc + sum_{i<n} a(i) b(i), accumulated in ascending i with fused multiply-adds; the loads of
-// every batch of SEQ_B terms are issued before its multiply-adds (loads in flight hide the
-// memory latency of the sequential chain).
-constexpr int SEQ_B = 16;
-template <int B = SEQ_B, class FA, class FB, class T>
-__device__ inline T seq_dot(int n, FA a, FB b, T acc) {
-  int i = 0;
-  for (; i + B <= n; i += B) {
-    T x[B], y[B];
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      x[u] = a(i + u);
-      y[u] = b(i + u);
-    }
-#pragma unroll
-    for (int u = 0; u < B; ++u) acc = fma(x[u], y[u], acc);
-  }
-  for (; i < n; ++i) acc = fma(a(i), b(i), acc);
-  return acc;
-}
-
 struct ValIdx {
   double v;
   int i;
@@ -125,43 +104,6 @@ __device__ inline double wg_sum(double x, double* sh) {
   double r = sh[NT / WAVE];
   __syncthreads();
   return r;
-}
-
-// C = alpha * op(A) op(B) + beta * C  (row-major; op = transpose when the flag is set).
-// Every output element accumulates its products in ascending k with fused multiply-adds, in
-// the precision of C (operands are converted on load).  C must not alias A or B.  beta == 0
-// never reads C.
-template <int NT = WG, class TA, class TB, class TC>
-__device__ inline void wg_gemm(int M, int N, int K, double alpha, const TA* __restrict__ A, int lda, bool ta,
-                               const TB* __restrict__ B, int ldb, bool tb, double beta, TC* C, int ldc) {
-  for (int idx = threadIdx.x; idx < M * N; idx += NT) {
-    int r = idx / N, c = idx - r * N;
-    const TA* pa = ta ? A + r : A + (size_t)r * lda;
-    const TB* pb = tb ? B + (size_t)c * ldb : B + c;
-    size_t sa = ta ? (size_t)lda : 1, sb = tb ? 1 : (size_t)ldb;
-    TC acc = seq_dot(K, [&](int k) { return (TC)pa[k * sa]; }, [&](int k) { return (TC)pb[k * sb]; }, (TC)0);
-    TC v = (TC)alpha * acc;
-    if (beta != 0.0) v += (TC)beta * C[(size_t)r * ldc + c];
-    C[(size_t)r * ldc + c] = v;
-  }
-  __syncthreads();
-}
-
-template <int NT = WG, class TS, class TD>
-__device__ inline void wg_copy(int M, int N, const TS* __restrict__ A, int lda, TD* __restrict__ C, int ldc) {
-  for (int idx = threadIdx.x; idx < M * N; idx += NT) {
-    int r = idx / N, c = idx - r * N;
-    C[(size_t)r * ldc + c] = (TD)A[(size_t)r * lda + c];
-  }
-  __syncthreads();
-}
-template <int NT = WG>
-__device__ inline void wg_zero(int M, int N, double* C, int ldc) {
-  for (int idx = threadIdx.x; idx < M * N; idx += NT) {
-    int r = idx / N, c = idx - r * N;
-    C[(size_t)r * ldc + c] = 0.0;
-  }
-  __syncthreads();
 }
 
 // In-place LU with row partial pivoting (ties to the lowest row) of the m x m row-major A;

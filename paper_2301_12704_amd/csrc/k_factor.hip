@@ -323,74 +323,6 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   }
 }
 
-// Left factor on the rows Z_x: every M2L block (x, c), c in IL(x), except the pair block,
-// and the L2L block become L_x * block.
-template <class RT>
-__global__ void __launch_bounds__(WG) k_row_xform(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
-                                                  int64_t wsz, int cap, int maxblk, double* scratch, int64_t sstride) {
-  RT* tmp = (RT*)scratch + (size_t)blockIdx.x * sstride;
-  size_t c2 = (size_t)cap * cap;
-  int total = nx * maxblk;
-  for (int task = blockIdx.x; task < total; task += gridDim.x) {
-    int t = task / maxblk, q = task - t * maxblk;
-    XformEntry X = xe[t];
-    int x = X.x;
-    int nil = P.il_off[x + 1] - P.il_off[x];
-    if (q > nil || (q == nil && P.l == 2)) continue;
-    int kold = P.k[x], knew = P.kn[x];
-    const RT* Lm = (const RT*)(ws + (size_t)X.pair * wsz) + (X.side ? 2 * c2 : 0);
-    double* B;
-    int cols, ld;
-    if (q < nil) {
-      int c = P.il[P.il_off[x] + q];
-      if (c == X.skip) continue;
-      B = P.slab + P.il_slot[P.il_off[x] + q];
-      cols = P.k[c];
-      ld = P.n[c];
-    } else {
-      B = P.slab + P.l2l_off[x];
-      cols = P.kP[x];
-      ld = cols;
-    }
-    int kold1 = kold > 0 ? kold : 1;
-    wg_gemm(knew, cols, kold, 1.0, Lm, kold1, false, B, ld, false, 0.0, tmp, cols > 0 ? cols : 1);
-    wg_copy(knew, cols, tmp, cols > 0 ? cols : 1, B, ld);
-  }
-}
-
-// Right factor on the columns y_x: every M2L block (d, x), d in IL(x), except the pair
-// block, becomes block * R_x^*; the M2M block (stored transposed) becomes R_x * block.
-template <class RT>
-__global__ void __launch_bounds__(WG) k_col_xform(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
-                                                  int64_t wsz, int cap, int maxblk, double* scratch, int64_t sstride) {
-  RT* tmp = (RT*)scratch + (size_t)blockIdx.x * sstride;
-  size_t c2 = (size_t)cap * cap;
-  int total = nx * maxblk;
-  for (int task = blockIdx.x; task < total; task += gridDim.x) {
-    int t = task / maxblk, q = task - t * maxblk;
-    XformEntry X = xe[t];
-    int x = X.x;
-    int nil = P.il_off[x + 1] - P.il_off[x];
-    if (q > nil || (q == nil && P.l == 2)) continue;
-    int kold = P.k[x], knew = P.kn[x];
-    int kold1 = kold > 0 ? kold : 1;
-    const RT* Rm = (const RT*)(ws + (size_t)X.pair * wsz) + (X.side ? 3 * c2 : c2);
-    if (q < nil) {
-      int dbox = P.il[P.il_off[x] + q];
-      if (dbox == X.skip) continue;
-      double* B = P.slab + P.il_slot[P.il_tr[P.il_off[x] + q]];
-      int rows = P.kn[dbox], ld = P.n[x];
-      wg_gemm(rows, knew, kold, 1.0, B, ld, false, Rm, kold1, true, 0.0, tmp, knew > 0 ? knew : 1);
-      wg_copy(rows, knew, tmp, knew > 0 ? knew : 1, B, ld);
-    } else {
-      double* B = P.slab + P.m2m_off[x];
-      int cols = P.kP[x];
-      wg_gemm(knew, cols, kold, 1.0, Rm, kold1, false, B, cols > 0 ? cols : 1, false, 0.0, tmp, cols > 0 ? cols : 1);
-      wg_copy(knew, cols, tmp, cols > 0 ? cols : 1, B, cols > 0 ? cols : 1);
-    }
-  }
-}
-
 __global__ void k_commit(LevelPtrs P, const XformEntry* __restrict__ xe, int nx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nx) P.k[xe[t].x] = P.kn[xe[t].x];
@@ -826,17 +758,19 @@ __global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int*
   }
 }
 
-// One 16-wide output slab of an in-place product on FP64 MFMA 16x16x4: out = opA opB (M x N,
-// K terms), element (i, k) of opA at A[i ai + k ak] and (k, j) of opB at B[k bk + j bj].
-// Every element is the ascending fused multiply-add chain from zero of wg_gemm (the slots past
-// K add exact zeros at its end).  The wave computes columns 16 s .. 16 s + 15 (colslab) or
-// rows 16 s .. 16 s + 15 of out into its workspace tmp (16 max(M, N) entries), then writes
-// them to dst (ldd).  dst may be the operand the slab came from: each output column (colslab)
-// or row depends only on the same column or row of that operand, and every read has been
-// consumed before the first write.
-__device__ inline void wave_xform_slab(int M, int N, int K, const double* A, int64_t ai, int64_t ak, const double* B,
-                                       int64_t bk, int64_t bj, bool colslab, int s, double* tmp, double* dst,
-                                       int64_t ldd) {
+// One 16-wide output slab of an in-place product on MFMA 16x16x4 of precision RT: out = opA opB
+// (M x N, K terms), element (i, k) of opA at A[i ai + k ak] and (k, j) of opB at B[k bk + j bj],
+// operands converted to RT.  In FP64 every element is the ascending fused multiply-add chain
+// from zero over k (the slots past K add exact zeros at its end); in FP32 (the precision
+// form) the order inside an MFMA is the hardware's.  The wave computes columns 16 s .. 16 s + 15
+// (colslab) or rows 16 s .. 16 s + 15 of out into its workspace tmp (16 max(M, N) entries),
+// then writes them to dst (ldd, FP64).  dst may be the operand the slab came from: each output
+// column (colslab) or row depends only on the same column or row of that operand, and every
+// read has been consumed before the first write.
+template <class RT, class TA, class TB>
+__device__ inline void wave_xform_slab(int M, int N, int K, const TA* A, int64_t ai, int64_t ak, const TB* B, int64_t bk,
+                                       int64_t bj, bool colslab, int s, RT* tmp, double* dst, int64_t ldd) {
+  using RT4 = typename MfmaT<sizeof(RT) == 4>::T4;
   const int lane = threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
   const int nt = colslab ? (M + 15) / 16 : (N + 15) / 16;
   const int nsteps = (K + 3) / 4;
@@ -844,25 +778,25 @@ __device__ inline void wave_xform_slab(int M, int N, int K, const double* A, int
   for (int t = 0; t < nt; ++t) {
     const int R0 = colslab ? 16 * t : 16 * s, C0 = colslab ? 16 * s : 16 * t;
     const bool aok = R0 + fr < M, bok = C0 + fr < N;
-    const double* Ar = A + (int64_t)(R0 + fr) * ai;
-    const double* Bc = B + (int64_t)(C0 + fr) * bj;
+    const TA* Ar = A + (int64_t)(R0 + fr) * ai;
+    const TB* Bc = B + (int64_t)(C0 + fr) * bj;
     auto fa = [&](int st) {
       int k = 4 * st + fk;
-      return (aok && k < K) ? Ar[(int64_t)k * ak] : 0.0;
+      return (aok && k < K) ? (RT)Ar[(int64_t)k * ak] : (RT)0;
     };
     auto fb = [&](int st) {
       int k = 4 * st + fk;
-      return (bok && k < K) ? Bc[(int64_t)k * bk] : 0.0;
+      return (bok && k < K) ? (RT)Bc[(int64_t)k * bk] : (RT)0;
     };
-    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    double pa[KC], pb[KC];
+    RT4 acc = {0, 0, 0, 0};
+    RT pa[KC], pb[KC];
 #pragma unroll
     for (int u = 0; u < KC; ++u) {
-      pa[u] = u < nsteps ? fa(u) : 0.0;
-      pb[u] = u < nsteps ? fb(u) : 0.0;
+      pa[u] = u < nsteps ? fa(u) : (RT)0;
+      pb[u] = u < nsteps ? fb(u) : (RT)0;
     }
     for (int s0 = 0; s0 < nsteps; s0 += KC) {
-      double ca[KC], cb[KC];
+      RT ca[KC], cb[KC];
 #pragma unroll
       for (int u = 0; u < KC; ++u) {
         ca[u] = pa[u];
@@ -872,18 +806,21 @@ __device__ inline void wave_xform_slab(int M, int N, int K, const double* A, int
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
           int st = s0 + KC + u;
-          pa[u] = st < nsteps ? fa(st) : 0.0;
-          pb[u] = st < nsteps ? fb(st) : 0.0;
+          pa[u] = st < nsteps ? fa(st) : (RT)0;
+          pb[u] = st < nsteps ? fb(st) : (RT)0;
         }
       }
 #pragma unroll
       for (int u = 0; u < KC; ++u)
         if (s0 + u < nsteps) acc = mfma16(ca[u], cb[u], acc);
     }
+    // output (lane, q): row R0 + lane / 16 + 4 q (FP64) or R0 + 4 (lane / 16) + q (FP32),
+    // column C0 + lane % 16
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      int r = R0 + fk + 4 * q, c = C0 + fr;
-      if (r < M && c < N) tmp[colslab ? r * 16 + fr : c * 16 + fk + 4 * q] = acc[q];
+      int rr = sizeof(RT) == 4 ? 4 * fk + q : fk + 4 * q;
+      int r = R0 + rr, c = C0 + fr;
+      if (r < M && c < N) tmp[colslab ? r * 16 + fr : c * 16 + rr] = acc[q];
     }
   }
   __threadfence_block();
@@ -892,29 +829,30 @@ __device__ inline void wave_xform_slab(int M, int N, int K, const double* A, int
     const int w = min(16, N - 16 * s);
     for (int idx = lane; idx < M * 16; idx += WAVE) {
       int f = idx / 16, u = idx % 16;
-      if (u < w) dst[(int64_t)f * ldd + 16 * s + u] = tmp[f * 16 + u];
+      if (u < w) dst[(int64_t)f * ldd + 16 * s + u] = (double)tmp[f * 16 + u];
     }
   } else {
     const int w = min(16, M - 16 * s);
     for (int idx = lane; idx < w * N; idx += WAVE) {
       int u = idx / N, f = idx % N;
-      dst[(int64_t)(16 * s + u) * ldd + f] = tmp[f * 16 + u];
+      dst[(int64_t)(16 * s + u) * ldd + f] = (double)tmp[f * 16 + u];
     }
   }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
 }
 
-// The basis changes of a round in FP64 (rows Z_x: L_x * block, as k_row_xform; columns y_x:
-// block * R_x^* and the M2M block R_x * block, as k_col_xform), one 16-wide slab of one block
-// per wave, through wave_xform_slab.  Work items (entry, block, slab) are spread over all waves
-// of the grid; wstride is each wave's workspace.
-__global__ void __launch_bounds__(WG) k_xform64(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
-                                                int64_t wsz, int cap, int maxblk, int nslab, int cols_side,
-                                                double* scratch, int64_t wstride) {
+// The basis changes of a round (rows Z_x: L_x * block; columns y_x: block * R_x^* and the M2M
+// block R_x * block), in the precision RT of the compression, one 16-wide slab of one block
+// per wave, through wave_xform_slab.  Work items (entry, block, slab) are spread over all
+// waves of the grid; wstride is each wave's workspace (doubles).
+template <class RT>
+__global__ void __launch_bounds__(WG) k_xform(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
+                                              int64_t wsz, int cap, int maxblk, int nslab, int cols_side,
+                                              double* scratch, int64_t wstride) {
   const int64_t gw = (int64_t)blockIdx.x * (WG / WAVE) + threadIdx.x / WAVE;
   const int64_t nw = (int64_t)gridDim.x * (WG / WAVE);
-  double* tmp = scratch + gw * wstride;
+  RT* tmp = (RT*)(scratch + gw * wstride);
   const size_t c2 = (size_t)cap * cap;
   const int64_t total = (int64_t)nx * maxblk * nslab;
   for (int64_t item = gw; item < total; item += nw) {
@@ -928,7 +866,7 @@ __global__ void __launch_bounds__(WG) k_xform64(LevelPtrs P, const XformEntry* _
     const int kold = P.k[x], knew = P.kn[x];
     const int kold1 = kold > 0 ? kold : 1;
     if (!cols_side) {
-      const double* Lm = ws + (size_t)X.pair * wsz + (X.side ? 2 * c2 : 0);
+      const RT* Lm = (const RT*)(ws + (size_t)X.pair * wsz) + (X.side ? 2 * c2 : 0);
       double* B;
       int cols, ld;
       if (q < nil) {
@@ -943,21 +881,21 @@ __global__ void __launch_bounds__(WG) k_xform64(LevelPtrs P, const XformEntry* _
         ld = cols;
       }
       if (16 * s >= cols) continue;
-      wave_xform_slab(knew, cols, kold, Lm, kold1, 1, B, ld, 1, true, s, tmp, B, ld);
+      wave_xform_slab<RT>(knew, cols, kold, Lm, kold1, 1, B, ld, 1, true, s, tmp, B, ld);
     } else {
-      const double* Rm = ws + (size_t)X.pair * wsz + (X.side ? 3 * c2 : c2);
+      const RT* Rm = (const RT*)(ws + (size_t)X.pair * wsz) + (X.side ? 3 * c2 : c2);
       if (q < nil) {
         int dbox = P.il[P.il_off[x] + q];
         if (dbox == X.skip) continue;
         double* B = P.slab + P.il_slot[P.il_tr[P.il_off[x] + q]];
         int rows = P.kn[dbox], ld = P.n[x];
         if (16 * s >= rows) continue;
-        wave_xform_slab(rows, knew, kold, B, ld, 1, Rm, 1, kold1, false, s, tmp, B, ld);
+        wave_xform_slab<RT>(rows, knew, kold, B, ld, 1, Rm, 1, kold1, false, s, tmp, B, ld);
       } else {
         double* B = P.slab + P.m2m_off[x];
         int cols = P.kP[x];
         if (16 * s >= cols) continue;
-        wave_xform_slab(knew, cols, kold, Rm, kold1, 1, B, cols, 1, true, s, tmp, B, cols);
+        wave_xform_slab<RT>(knew, cols, kold, Rm, kold1, 1, B, cols, 1, true, s, tmp, B, cols);
       }
     }
   }
@@ -1571,14 +1509,13 @@ static void factor_levels(aifmm_system& s) {
     int kPmax = 1;
     if (l > 2)
       for (int b = 0; b < lv.nb; ++b) kPmax = std::max(kPmax, s.lev[l - 1].knn[b >> s.d]);
-    int64_t sstride = (int64_t)cap * std::max(cap, kPmax);
-    // FP64 basis changes: 16-wide slabs, each wave with a workspace of 16 x maxdim
+    // basis changes: 16-wide slabs, each wave with a workspace of 16 x maxdim
     const int maxdim = std::max(cap, kPmax);
     const int nslab = cdiv(maxdim, 16);
     const int64_t wstride = (int64_t)16 * maxdim;
     DBuf<double> ws, scratch;
     ws.alloc((size_t)maxcol * wsz);
-    scratch.alloc((size_t)XG * std::max<int64_t>(sstride, (int64_t)(WG / WAVE) * wstride));
+    scratch.alloc((size_t)XG * (WG / WAVE) * wstride);
     // forward results of the pivot-block solves of one colour (a W-sized block per box) and the
     // LDS of the row permutation of each pivot-block LU
     int64_t tstride = 2;
@@ -1765,19 +1702,20 @@ static void factor_levels(aifmm_system& s) {
           AIFMM_HIP(hipLaunchCooperativeKernel(kcomp, dim3(ne * G), dim3(CT), args, shm, st));
         }
         AIFMM_HIP(hipEventRecord(ce.second, st));
-        int grid = std::min<int64_t>(XG, (int64_t)nx * maxblk);
-        if (f32) {
-          hipLaunchKernelGGL(k_row_xform<float>, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p,
-                             sstride);
-          hipLaunchKernelGGL(k_col_xform<float>, dim3(grid), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, scratch.p,
-                             sstride);
-        } else {
+        {
           int64_t items = (int64_t)nx * maxblk * nslab;
           int g64 = (int)std::min<int64_t>(XG, std::max<int64_t>(1, cdiv(items, WG / WAVE)));
-          hipLaunchKernelGGL(k_xform64, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
-                             scratch.p, wstride);
-          hipLaunchKernelGGL(k_xform64, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
-                             scratch.p, wstride);
+          if (f32) {
+            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
+                               scratch.p, wstride);
+            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
+                               scratch.p, wstride);
+          } else {
+            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
+                               scratch.p, wstride);
+            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
+                               scratch.p, wstride);
+          }
         }
         hipLaunchKernelGGL(k_commit, dim3(cdiv(nx, WG)), dim3(WG), 0, st, P, ex, nx);
       }

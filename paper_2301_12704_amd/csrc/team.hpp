@@ -108,14 +108,75 @@ __device__ inline void t_zero(Team<NT>& T, int M, int N, TD* C, int ldc) {
   T.sync();
 }
 // C = alpha op(A) op(B) + beta C, each element accumulated from zero in ascending k in the
-// precision of C, then scaled and added (as wg_gemm).  In FP64 the team's waves take 16 x 16
-// output tiles on FP64 MFMA 16x16x4, which adds its four products one fused multiply-add at a
-// time in ascending k (the slots past K add exact zeros at the end of the chain), so the
-// results are those of the sequential chains; other precisions take one element per thread.
+// precision of the operands, then scaled and added in C's precision.  The team's waves take
+// 16 x 16 output tiles on MFMA 16x16x4.  All-FP64 products use FP64 MFMA, which adds its four
+// products one fused multiply-add at a time in ascending k (the slots past K add exact zeros
+// at the end of the chain), so the results are those of the sequential chains; products with
+// an FP32 operand or result (the precision form) use FP32 MFMA with FP32 accumulation, in the
+// hardware's order inside an MFMA.
 template <int NT, class TA, class TB, class TC>
 __device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, const TA* __restrict__ A, int lda,
                               bool ta, const TB* __restrict__ B, int ldb, bool tb, double beta, TC* C, int ldc) {
-  if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8) {
+  if constexpr (sizeof(TA) == 4 || sizeof(TB) == 4 || sizeof(TC) == 4) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int KC = 8;
+    const int lane = (int)threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
+    const int wid = T.member * (NT / WAVE) + (int)threadIdx.x / WAVE, nwv = T.G * (NT / WAVE);
+    const int tm = (M + 15) / 16, tn = (N + 15) / 16, nsteps = (K + 3) / 4;
+    const size_t ai = ta ? 1 : (size_t)lda, ak = ta ? (size_t)lda : 1;
+    const size_t bk = tb ? 1 : (size_t)ldb, bj = tb ? (size_t)ldb : 1;
+    for (int tile = wid; tile < tm * tn; tile += nwv) {
+      const int R0 = (tile / tn) * 16, C0 = (tile % tn) * 16;
+      const bool aok = R0 + fr < M, bok = C0 + fr < N;
+      const TA* Ar = A + (size_t)(R0 + fr) * ai;
+      const TB* Bc = B + (size_t)(C0 + fr) * bj;
+      auto fa = [&](int s) {
+        int k = 4 * s + fk;
+        return (aok && k < K) ? (float)Ar[(size_t)k * ak] : 0.0f;
+      };
+      auto fb = [&](int s) {
+        int k = 4 * s + fk;
+        return (bok && k < K) ? (float)Bc[(size_t)k * bk] : 0.0f;
+      };
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      float pa[KC], pb[KC];
+#pragma unroll
+      for (int u = 0; u < KC; ++u) {
+        pa[u] = u < nsteps ? fa(u) : 0.0f;
+        pb[u] = u < nsteps ? fb(u) : 0.0f;
+      }
+      for (int s0 = 0; s0 < nsteps; s0 += KC) {
+        float ca[KC], cb[KC];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+          ca[u] = pa[u];
+          cb[u] = pb[u];
+        }
+        if (s0 + KC < nsteps) {
+#pragma unroll
+          for (int u = 0; u < KC; ++u) {
+            int s = s0 + KC + u;
+            pa[u] = s < nsteps ? fa(s) : 0.0f;
+            pb[u] = s < nsteps ? fb(s) : 0.0f;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < KC; ++u)
+          if (s0 + u < nsteps) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[u], cb[u], acc, 0, 0, 0);
+      }
+      // output (lane, q): row R0 + 4 (lane / 16) + q, column C0 + lane % 16 (FP32 MFMA layout)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = R0 + 4 * fk + q, c = C0 + fr;
+        if (r < M && c < N) {
+          TC v = (TC)((float)alpha * acc[q]);
+          if (beta != 0.0) v += (TC)beta * C[(size_t)r * ldc + c];
+          C[(size_t)r * ldc + c] = v;
+        }
+      }
+    }
+  } else {
+    static_assert(sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8, "FP64 or FP32 products only");
     typedef double d4 __attribute__((ext_vector_type(4)));
     constexpr int KC = 8;
     const int lane = (int)threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
@@ -172,17 +233,6 @@ __device__ inline void t_gemm(Team<NT>& T, int M, int N, int K, double alpha, co
           C[(size_t)r * ldc + c] = (TC)v;
         }
       }
-    }
-  } else {
-    for (int idx = T.gtid; idx < M * N; idx += T.GT) {
-      int r = idx / N, c = idx - r * N;
-      const TA* pa = ta ? A + r : A + (size_t)r * lda;
-      const TB* pb = tb ? B + (size_t)c * ldb : B + c;
-      size_t sa = ta ? (size_t)lda : 1, sb = tb ? 1 : (size_t)ldb;
-      TC acc = seq_dot(K, [&](int k) { return (TC)pa[k * sa]; }, [&](int k) { return (TC)pb[k * sb]; }, (TC)0);
-      TC v = (TC)alpha * acc;
-      if (beta != 0.0) v += (TC)beta * C[(size_t)r * ldc + c];
-      C[(size_t)r * ldc + c] = v;
     }
   }
   T.sync();
