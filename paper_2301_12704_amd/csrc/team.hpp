@@ -3,9 +3,9 @@
 // barrier is __syncthreads().  Team routines distribute their work over the G * NT team
 // threads and end with a team barrier, so results are visible to every member on return.
 //
-// Every output element is computed in one fixed order whatever G is: by one thread in the
-// order of the single-workgroup routines of dense_wg.hpp, or, for the row sums of the pivoted
-// QR and the Q formation, by one group of 16 lanes in the fixed chain-and-tree order below.
+// Every output element is computed in one fixed order whatever G is: by one MFMA tile of one
+// wave (the dense products), by one group of 16 lanes in the fixed chain-and-tree order below
+// (the row sums of the pivoted QR and the Q formation), or by one thread (copies).
 #pragma once
 #include "dense_wg.hpp"
 
