@@ -4,15 +4,15 @@
 //   1. compression rounds: round r compresses the r-th pending pair of every box of the
 //      colour (P2P pairs by four RRQRs, P2L/M2P pairs by two, Sec. 3.2.1-3.2.3), then the
 //      basis changes of the other blocks of the touched rows Z and columns y are applied
-//      (left factor L in one kernel, right factor R^* in the next, so no block is written
-//      by two workgroups at once);
+//      (left factors L in one launch, right factors R^* in the next, so no block element is
+//      written twice in a launch);
 //   2. elimination of every box of the colour: gather of the pivot block
 //      [[K_ii, U_i], [V_i^*, 0]] and of the coupled blocks, pivoted LU, triangular solves
 //      W = Piv^{-1} A[(X_i,Y_i), O_c], Schur update A[O_r, O_c] -= A[O_r, x_i] W_x and the
 //      new rows Z_i = W_z.
 // Between levels the remaining Z^{(l)} x y^{(l)} blocks become the next level's particle
 // blocks (eq. particleAtNonLeafLevel), and after level 2 the level-2 multipole system is
-// factored densely (Algorithm "Back Substitution", first line).
+// factored densely (it is solved directly at the end of the elimination, Sec. 3.2).
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
