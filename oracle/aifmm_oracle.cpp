@@ -96,7 +96,7 @@ int lu_factor(Mat& A, std::vector<int>& perm) {
 // Solve (LU) X = P B in place on B (n x m); perm from lu_factor (row i of PA = row perm[i] of A).
 // Forward substitution sums each row's terms in ascending column order.  Backward substitution
 // sums them in ascending column order, or with back_desc in descending column order (the
-// column-oriented back substitution of reading 29, used for the pivot blocks of the
+// column-oriented back substitution (the paper fixes no order), used for the pivot blocks of the
 // elimination).
 Mat lu_solve(const Mat& LU, const std::vector<int>& perm, const Mat& B, int counter = 1, bool back_desc = false) {
   int n = LU.r, m = B.c;
@@ -123,7 +123,7 @@ Mat lu_solve(const Mat& LU, const std::vector<int>& perm, const Mat& B, int coun
   return X;
 }
 
-// Householder QR with column pivoting (Q10 reading of the RRQR with threshold eps_A,
+// Householder QR with column pivoting (the reading taken of the RRQR with threshold eps_A,
 // Sec. 3.2.1): trailing column norms recomputed exactly every step, ties (within a relative
 // 1e-11) to the lowest column, stop at the smallest k with |R_{k+1,k+1}| <= tol |R_11|.
 // Norms and reflector products are row sums in the order of rowsum16.
@@ -140,8 +140,8 @@ struct Cpqr {
 
 const double kTieTol = 1e-11;
 
-// Sum over the rows i = a .. m-1 of x(i) y(i) in the fixed order of reading 28 (the paper fixes
-// no order): sixteen partial fused multiply-add chains, chain q taking the rows i = q (mod 16)
+// Sum over the rows i = a .. m-1 of x(i) y(i) in one fixed order, the device's too (the paper
+// fixes no order): sixteen partial fused multiply-add chains, chain q taking the rows i = q (mod 16)
 // in ascending order, then the pairwise tree ((t0 + t1) + (t2 + t3)) + ... over the chains.
 // Every row sum of the pivoted QR and of the Q formation is taken this way.
 template <class X, class Y>
@@ -220,7 +220,7 @@ Cpqr cpqr(const Mat& M, double tol) {
   return out;
 }
 // First q columns of Q = H_1 H_2 ... H_rank (m x q).  Columns beyond the rank are the
-// further columns of the same orthogonal Householder Q (Q11 reading).
+// further columns of the same orthogonal Householder Q (the paper leaves them open).
 Mat cpqr_q(const Cpqr& f, int q) {
   int m = f.m;
   Mat Q(m, q);
@@ -284,7 +284,7 @@ struct Kern {
   }
 };
 
-// ACA with partial pivoting (Q5 reading of the NNCA pivot search, Sec. 2.3).  Works on an
+// ACA with partial pivoting (the reading taken of the NNCA pivot search, Sec. 2.3).  Works on an
 // implicitly given m x n matrix; returns pivots in selection order and the factors.
 struct AcaOut {
   std::vector<int> I, J;
@@ -439,7 +439,7 @@ struct Level {
   std::vector<Mat> U, Vs;                  // leaf L2P U_B (n x k) and P2M V_B^* (k x n)
   std::vector<Mat> Ud, Vds;                // L2L U^dagger_B (k_B x k_P), M2M V^dagger*_B (k_P x k_B)
   std::vector<std::vector<Mat>> m2l;       // per box, per IL entry: A_BD (k_B x k_D)
-  std::vector<int> order;                  // elimination order (Q3)
+  std::vector<int> order;                  // elimination order: colour-major, Morton inside a colour
   std::vector<int> kfin, nfin;             // rank and x-size at elimination
 };
 
@@ -490,8 +490,9 @@ int cheb(const std::array<int, 3>& a, const std::array<int, 3>& b, int d) {
   return m;
 }
 
-// Sec. 2.1: smallest hypercube holding the points (Q2: centred at the bounding-box
-// midpoint, side = largest extent), uniform subdivision to depth L (Q1).
+// Sec. 2.1: smallest hypercube holding the points (centred at the bounding-box
+// midpoint, side = largest extent), uniform subdivision to depth
+// L = max(2, ceil(log_{2^d}(N / n_max))).
 void build_tree(oracle_sys& s) {
   int d = s.d;
   double lo[3], hi[3];
@@ -542,7 +543,7 @@ void build_tree(oracle_sys& s) {
       }
 }
 
-// Sec. 2.2, neighbour / interaction-list table (Q4: i in N(i); admissible iff integer
+// Sec. 2.2, neighbour / interaction-list table (i in N(i); admissible iff integer
 // Chebyshev distance >= 2, which is the eta = sqrt(d) condition on the box geometry).
 void build_lists(oracle_sys& s) {
   int d = s.d;
@@ -567,7 +568,7 @@ void build_lists(oracle_sys& s) {
   }
 }
 
-// Solve X C = B for X (C k x k, B r x k) through an LU of C^T (Q7: never an explicit inverse).
+// Solve X C = B for X (C k x k, B r x k) through an LU of C^T (never an explicit inverse).
 Mat right_solve(const Mat& C, const Mat& B) {
   Mat Ct = tr(C);
   std::vector<int> perm;
@@ -591,7 +592,7 @@ Mat kblock(const oracle_sys& s, const std::vector<int64_t>& r, const std::vector
 
 // Sec. 2.3: NNCA, bottom-up.  Row set T = t^B at the leaf and the children's incoming
 // pivots above it; column search space F^{B,i} = sources of IL(B) (eq. Fj).  Outgoing
-// pivots are the incoming ones swapped (Q6: u = v and a symmetric kernel).
+// pivots are the incoming ones swapped (u = v and a symmetric kernel).
 bool build_nnca(oracle_sys& s) {
   int d = s.d, L = s.L;
   for (int l = L; l >= 2; --l) {
@@ -671,7 +672,8 @@ bool build_nnca(oracle_sys& s) {
   return true;
 }
 
-// Sec. 3.1: the extended sparse system (equations X, Y, Z with the Q9 signs).
+// Sec. 3.1: the extended sparse system (equations X: K x + U z = b, Y: V^T x - y = 0,
+// Z: U^dagger z_P + sum A y - z = 0).
 void assemble(oracle_sys& s) {
   int d = s.d, L = s.L;
   Store& S = s.S;
@@ -715,7 +717,7 @@ void assemble(oracle_sys& s) {
   }
 }
 
-// Q3: colour-major order, colour = (c_1 mod 5, ..., c_d mod 5) lexicographic, Morton inside.
+// Colour-major order, colour = (c_1 mod 5, ..., c_d mod 5) lexicographic, Morton inside.
 void build_order(oracle_sys& s) {
   int d = s.d;
   for (int l = 2; l <= s.L; ++l) {
@@ -824,7 +826,7 @@ struct Comp {
 };
 
 // Sec. 3.2.1: compression and redirection of the P2P fill-in pair (P2P_ij, P2P_ji), with the
-// Q10-Q13 readings (four RRQRs, per-box rank = max of its U-side and V-side ranks,
+// Readings of Sec. 3.2.1-3.2.3 (four RRQRs, per-box rank = max of its U-side and V-side ranks,
 // coefficients by projection onto the final orthonormal bases).
 Comp compress_p2p(oracle_sys& s, int l, int i, int j) {
   Store& S = s.S;
@@ -863,7 +865,8 @@ Comp compress_p2p(oracle_sys& s, int l, int i, int j) {
 }
 
 // Sec. 3.2.2 and 3.2.3: compression of P2L_ri (row Z_r, column x_i) and M2P_ir (row X_i,
-// column y_r), r eliminated, i about to be eliminated.  Box r's bases are frozen (Q15).
+// column y_r), r eliminated, i about to be eliminated.  Box r's bases are frozen (bases of
+// eliminated boxes never change).
 Comp compress_p2l(oracle_sys& s, int l, int r, int i) {
   Store& S = s.S;
   Comp c;
@@ -1040,7 +1043,7 @@ bool factor(oracle_sys& s) {
     for (int q = 0; q < lv.nb; ++q) pos[lv.order[q]] = q;
     std::set<std::pair<int, int>> vP2P;   // unordered (min, max)
     std::set<std::pair<int, int>> vP2L;   // ordered (eliminated, not eliminated)
-    // colour batches of the order (Q3): the compressions of one batch touch disjoint rows and
+    // colour batches of the order: the compressions of one batch touch disjoint rows and
     // columns except for commuting left/right factors on shared M2L blocks, and an
     // elimination never touches another box of its batch, so every batch runs as: the
     // r-th compression of each of its boxes for r = 0, 1, ... (left factors of the round,
@@ -1057,7 +1060,7 @@ bool factor(oracle_sys& s) {
       size_t rounds = 0;
       for (int q = q0; q < q1; ++q) {
         int i = lv.order[q];
-        // pending P2P pairs containing i, by increasing partner position (Q14)
+        // pending P2P pairs containing i, by increasing partner position
         std::vector<std::pair<int, int>> todo;
         for (auto& pr : vP2P)
           if (pr.first == i || pr.second == i) {
@@ -1115,7 +1118,8 @@ bool factor(oracle_sys& s) {
       return false;
     }
   }
-  // Algorithm "Back Substitution", first line: the level-2 multipole system, factored densely (Q16)
+  // the level-2 multipole system, solved directly at the end of the elimination (Sec. 3.2):
+  // dense partial-pivot LU
   Level& l2 = s.lev[2];
   s.top_vars.clear();
   s.top_dims.clear();
@@ -1386,7 +1390,7 @@ oracle_sys* oracle_create(const double* pts, int64_t n, int d, int kind, double 
   s->K = Kern{s->pts.data(), d, kind, scale, shift};
   if (depth > 0) s->L = depth;
   else {
-    // Q1: L = max(2, ceil(log_{2^d}(N / n_max)))
+    // depth rule: L = max(2, ceil(log_{2^d}(N / n_max)))
     int L = 0;
     double cap = (double)leaf_size;
     while ((double)n > cap) { cap *= (double)(1 << d); ++L; }

@@ -71,7 +71,8 @@ def test_depth_rule_and_counts():
         assert np.array_equal(up, cnt.reshape(-1, 4).sum(1))
         cnt = up
     assert s.counts(0)[0] == 4096
-    # leaf membership by the Q2 rule, recomputed independently
+    # leaf membership by the hypercube rule (bounding-box midpoint, largest extent), recomputed
+    # independently
     pts = c["pts"]
     lo, hi = pts.min(0), pts.max(0)
     side = (hi - lo).max()

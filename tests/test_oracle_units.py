@@ -1,10 +1,10 @@
 """Pins of the oracle's dense building blocks against closed forms, library routines used as
 independent references, and brute force on tiny inputs.
 
-- ACA (NNCA pivot search, Q5 reading): an exact rank-r matrix is recovered with rank r; the
+- ACA with partial pivoting (the NNCA pivot search): an exact rank-r matrix is recovered with rank r; the
   skeleton (cross) identity M[:,J] M[I,J]^{-1} M[I,:]; the pivot rule (argmax of the residual
   row/column) checked step by step from the returned factors.
-- RRQR (Sec. 3.2.1 with the Q10 reading): orthonormal Q, upper-triangular R in pivoted order,
+- RRQR (Sec. 3.2.1, Householder QR with column pivoting): orthonormal Q, upper-triangular R in pivoted order,
   truncation rank against prescribed singular values, truncation residual bound.
 - Dense partial-pivot LU against numpy.linalg.solve and a singular case.
 - Kernel entries against closed forms; brute-force matvec against a numpy product.
@@ -55,7 +55,7 @@ def test_aca_exact_rank(r):
     rng = np.random.default_rng(10 + r)
     M = rng.standard_normal((40, r)) @ rng.standard_normal((r, 70))
     I, J, U, V = oracle.aca(M, 1e-12)
-    # the stopping test is taken after a term is added and that term is kept (Q5), so on an
+    # the stopping test is taken after a term is added and that term is kept, so on an
     # exact rank-r matrix the last of at most r+1 terms is rounding noise below the tolerance
     assert len(I) in (r, r + 1)
     if len(I) == r + 1:
