@@ -113,6 +113,7 @@ aifmm_status aifmm_factor(aifmm_system* s) {
   aifmm_status st = guarded(s, [&] {
     AIFMM_HIP(hipSetDevice(s->device));
     aifmm::factor_system(*s);
+    aifmm::prepare_solve(*s);
   });
   if (st == AIFMM_OK) s->factored = true;
   return st;

@@ -139,22 +139,23 @@ void matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ldx, 
   int64_t N = s.N;
   DBuf<double> xin, xt, yt, yout;
   const double* xs = x;
-  if (!x_dev) {
-    xin.alloc((size_t)ldx * nr);
-    AIFMM_HIP(hipMemcpyAsync(xin.p, x, sizeof(double) * ldx * nr, hipMemcpyHostToDevice, st));
+  int64_t ldxs = ldx;
+  if (!x_dev) {  // host x: its N rows per column staged compactly
+    xin.alloc((size_t)N * nr);
+    h2d_cols(xin.p, x, ldx, N, nr, st);
     xs = xin.p;
+    ldxs = N;
   }
   xt.alloc((size_t)N * nr);
   yt.alloc((size_t)N * nr);
-  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xs, ldx, s.d_perm.p, N, nr, xt.p);
+  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xs, ldxs, s.d_perm.p, N, nr, xt.p);
   matvec_tree(s, xt.p, nr, yt.p);
   if (y_dev) {
     hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, yt.p, s.d_perm.p, N, nr, y, ldy);
   } else {
-    yout.alloc((size_t)ldy * nr);
-    yout.zero(st);
-    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, yt.p, s.d_perm.p, N, nr, yout.p, ldy);
-    AIFMM_HIP(hipMemcpyAsync(y, yout.p, sizeof(double) * ldy * nr, hipMemcpyDeviceToHost, st));
+    yout.alloc((size_t)N * nr);
+    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, yt.p, s.d_perm.p, N, nr, yout.p, N);
+    d2h_cols(y, ldy, yout.p, N, nr, st);
   }
   AIFMM_HIP(hipStreamSynchronize(st));
 }
@@ -189,13 +190,15 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
   DBuf<double>&bt = G.bt, &xt = G.xt, &r = G.r, &w = G.w, &part = G.part, &dalpha = G.dalpha;
   std::vector<DBuf<double>>&V = G.V, &Z = G.Z;
   const double* bs = b;
-  if (!b_dev) {
-    if ((int64_t)G.bin.n < ldb * nr) G.bin.alloc((size_t)ldb * nr);
-    AIFMM_HIP(hipMemcpyAsync(G.bin.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
+  int64_t ldbs = ldb;
+  if (!b_dev) {  // host b: its N rows per column staged compactly
+    if ((int64_t)G.bin.n < N * nr) G.bin.alloc((size_t)N * nr);
+    h2d_cols(G.bin.p, b, ldb, N, nr, st);
     bs = G.bin.p;
+    ldbs = N;
   }
   xt.zero(st);
-  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(vec, WG)), dim3(WG), 0, st, bs, ldb, s.d_perm.p, N, nr, bt.p);
+  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(vec, WG)), dim3(WG), 0, st, bs, ldbs, s.d_perm.p, N, nr, bt.p);
   std::vector<double> bnorm = coldots(s, bt.p, bt.p, nr, part);
   for (auto& v : bnorm) v = std::sqrt(v);
   std::vector<int> done(nr, 0), its(nr, 0);
@@ -302,10 +305,9 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
     hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(vec, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, x, ldx);
   } else {
     DBuf<double>& xo = G.xo;
-    if (xo.n < (size_t)ldx * nr) xo.alloc((size_t)ldx * nr);
-    if (ldx > N) AIFMM_HIP(hipMemsetAsync(xo.p, 0, sizeof(double) * ldx * nr, st));
-    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(vec, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, xo.p, ldx);
-    AIFMM_HIP(hipMemcpyAsync(x, xo.p, sizeof(double) * ldx * nr, hipMemcpyDeviceToHost, st));
+    if (xo.n < (size_t)N * nr) xo.alloc((size_t)N * nr);
+    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(vec, WG)), dim3(WG), 0, st, xt.p, s.d_perm.p, N, nr, xo.p, N);
+    d2h_cols(x, ldx, xo.p, N, nr, st);
   }
   AIFMM_HIP(hipStreamSynchronize(st));
   bool ok = true;

@@ -4,6 +4,8 @@
 // level row-major (row, rhs) so every box touches contiguous rows.
 #include <algorithm>
 #include <chrono>
+#include <mutex>
+#include <string>
 
 #include "dense_wg.hpp"
 #include "system.hpp"
@@ -317,6 +319,29 @@ static void build_solve_plan(aifmm_system& s) {
   sc.built = true;
 }
 
+// Work buffers of one solve of nr columns: per level l the right-hand sides of the Z rows
+// (R[l-1]), the solution of the y / x variables (X[l-1], X[l] for l < L), the forward results
+// w = Piv^{-1} rhs of every box (W[l]) and the gathered coupled-column segments (G).
+struct SolveBufs {
+  std::vector<double*> R, X, W;
+  double* G = nullptr;
+};
+
+// Doubles of each work buffer for nr columns (R and X by level l - 1, W by level l), and G.
+static void solve_buf_sizes(aifmm_system& s, int nr, std::vector<int64_t>& rsz, std::vector<int64_t>& wsz,
+                            int64_t& gsz) {
+  int L = s.L;
+  rsz.assign(L + 1, 0);
+  wsz.assign(L + 1, 0);
+  for (int l = L; l >= 2; --l) {
+    rsz[l - 1] = std::max<int64_t>(1, s.lev[l].koff[s.lev[l].nb]) * nr;
+    wsz[l] = std::max<int64_t>(1, s.sc.lev[l].woff.back()) * nr;
+  }
+  int64_t gmax = 1;
+  for (int l = 2; l <= L; ++l) gmax = std::max(gmax, s.sc.lev[l].grows);
+  gsz = gmax * nr;
+}
+
 static void ensure_solve_buffers(aifmm_system& s, int nr) {
   SolveCache& sc = s.sc;
   if (!sc.built) build_solve_plan(s);
@@ -328,15 +353,15 @@ static void ensure_solve_buffers(aifmm_system& s, int nr) {
   sc.X.resize(L + 1);
   sc.W.clear();
   sc.W.resize(L + 1);
+  std::vector<int64_t> rsz, wsz;
+  int64_t gsz = 0;
+  solve_buf_sizes(s, nr, rsz, wsz, gsz);
   for (int l = L; l >= 2; --l) {
-    int64_t K = s.lev[l].koff[s.lev[l].nb];
-    sc.R[l - 1].alloc((size_t)std::max<int64_t>(1, K) * nr);
-    sc.X[l - 1].alloc((size_t)std::max<int64_t>(1, K) * nr);
-    sc.W[l].alloc((size_t)std::max<int64_t>(1, sc.lev[l].woff.back()) * nr);
+    sc.R[l - 1].alloc((size_t)rsz[l - 1]);
+    sc.X[l - 1].alloc((size_t)rsz[l - 1]);
+    sc.W[l].alloc((size_t)wsz[l]);
   }
-  int64_t gmax = 1;
-  for (int l = 2; l <= L; ++l) gmax = std::max(gmax, sc.lev[l].grows);
-  sc.G.alloc((size_t)gmax * nr);
+  sc.G.alloc((size_t)gsz);
   sc.nr_cap = nr;
 }
 
@@ -352,20 +377,36 @@ static void launch_rows(int ntask, const STask* t, const double* fslab, const do
   else hipLaunchKernelGGL((k_rows_gemm<16, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
 }
 
-// Solve with tree-ordered row-major right-hand sides (N x nr) on the device; x may alias nothing.
-// The launch sequence of one solve (buffers already sized for nr): kernels and one
-// device-to-device copy only, so it can also be captured into a graph.
-static void solve_tree_launch(aifmm_system& s, const double* rhs, int nr, double* x) {
+static SolveBufs cache_bufs(aifmm_system& s) {
+  SolveCache& sc = s.sc;
+  SolveBufs B;
+  B.R.assign(s.L + 1, nullptr);
+  B.X.assign(s.L + 1, nullptr);
+  B.W.assign(s.L + 1, nullptr);
+  for (int l = 0; l <= s.L; ++l) {
+    B.R[l] = sc.R[l].p;
+    B.X[l] = sc.X[l].p;
+    B.W[l] = sc.W[l].p;
+  }
+  B.G = sc.G.p;
+  return B;
+}
+
+// Solve with tree-ordered row-major right-hand sides (N x nr) on the device; x may be rhs
+// itself (then the solve runs in place), otherwise it aliases nothing.  The launch sequence of
+// one solve (buffers sized for nr): kernels and at most one device-to-device copy, so it can
+// also be captured into a graph.
+static void solve_tree_launch(aifmm_system& s, const double* rhs, int nr, double* x, const SolveBufs& B) {
   hipStream_t st = s.stream;
   int L = s.L;
   int64_t N = s.N;
   SolveCache& sc = s.sc;
   // rhs of the X rows of level L is the input; rhs of Z rows of level l = X rows of level l-1
-  AIFMM_HIP(hipMemcpyAsync(x, rhs, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, st));
-  auto Xrows = [&](int l) { return l == L ? x : sc.R[l].p; };   // rhs, overwritten in place
+  if (x != rhs) AIFMM_HIP(hipMemcpyAsync(x, rhs, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, st));
+  auto Xrows = [&](int l) { return l == L ? x : B.R[l]; };   // rhs, overwritten in place
   for (int l = L; l >= 2; --l) {
     int64_t K = s.lev[l].koff[s.lev[l].nb];
-    if (K > 0) hipLaunchKernelGGL(k_zero, dim3(cdiv(K * nr, WG)), dim3(WG), 0, st, sc.R[l - 1].p, K * nr);
+    if (K > 0) hipLaunchKernelGGL(k_zero, dim3(cdiv(K * nr, WG)), dim3(WG), 0, st, B.R[l - 1], K * nr);
   }
   // the forward sweep keeps rhs(X^{(L)}) in x; the backward sweep overwrites x with sol(x^{(L)})
   // box by box after every read of rhs(X_b) (the forward sweep has finished by then)
@@ -373,11 +414,11 @@ static void solve_tree_launch(aifmm_system& s, const double* rhs, int nr, double
     LevelDev& lv = s.lev[l];
     SolveLevel& sl = sc.lev[l];
     double* Xr = Xrows(l);
-    double* Zr = sc.R[l - 1].p;
+    double* Zr = B.R[l - 1];
     for (size_t c = 0; c + 1 < sl.fw_off.size(); ++c) {
-      launch_rows<0>(sl.fw_off[c + 1] - sl.fw_off[c], sl.fw.p + sl.fw_off[c], lv.fslab.p, Xr, sc.W[l].p, Zr, nullptr,
+      launch_rows<0>(sl.fw_off[c + 1] - sl.fw_off[c], sl.fw.p + sl.fw_off[c], lv.fslab.p, Xr, B.W[l], Zr, nullptr,
                      nr, st);
-      launch_rows<1>(sl.fu_off[c + 1] - sl.fu_off[c], sl.fu.p + sl.fu_off[c], lv.fslab.p, sc.W[l].p, Xr, Zr, nullptr,
+      launch_rows<1>(sl.fu_off[c + 1] - sl.fu_off[c], sl.fu.p + sl.fu_off[c], lv.fslab.p, B.W[l], Xr, Zr, nullptr,
                      nr, st);
     }
   }
@@ -385,8 +426,8 @@ static void solve_tree_launch(aifmm_system& s, const double* rhs, int nr, double
   // level-2 multipoles: y^{(2)} = Top^{-1} rhs(Z^{(2)})
   if (s.Ktop > 0) {
     int K = s.Ktop, nblk = (K + TB - 1) / TB;
-    double* Xt = sc.X[1].p;
-    hipLaunchKernelGGL(k_top_perm, dim3(cdiv((int64_t)K * nr, WG)), dim3(WG), 0, st, sc.R[1].p, sc.top_perm.p, K, nr, Xt);
+    double* Xt = B.X[1];
+    hipLaunchKernelGGL(k_top_perm, dim3(cdiv((int64_t)K * nr, WG)), dim3(WG), 0, st, B.R[1], sc.top_perm.p, K, nr, Xt);
     for (int bi = 0; bi < nblk; ++bi) {
       int b0 = bi * TB, w = std::min(TB, K - b0);
       hipLaunchKernelGGL(k_top_diag, dim3(1), dim3(WG), 0, st, s.d_top.p, K, b0, w, Xt, nr, 1);
@@ -404,14 +445,14 @@ static void solve_tree_launch(aifmm_system& s, const double* rhs, int nr, double
   for (int l = 2; l <= L; ++l) {
     LevelDev& lv = s.lev[l];
     SolveLevel& sl = sc.lev[l];
-    double* xs = l == L ? x : sc.X[l].p;
-    const double* ys = sc.X[l - 1].p;
+    double* xs = l == L ? x : B.X[l];
+    const double* ys = B.X[l - 1];
     for (size_t c = sl.bw_off.size() - 1; c-- > 0;) {
       int ng = sl.gs_off[c + 1] - sl.gs_off[c];
       if (ng > 0)
-        hipLaunchKernelGGL(k_gather_seg, dim3(ng), dim3(WG), 0, st, sl.gs.p + sl.gs_off[c], ys, xs, sc.G.p, nr);
-      launch_rows<2>(sl.bw_off[c + 1] - sl.bw_off[c], sl.bw.p + sl.bw_off[c], lv.fslab.p, sc.G.p, xs, nullptr,
-                     sc.W[l].p, nr, st);
+        hipLaunchKernelGGL(k_gather_seg, dim3(ng), dim3(WG), 0, st, sl.gs.p + sl.gs_off[c], ys, xs, B.G, nr);
+      launch_rows<2>(sl.bw_off[c + 1] - sl.bw_off[c], sl.bw.p + sl.bw_off[c], lv.fslab.p, B.G, xs, nullptr,
+                     B.W[l], nr, st);
     }
   }
   launch_check("backward sweep");
@@ -419,7 +460,7 @@ static void solve_tree_launch(aifmm_system& s, const double* rhs, int nr, double
 
 void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x) {
   ensure_solve_buffers(s, nr);
-  solve_tree_launch(s, rhs, nr, x);
+  solve_tree_launch(s, rhs, nr, x, cache_bufs(s));
   AIFMM_HIP(hipStreamSynchronize(s.stream));
 }
 
@@ -439,16 +480,19 @@ void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
   if ((int64_t)G.bt.n < N * nr) G.bt.alloc((size_t)N * nr);
   if ((int64_t)G.xt.n < N * nr) G.xt.alloc((size_t)N * nr);
   const double* bsrc = b;
-  if (!b_dev) {
-    if ((int64_t)G.bin.n < ldb * nr) G.bin.alloc((size_t)ldb * nr);
-    AIFMM_HIP(hipMemcpyAsync(G.bin.p, b, sizeof(double) * ldb * nr, hipMemcpyHostToDevice, st));
+  int64_t ldbs = ldb;
+  if (!b_dev) {  // host b: its N rows per column staged compactly
+    if ((int64_t)G.bin.n < N * nr) G.bin.alloc((size_t)N * nr);
+    h2d_cols(G.bin.p, b, ldb, N, nr, st);
     bsrc = G.bin.p;
+    ldbs = N;
   }
-  hipLaunchKernelGGL(k_perm_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, bsrc, ldb, s.d_perm.p, N, nr, G.bt.p);
+  hipLaunchKernelGGL(k_perm_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, bsrc, ldbs, s.d_perm.p, N, nr, G.bt.p);
   ensure_solve_buffers(s, nr);
   SolveCache& sc = s.sc;
+  const SolveBufs bufs = cache_bufs(s);
   if (graphs_off() || st == nullptr) {  // the legacy default stream cannot be captured
-    solve_tree_launch(s, G.bt.p, nr, G.xt.p);
+    solve_tree_launch(s, G.bt.p, nr, G.xt.p, bufs);
   } else {
     // the solve's few hundred launches replayed from one graph, captured for this column count
     // and these buffers (recaptured when either changes; a factorization resets it)
@@ -458,7 +502,7 @@ void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
       hipGraph_t g = nullptr;
       AIFMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       try {
-        solve_tree_launch(s, G.bt.p, nr, G.xt.p);
+        solve_tree_launch(s, G.bt.p, nr, G.xt.p, bufs);
       } catch (...) {
         (void)hipStreamEndCapture(st, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -477,14 +521,20 @@ void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
   if (x_dev) {
     hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, G.xt.p, s.d_perm.p, N, nr, x, ldx);
   } else {
-    if ((int64_t)G.xo.n < ldx * nr) G.xo.alloc((size_t)ldx * nr);
-    if (ldx > N) AIFMM_HIP(hipMemsetAsync(G.xo.p, 0, sizeof(double) * ldx * nr, st));
-    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, G.xt.p, s.d_perm.p, N, nr, G.xo.p, ldx);
-    AIFMM_HIP(hipMemcpyAsync(x, G.xo.p, sizeof(double) * ldx * nr, hipMemcpyDeviceToHost, st));
+    if ((int64_t)G.xo.n < N * nr) G.xo.alloc((size_t)N * nr);
+    hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, G.xt.p, s.d_perm.p, N, nr, G.xo.p, N);
+    d2h_cols(x, ldx, G.xo.p, N, nr, st);
   }
   AIFMM_HIP(hipStreamSynchronize(st));
   launch_check("solve");
   s.stats.solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// The solve's task lists, built right after a factorization so that later solves (including
+// the allocation-free one) find them ready.
+void prepare_solve(aifmm_system& s) {
+  if (!s.sc.built) build_solve_plan(s);
+  AIFMM_HIP(hipStreamSynchronize(s.stream));
 }
 
 }  // namespace aifmm

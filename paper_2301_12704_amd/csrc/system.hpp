@@ -92,6 +92,24 @@ struct DBuf {
   size_t bytes() const { return n * sizeof(T); }
 };
 
+// Host N x nr column-major array with leading dimension ld (>= N) to or from a compact device
+// array (leading dimension N).  Only the N rows of each column are touched on the host side, so
+// the caller's padding rows and anything past the last column stay as they are.
+inline void h2d_cols(double* dst, const double* src, int64_t ld, int64_t N, int64_t nr, hipStream_t st) {
+  if (ld == N)
+    AIFMM_HIP(hipMemcpyAsync(dst, src, sizeof(double) * N * nr, hipMemcpyHostToDevice, st));
+  else
+    AIFMM_HIP(hipMemcpy2DAsync(dst, sizeof(double) * N, src, sizeof(double) * ld, sizeof(double) * N, nr,
+                               hipMemcpyHostToDevice, st));
+}
+inline void d2h_cols(double* dst, int64_t ld, const double* src, int64_t N, int64_t nr, hipStream_t st) {
+  if (ld == N)
+    AIFMM_HIP(hipMemcpyAsync(dst, src, sizeof(double) * N * nr, hipMemcpyDeviceToHost, st));
+  else
+    AIFMM_HIP(hipMemcpy2DAsync(dst, sizeof(double) * ld, src, sizeof(double) * N, sizeof(double) * N, nr,
+                               hipMemcpyDeviceToHost, st));
+}
+
 struct KernelDesc {
   int kind;      // 0: exp(-r/scale), 1: 1/sqrt(r^2 + scale^2)
   double scale;  // > 0
@@ -295,6 +313,7 @@ void factor_system(aifmm_system& s);
 void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx,
                   bool b_dev, bool x_dev);
 void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x);
+void prepare_solve(aifmm_system& s);
 // k_gmres.hip
 void matvec_tree(aifmm_system& s, const double* x, int nr, double* y);
 void matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy, bool x_dev,
