@@ -55,6 +55,13 @@ def lib():
         L.oracle_cpqr.restype = i32
         L.oracle_create.argtypes = [vp, i64, i32, i32, d, d, d, i32, i32]
         L.oracle_create.restype = vp
+        L.oracle_create_mode.argtypes = [vp, i64, i32, i32, d, d, d, i32, i32, i32]
+        L.oracle_create_mode.restype = vp
+        L.oracle_rhs_violations.argtypes = [vp]
+        L.oracle_rhs_violations.restype = i64
+        L.oracle_row_set.argtypes = [vp, i32, i32, vp]
+        L.oracle_row_set.restype = i32
+        L.oracle_kexp.argtypes = [vp, i64, vp]
         L.oracle_error.argtypes = [vp]
         L.oracle_error.restype = ctypes.c_char_p
         for name in ["oracle_depth"]:
@@ -151,6 +158,19 @@ def aca(M, tol):
     return I[:r], J[:r], U[:r].T.copy(), V[:r].copy()
 
 
+def kexp(x):
+    """The exponential kernel's e^x routine, elementwise."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    lib().oracle_kexp(_p(x), x.size, _p(out))
+    return out
+
+
+# readings where the paper fixes no order or routine (oracle.h, ORACLE_MODE_*)
+MODE_STD_EXP, MODE_ASC_SUMS, MODE_ASC_BACK, MODE_SEQUENTIAL = 1, 2, 4, 8
+MODE_TEXTBOOK = 15
+
+
 def cpqr(M, tol, qcols=None):
     M = np.ascontiguousarray(M, dtype=np.float64)
     m, n = M.shape
@@ -165,13 +185,13 @@ def cpqr(M, tol, qcols=None):
 class System:
     """Oracle AIFMM system: build (tree, lists, NNCA, extended system) in the constructor."""
 
-    def __init__(self, pts, kernel, tol, leaf_size=64, depth=0):
+    def __init__(self, pts, kernel, tol, leaf_size=64, depth=0, mode=0):
         self.pts = np.ascontiguousarray(pts, dtype=np.float64)
         self.N, self.d = self.pts.shape
         self.kernel = kernel
         L = lib()
-        self.h = L.oracle_create(_p(self.pts), self.N, self.d, KERNELS[kernel[0]], kernel[1],
-                                 kernel[2], tol, leaf_size, depth)
+        self.h = L.oracle_create_mode(_p(self.pts), self.N, self.d, KERNELS[kernel[0]], kernel[1],
+                                      kernel[2], tol, leaf_size, depth, int(mode))
         err = L.oracle_error(self.h).decode()
         if err:
             raise RuntimeError(err)
@@ -266,6 +286,15 @@ class System:
 
     def far_fill(self):
         return lib().oracle_far_fill_count(self.h)
+
+    def rhs_violations(self):
+        return lib().oracle_rhs_violations(self.h)
+
+    def row_set(self, level, box):
+        n = lib().oracle_row_set(self.h, level, box, None)
+        out = np.zeros(max(n, 1), np.int64)
+        lib().oracle_row_set(self.h, level, box, _p(out))
+        return out[:n]
 
     def margins(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

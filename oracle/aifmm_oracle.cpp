@@ -36,6 +36,12 @@ struct Mat {
 
 double g_flops[5];
 
+// Arithmetic and ordering choices that the paper leaves open (see oracle.h, ORACLE_MODE_*):
+// the default follows the device's choices; the textbook mode takes the plainest reading of
+// each.  Set from the system's mode at the start of every call that computes.
+int g_mode = 0;
+enum { MODE_STD_EXP = 1, MODE_ASC_SUMS = 2, MODE_ASC_BACK = 4, MODE_SEQUENTIAL = 8 };
+
 Mat mul(const Mat& A, const Mat& B, int counter = -1) {
   Mat C(A.r, B.c);
   for (int i = 0; i < A.r; ++i)
@@ -146,6 +152,11 @@ const double kTieTol = 1e-11;
 // Every row sum of the pivoted QR and of the Q formation is taken this way.
 template <class X, class Y>
 double rowsum16(int a, int m, X x, Y y) {
+  if (g_mode & MODE_ASC_SUMS) {  // textbook order: one chain, ascending rows
+    double t = 0.0;
+    for (int i = a; i < m; ++i) t = std::fma(x(i), y(i), t);
+    return t;
+  }
   double t[16] = {0.0};
   for (int i = a; i < m; ++i) t[i % 16] = std::fma(x(i), y(i), t[i % 16]);
   for (int d = 1; d < 16; d *= 2)
@@ -277,7 +288,7 @@ struct Kern {
       r2 += z * z;
     }
     double v;
-    if (kind == 0) v = kexp(-std::sqrt(r2) / scale);
+    if (kind == 0) v = (g_mode & MODE_STD_EXP) ? std::exp(-std::sqrt(r2) / scale) : kexp(-std::sqrt(r2) / scale);
     else v = 1.0 / std::sqrt(r2 + scale * scale);
     if (i == j) v += shift;
     return v;
@@ -464,6 +475,11 @@ struct oracle_sys {
   std::vector<std::array<int, 6>> trace_ranks;     // r1..r4 (P2P) or r5, r6, then k_i', k_j'
   std::vector<std::array<double, 8>> trace_ratio;  // per RRQR: kept, next ratio
   int64_t far_fill = 0;
+  int mode = 0;
+  // rows whose right-hand side may be nonzero at this point of the elimination (the X rows of
+  // every level, and every row an elimination has updated); compressions must not transform them
+  std::set<int64_t> rhs_rows;
+  int64_t rhs_violations = 0;
   double cpqr_margin = 1e300, aca_stop = 1e300, aca_gap = 1e300;
   double flops[5] = {0, 0, 0, 0, 0};
   Mat dense_ext;  // built on demand
@@ -776,6 +792,8 @@ void merge_level(oracle_sys& s, int l) {
 
 void set_basis(oracle_sys& s, int l, int b, const Mat& U, const Mat& V) {
   Store& S = s.S;
+  // the new row Y_b is the old one transformed by the change of multipole basis
+  if (s.rhs_rows.count(var(VY, l, b))) ++s.rhs_violations;
   int k = U.c;
   S.dim[var(VY, l, b)] = k;
   S.dim[var(VZ, l, b)] = k;
@@ -798,6 +816,7 @@ void note_cpqr(oracle_sys& s, const Cpqr& f) {
 void row_update(oracle_sys& s, int l, int b, const Mat& Lb, int64_t skip_col) {
   Store& S = s.S;
   int64_t R = var(VZ, l, b);
+  if (s.rhs_rows.count(R)) ++s.rhs_violations;  // a row operation on a row with a right-hand side
   for (int64_t c : S.row_cols(R)) {
     if (c == var(Vz, l, b) || c == skip_col) continue;
     Mat* B = S.find(R, c);
@@ -1004,7 +1023,7 @@ bool eliminate(oracle_sys& s, int l, int i) {
     s.err = "singular self-block at level " + std::to_string(l) + " box " + std::to_string(i);
     return false;
   }
-  F.W = lu_solve(F.LU, F.perm, Rb, 1, true);
+  F.W = lu_solve(F.LU, F.perm, Rb, 1, !(g_mode & MODE_ASC_BACK));
   Mat Upd = mul(Cb, F.W, 2);
   // scatter: A[O_r, O_c] -= A[O_r, (x_i, z_i)] Piv^{-1} A[(X_i, Y_i), O_c]
   {
@@ -1021,6 +1040,7 @@ bool eliminate(oracle_sys& s, int l, int i) {
       ro += F.dOr[a];
     }
   }
+  for (int64_t r : F.Or) s.rhs_rows.insert(r);  // the elimination's right-hand-side updates
   for (int64_t r : F.PR)
     for (int64_t c : S.row_cols(r)) S.erase(r, c);
   for (int64_t c : F.PC)
@@ -1033,9 +1053,12 @@ bool eliminate(oracle_sys& s, int l, int i) {
 bool factor(oracle_sys& s) {
   int d = s.d, L = s.L;
   Store& S = s.S;
+  s.rhs_rows.clear();
+  s.rhs_violations = 0;
   for (int l = L; l >= 2; --l) {
     Level& lv = s.lev[l];
     if (l < L) merge_level(s, l);
+    for (int b = 0; b < lv.nb; ++b) s.rhs_rows.insert(var(VX, l, b));  // b on X^(L), stacked Z rows above
     lv.kfin.assign(lv.nb, 0);
     lv.nfin.assign(lv.nb, 0);
     std::vector<char> elim(lv.nb, 0);
@@ -1047,7 +1070,8 @@ bool factor(oracle_sys& s) {
     // columns except for commuting left/right factors on shared M2L blocks, and an
     // elimination never touches another box of its batch, so every batch runs as: the
     // r-th compression of each of its boxes for r = 0, 1, ... (left factors of the round,
-    // then right factors), then the eliminations
+    // then right factors), then the eliminations.  In the sequential mode every batch is one
+    // box: its compressions one after the other, then its elimination.
     for (int q0 = 0; q0 < lv.nb;) {
       auto colour = [&](int b) {
         int64_t c = 0;
@@ -1055,7 +1079,9 @@ bool factor(oracle_sys& s) {
         return c;
       };
       int q1 = q0;
-      while (q1 < lv.nb && colour(lv.order[q1]) == colour(lv.order[q0])) ++q1;
+      if (g_mode & MODE_SEQUENTIAL) q1 = q0 + 1;  // the Algorithm's order: one box after the other
+      else
+        while (q1 < lv.nb && colour(lv.order[q1]) == colour(lv.order[q0])) ++q1;
       std::vector<std::vector<std::pair<int, int>>> ops(q1 - q0);  // (kind, partner)
       size_t rounds = 0;
       for (int q = q0; q < q1; ++q) {
@@ -1311,6 +1337,7 @@ extern "C" {
 
 void oracle_kernel_block(const double* pts, int d, int kind, double scale, double shift,
                          const int64_t* rows, int64_t nr, const int64_t* cols, int64_t nc, double* out) {
+  g_mode = 0;  // unit routines and the brute-force product take the default readings
   Kern K{pts, d, kind, scale, shift};
   for (int64_t i = 0; i < nr; ++i)
     for (int64_t j = 0; j < nc; ++j) out[i * nc + j] = K(rows[i], cols[j]);
@@ -1318,6 +1345,7 @@ void oracle_kernel_block(const double* pts, int d, int kind, double scale, doubl
 
 void oracle_matvec_rows(const double* pts, int64_t n, int d, int kind, double scale, double shift,
                         const int64_t* rows, int64_t nsel, const double* x, int64_t nrhs, double* y) {
+  g_mode = 0;  // unit routines and the brute-force product take the default readings
   Kern K{pts, d, kind, scale, shift};
   std::vector<double> acc(nrhs);
   for (int64_t r = 0; r < nsel; ++r) {
@@ -1353,6 +1381,7 @@ int oracle_dense_solve(int64_t n, const double* A, int64_t nrhs, const double* B
 }
 
 int oracle_aca(const double* M, int m, int n, double tol, int* I, int* J, double* U, double* V) {
+  g_mode = 0;  // unit routines and the brute-force product take the default readings
   auto f = [&](int i, int j) { return M[(size_t)i * n + j]; };
   AcaOut a = aca_pp(m, n, f, tol);
   int k = (int)a.I.size();
@@ -1366,6 +1395,7 @@ int oracle_aca(const double* M, int m, int n, double tol, int* I, int* J, double
 }
 
 int oracle_cpqr(const double* M, int m, int n, double tol, int qcols, double* Q, int* perm, double* R) {
+  g_mode = 0;  // unit routines and the brute-force product take the default readings
   Mat A(m, n);
   for (size_t q = 0; q < (size_t)m * n; ++q) A.a[q] = M[q];
   Cpqr f = cpqr(A, tol);
@@ -1380,7 +1410,14 @@ int oracle_cpqr(const double* M, int m, int n, double tol, int qcols, double* Q,
 
 oracle_sys* oracle_create(const double* pts, int64_t n, int d, int kind, double scale, double shift,
                           double tol, int leaf_size, int depth) {
+  return oracle_create_mode(pts, n, d, kind, scale, shift, tol, leaf_size, depth, 0);
+}
+
+oracle_sys* oracle_create_mode(const double* pts, int64_t n, int d, int kind, double scale, double shift,
+                               double tol, int leaf_size, int depth, int mode) {
+  g_mode = mode;
   oracle_sys* s = new oracle_sys();
+  s->mode = mode;
   for (int q = 0; q < 5; ++q) g_flops[q] = 0;
   s->N = n;
   s->d = d;
@@ -1513,6 +1550,7 @@ int oracle_dense_extended(oracle_sys* s, int64_t* dim, double* out, int64_t* xco
 }
 
 int oracle_factor(oracle_sys* s) {
+  g_mode = s->mode;
   if (!s->err.empty()) return 4;
   if (s->factored) return 4;
   for (int q = 0; q < 5; ++q) g_flops[q] = 0;
@@ -1524,6 +1562,7 @@ int oracle_factor(oracle_sys* s) {
 }
 
 int oracle_solve(oracle_sys* s, const double* b, int64_t nrhs, double* x) {
+  g_mode = s->mode;
   if (!s->factored) return 4;
   return solve(*s, b, nrhs, x) ? 0 : 3;
 }
@@ -1544,6 +1583,23 @@ int64_t oracle_trace_ranks(oracle_sys* s, int* ranks, double* ratio, int64_t cap
   return n;
 }
 int64_t oracle_far_fill_count(oracle_sys* s) { return s->far_fill; }
+int64_t oracle_rhs_violations(oracle_sys* s) { return s->rhs_violations; }
+int oracle_row_set(oracle_sys* s, int level, int box, int64_t* out) {
+  // T_B: the box's points at the leaf, the children's incoming pivots (child order) above
+  if (level < 2 || level > s->L) return -1;
+  std::vector<int64_t> T;
+  if (level == s->L) T = s->lev[level].pts[box];
+  else
+    for (int ch = 0; ch < (1 << s->d); ++ch) {
+      const std::vector<int64_t>& t = s->lev[level + 1].ti[(box << s->d) | ch];
+      T.insert(T.end(), t.begin(), t.end());
+    }
+  if (out) for (size_t q = 0; q < T.size(); ++q) out[q] = T[q];
+  return (int)T.size();
+}
+void oracle_kexp(const double* x, int64_t n, double* out) {
+  for (int64_t q = 0; q < n; ++q) out[q] = kexp(x[q]);
+}
 int oracle_lists(oracle_sys* s, int level, int box, int* nbr, int* il) {
   if (level < 0 || level > s->L) return -1;
   Level& lv = s->lev[level];

@@ -52,6 +52,23 @@ int    oracle_cpqr(const double* M, int m, int n, double tol, int qcols, double*
 typedef struct oracle_sys oracle_sys;
 oracle_sys* oracle_create(const double* pts, int64_t n, int d, int kind, double scale, double shift,
                           double tol, int leaf_size, int depth);
+/* Readings where the paper fixes no operation order or arithmetic routine.  Mode 0 (the
+   default) takes the orders the device uses; the flags switch each to its textbook form:
+     ORACLE_MODE_STD_EXP     e^x of the exponential kernel from the C library (exp) instead of
+                             the Cody-Waite / Taylor routine;
+     ORACLE_MODE_ASC_SUMS    row sums of the pivoted QRs and Q formations as one ascending
+                             chain instead of sixteen interleaved chains and a tree;
+     ORACLE_MODE_ASC_BACK    back substitution of the pivot blocks in ascending column order;
+     ORACLE_MODE_SEQUENTIAL  the Algorithm's order box by box (each compression applied in full,
+                             then the elimination) instead of colour rounds.
+   ORACLE_MODE_TEXTBOOK = all four. */
+#define ORACLE_MODE_STD_EXP 1
+#define ORACLE_MODE_ASC_SUMS 2
+#define ORACLE_MODE_ASC_BACK 4
+#define ORACLE_MODE_SEQUENTIAL 8
+#define ORACLE_MODE_TEXTBOOK 15
+oracle_sys* oracle_create_mode(const double* pts, int64_t n, int d, int kind, double scale, double shift,
+                               double tol, int leaf_size, int depth, int mode);
 const char* oracle_error(oracle_sys* s);
 int    oracle_depth(oracle_sys* s);
 int    oracle_box_count(oracle_sys* s, int level, int* nb /* 2^(d*level) */);   /* n_b (x size) */
@@ -75,6 +92,14 @@ int64_t oracle_trace(oracle_sys* s, int* out, int64_t cap);
 int64_t oracle_trace_ranks(oracle_sys* s, int* ranks, double* ratio, int64_t cap);
 /* number of blocks ever created outside dist_inf <= 2 (must be 0) */
 int64_t oracle_far_fill_count(oracle_sys* s);
+/* number of compressions that transformed a row (Z by a left factor, Y by a new basis) whose
+   right-hand side may already be nonzero (must be 0: compressions never touch the RHS) */
+int64_t oracle_rhs_violations(oracle_sys* s);
+/* row set T_B of the NNCA of a box (original indices; the box's points at the leaf, the
+   children's incoming pivots above); returns |T_B| */
+int    oracle_row_set(oracle_sys* s, int level, int box, int64_t* out);
+/* the exponential kernel's e^x routine, elementwise */
+void   oracle_kexp(const double* x, int64_t n, double* out);
 /* N(box) and IL(box) at a level; returns 1000*|N| + |IL| */
 int    oracle_lists(oracle_sys* s, int level, int box, int* nbr, int* il);
 /* decision margins: min over all CPQR calls of |log(ratio)| where ratio = |R_kk|/(tol|R_11|)
