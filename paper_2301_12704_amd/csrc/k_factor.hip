@@ -191,6 +191,7 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     }
     if (split) {  // join (waits for a whole chain: a longer bound); every member takes the ranks
       T.sync(1u << 28);
+      if (T.bad) return;  // the other half's ranks may be stale: the host reports the failure
       r1 = tr[0];
       r2 = tr[1];
       r3 = tr[2];
@@ -214,7 +215,10 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       t_gemm(C, kjn, kj, nj, 1.0, nUj, cap, true, U_j, nj, false, 0.0, Lb_j, kj1);
       t_gemm(C, kjn, kj, nj, 1.0, nVj, cap, true, V_j, nj, false, 0.0, Rb_j, kj1);
     }
-    if (split) T.sync(1u << 28);
+    if (split) {
+      T.sync(1u << 28);
+      if (T.bad) return;
+    }
     int nj1 = nj > 0 ? nj : 1, ni1 = ni > 0 ? ni : 1;
     if (!split || inA) {
       // A_ij := L_i A_ij R_j^* + R~_ij^*,  L~_ij = U~_i^* P2P_ij (kin x nj), R~_ij = V~_j^* L~_ij^*
@@ -242,7 +246,10 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       C.sync();
       t_gemm(C, kjn, kin, ki, 1.0, u1, ki1, false, Rb_i, ki1, true, 1.0, Aji, ni);
     }
-    if (split) T.sync(1u << 28);
+    if (split) {
+      T.sync(1u << 28);
+      if (T.bad) return;
+    }
     // bases, fill-ins, ranks
     t_copy(T, ni, kin, nU, cap, (double*)U_i, ni);
     t_copy(T, ni, kin, nV, cap, (double*)V_i, ni);
@@ -283,12 +290,15 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       // RRQR: [U_i | M2P_ir] = U~_i L_ir
       t_copy(C, ni, ki, U_i, ni, Mc, ld);
       t_copy(C, ni, kr, M2P, nr, Mc + ki, ld);
+      // column storage of the chain: t1b, never t1, which holds the new A_ri below when both
+      // chains run on one workgroup
       r6 = t_cpqr(C, ni, ld, Mc, ld, tol, V2, cap, tau + cap, split ? nrmb : nrm, lnr, shv, vsh, pos, at, trr + 2,
-                  lcol, pubS, split ? t1b : t1);
+                  lcol, pubS, t1b);
       if (C.gtid == 0) tr[1] = r6;
     }
     if (split) {
       T.sync(1u << 28);
+      if (T.bad) return;
       r5 = tr[0];
       r6 = tr[1];
     }
@@ -302,13 +312,16 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
       t_gemm(C, kr, kin, ni, 1.0, P2L, ni, false, nV, cap, false, 1.0, t1, cap);
     }
     if (!split || !inA) {
-      t_formq(C, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, split ? t1b : t1);
+      t_formq(C, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, t1b);  // t1 holds A_ri here
       t_gemm(C, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
       // A_ir := L_i A_ir + U~_i^* M2P_ir
       t_gemm(C, kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
       t_gemm(C, kin, kr, ni, 1.0, nU, cap, true, M2P, nr, false, 1.0, t2, kr1);
     }
-    if (split) T.sync(1u << 28);
+    if (split) {
+      T.sync(1u << 28);
+      if (T.bad) return;
+    }
     t_copy(T, kr, kin, t1, cap, Ari, ni);
     t_copy(T, kin, kr, t2, kr1, Air, nr);
     t_copy(T, ni, kin, nU, cap, (double*)U_i, ni);
@@ -1406,9 +1419,64 @@ static void activate_level(aifmm_system& s, int l) {
   AIFMM_HIP(hipStreamSynchronize(st));
 }
 
+// Algorithmic work of the level's compressions from the decision log (launch order; ranks
+// before each compression replayed from the NNCA ranks), and the pivot-step chains of its
+// rounds: a P2P compression runs the chains RRQR1 -> RRQR3 and RRQR2 -> RRQR4, a P2L one RRQR5
+// and RRQR6, on two half-teams when the team is split (else one after the other).
+static void count_compress(aifmm_system& s, int l, const std::vector<int64_t>& r_off, size_t t0) {
+  LevelDev& lv = s.lev[l];
+  LevelStats& ls = s.stats.lvl[l];
+  std::vector<int> k(lv.knn);
+  auto rrqr = [](double m, double n, double r) {
+    double f = 0;
+    for (double q = 0; q < r; ++q) f += 4.0 * (m - q) * (n - q);
+    return f;
+  };
+  auto formq = [](double m, double r, double q) { return 4.0 * m * q * r; };
+  auto gemm = [](double a, double b, double c) { return 2.0 * a * b * c; };
+  for (size_t round = 0; round + 1 < r_off.size(); ++round) {
+    double crit = 0;
+    for (int64_t q = r_off[round]; q < r_off[round + 1]; ++q) {
+      const TraceRec& t = s.trace[t0 + q];
+      const int i = t.i, j = t.partner;
+      const double ni = lv.n[i], nj = lv.n[j], ki = k[i], kj = k[j];
+      const double r1 = t.r[0], r2 = t.r[1], r3 = t.r[2], r4 = t.r[3], kin = t.r[4], kjn = t.r[5];
+      double f = 0, ca, cb;
+      if (t.kind == 0) {
+        f += rrqr(ni, ki + nj, r1) + rrqr(nj, kj + ni, r2) + rrqr(nj, kj + r1, r3) + rrqr(ni, ki + r2, r4);
+        f += formq(ni, r1, r1) + formq(nj, r2, r2) + formq(ni, r1, kin - r1) + formq(ni, r4, kin);
+        f += formq(nj, r2, kjn - r2) + formq(nj, r3, kjn);
+        f += gemm(nj, r1, ni) + gemm(ni, r2, nj);
+        f += 2 * gemm(kin, ki, ni) + 2 * gemm(kjn, kj, nj);
+        f += gemm(kin, nj, ni) + gemm(kjn, kin, nj) + gemm(kin, kj, ki) + gemm(kin, kjn, kj);
+        f += gemm(kjn, ni, nj) + gemm(kin, kjn, ni) + gemm(kjn, ki, kj) + gemm(kjn, kin, ki);
+        ca = r1 + r3;
+        cb = r2 + r4;
+        k[i] = (int)kin;
+        k[j] = (int)kjn;
+      } else {
+        const double kr = kj;  // the eliminated partner's rank (frozen)
+        f += rrqr(ni, ki + kr, r1) + rrqr(ni, ki + kr, r2) + formq(ni, r1, kin) + formq(ni, r2, kin);
+        f += 2 * gemm(kin, ki, ni) + gemm(kr, kin, ki) + gemm(kr, kin, ni) + gemm(kin, kr, ki) + gemm(kin, kr, ni);
+        ca = r1;
+        cb = r2;
+        k[i] = (int)kin;
+      }
+      ls.compress_flops += f;
+      ls.pivot_steps += ca + cb;
+      crit = std::max(crit, std::max(ca, cb));  // the two chains overlap on split teams
+    }
+    ls.crit_steps += crit;
+    ls.rounds += 1;
+  }
+  ls.compressions += (double)(r_off.back() - r_off.front());
+}
+
 static void count_flops(aifmm_system& s, int l) {
   LevelDev& lv = s.lev[l];
   LevelPlan& P = s.plan[l];
+  LevelStats& ls = s.stats.lvl[l];
+  ls.boxes = lv.nb;
   for (int b = 0; b < lv.nb; ++b) {
     int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
     double R = 0, C = 0;
@@ -1423,6 +1491,11 @@ static void count_flops(aifmm_system& s, int l) {
     s.stats.schur_bytes += 8.0 * (R * n + n * C + 2.0 * R * C);
     s.stats.trsm_flops += 2.0 * m * m * (C + n);
     s.stats.lu_flops += 2.0 * m * m * m / 3.0;
+    ls.schur_flops += 2.0 * R * n * C;
+    ls.schur_bytes += 8.0 * (R * n + n * C + 2.0 * R * C);
+    ls.trsm_flops += 2.0 * m * m * C;
+    ls.trsm_flops_impl += 2.0 * m * m * (C + n);
+    ls.lu_flops += 2.0 * m * m * m / 3.0;
   }
 }
 
@@ -1454,6 +1527,18 @@ static bool lds_off() {
 
 static bool team_off() {
   const char* v = getenv("AIFMM_NO_TEAMS");
+  return v && *v && *v != '0';
+}
+
+// pivot-block LU panels factored in place in device memory, never staged in LDS
+static bool lu_panels_off() {
+  const char* v = getenv("AIFMM_NO_LDS_PANELS");
+  return v && *v && *v != '0';
+}
+
+// test switch: raise the team abort flag from the host before a level's first launch
+static bool debug_abort() {
+  const char* v = getenv("AIFMM_DEBUG_ABORT");
   return v && *v && *v != '0';
 }
 
@@ -1490,6 +1575,7 @@ static void factor_levels(aifmm_system& s) {
   s.stats.schur_flops = s.stats.schur_bytes = s.stats.trsm_flops = s.stats.lu_flops = 0;
   s.stats.schur_kernel_s = s.stats.compress_kernel_s = s.stats.schur_launches = s.stats.compress_launches = 0;
   s.stats.trsm_kernel_s = s.stats.trsm_launches = 0;
+  s.stats.lvl.assign(L + 1, LevelStats{});
   s.trace.clear();
   s.sc = SolveCache{};
   s.d_flag.zero(st);
@@ -1588,6 +1674,8 @@ static void factor_levels(aifmm_system& s) {
     DBuf<double> d_trr;
     d_tr.alloc(rent.size() * 6 + 6);
     d_trr.alloc(rent.size() * 8 + 8);
+    d_tr.zero(st);
+    d_trr.zero(st);
     P.trace = d_tr.p;
     P.trace_ratio = d_trr.p;
     size_t rix = 0;
@@ -1657,7 +1745,14 @@ static void factor_levels(aifmm_system& s) {
     d_part.alloc((size_t)std::max(1, maxcol) * 4 * GMAX);
     d_pub.alloc((size_t)std::max(1, maxcol) * 2 * GMAX * cap);
     d_abort.alloc(1);
-    d_abort.zero(st);
+    d_part.zero(st);
+    if (debug_abort()) {  // the abort flag raised before the first launch: every team barrier of
+      const int one = 1;  // the level falls through at once and the level reports the failure
+      AIFMM_HIP(hipMemcpyAsync(d_abort.p, &one, sizeof(int), hipMemcpyHostToDevice, st));
+      AIFMM_HIP(hipStreamSynchronize(st));
+    } else {
+      d_abort.zero(st);
+    }
     hipEvent_t ev[4];
     for (auto& e : ev) AIFMM_HIP(hipEventCreate(&e));
     std::vector<std::pair<hipEvent_t, hipEvent_t>> sch_ev, cmp_ev, trs_ev;
@@ -1725,7 +1820,7 @@ static void factor_levels(aifmm_system& s) {
       {
         // teams of up to 16 co-resident workgroups per pivot block
         const int Gl = (lu_coop > 0) ? std::max(1, std::min(16, lu_coop / std::max(1, nbox))) : 1;
-        int64_t dynb = (int64_t)lu_shm;
+        int64_t dynb = lu_panels_off() ? 0 : (int64_t)lu_shm;  // bytes the panels may use
         int* flagp = s.d_flag.p;
         unsigned* lctr = d_luctr.p;
         int* lst = d_lust.p;
@@ -1761,10 +1856,12 @@ static void factor_levels(aifmm_system& s) {
     if (d_abort.download(st)[0])
       throw Error{AIFMM_ERR_DEVICE, "level " + std::to_string(l) + ": a team barrier timed out"};
     double sch_before = s.stats.schur_kernel_s;
+    LevelStats& ls = s.stats.lvl[l];
     for (auto& pr : sch_ev) {
       float ms = 0;
       AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
       s.stats.schur_kernel_s += ms * 1e-3;
+      ls.schur_s += ms * 1e-3;
       s.stats.schur_launches += 1;
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
@@ -1773,6 +1870,7 @@ static void factor_levels(aifmm_system& s) {
       float ms = 0;
       AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
       s.stats.trsm_kernel_s += ms * 1e-3;
+      ls.trsm_s += ms * 1e-3;
       s.stats.trsm_launches += 1;
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
@@ -1781,6 +1879,7 @@ static void factor_levels(aifmm_system& s) {
       float ms = 0;
       AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
       s.stats.compress_kernel_s += ms * 1e-3;
+      ls.compress_s += ms * 1e-3;
       s.stats.compress_launches += 1;
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
@@ -1792,6 +1891,7 @@ static void factor_levels(aifmm_system& s) {
       for (auto& kv : team_hist) fprintf(stderr, " G%d%s:%d", kv.first.first, kv.first.second ? "L" : "", kv.second);
       fprintf(stderr, "\n");
     }
+    const size_t trace0 = s.trace.size();
     {
       std::vector<int> tr = d_tr.download(st, rent.size() * 6);
       std::vector<double> trr = d_trr.download(st, rent.size() * 8);
@@ -1810,6 +1910,7 @@ static void factor_levels(aifmm_system& s) {
     if (flag[0]) throw Error{AIFMM_ERR_SINGULAR, "singular self-block at level " + std::to_string(flag[2]) + " box " + std::to_string(flag[1])};
     for (int b = 0; b < lv.nb; ++b)
       if (lv.kfin[b] > lv.n[b]) throw Error{AIFMM_ERR_CAPACITY, "rank above box size"};
+    count_compress(s, l, r_off, trace0);
     {
       double f0 = s.stats.schur_flops;
       count_flops(s, l);
@@ -1824,6 +1925,7 @@ static void factor_levels(aifmm_system& s) {
       lv.xoff[b + 1] = lv.xoff[b] + lv.n[b];
       lv.koff[b + 1] = lv.koff[b] + lv.kfin[b];
     }
+    ls.factor_s = since(tl);
   }
   // top-level multipole system
   {

@@ -29,6 +29,8 @@ struct Team {
   int* abort = nullptr;       // set when a barrier waited too long; every later barrier returns
   unsigned epoch = 0;
   int slot = 0;
+  bool bad = false;           // the abort flag was seen at the last barrier: data exchanged through
+                              // the team may be stale, so callers stop using it and exit
 
   __device__ void init(int member_, int G_, unsigned* ctr_, Cand* part_, int* abort_) {
     member = member_;
@@ -45,8 +47,12 @@ struct Team {
   // 0's agent-scope release; thread 0's acquire after the wait makes the other members' writes
   // visible to the whole workgroup.  The wait is bounded (max_spins polls, a few seconds by
   // default): on expiry the abort flag is raised and the team falls through, so every
-  // workgroup still runs to its end and the host reports the failure.
+  // workgroup still runs to its end and the host reports the failure.  Thread 0 reads the flag
+  // after the wait and the workgroup takes its value through LDS, so bad is uniform over the
+  // workgroup (members of a team may see the flag at different barriers; once raised it stays
+  // raised, so every later barrier of every member falls through and sets bad).
   __device__ void sync(unsigned max_spins = 1u << 24) {
+    __shared__ int s_bad;
     __syncthreads();
     if (G == 1) return;
     if (threadIdx.x == 0) {
@@ -64,8 +70,10 @@ struct Team {
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_bad = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
     __syncthreads();
+    bad = s_bad != 0;
   }
 
   // Publish one value per member and return all G of them (the same array on every thread).
@@ -478,6 +486,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     }
     if (T.G > 1) {
       const Cand* all = T.exchange(Cand{ps.mx, ps.nv, ps.p, ps.amb});
+      if (T.bad) break;  // the members' candidates may be stale: no pivot is taken from them
       PivState g{-1.0, -1.0, INT_MAX, 0};
       for (int q = 0; q < T.G; ++q) g = piv_merge(g, PivState{all[q].mv, all[q].nv, all[q].p, all[q].pad}, keep);
       ps = g;
@@ -497,7 +506,9 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       for (int c = T.cid; c < n; c += T.GT)
         if (pos[c] >= s && lnr[c / T.G] >= thr && pos[c] < b2.i) b2 = ValIdx{0.0, pos[c]};
       pp = T.argmax(b2, shv).i;
+      if (T.bad) break;
     }
+    if (pp < s || pp >= n) break;  // no live column (cannot happen while s < min(m, n))
     const int cp = at[pp];
     // the pivot's norm: carried by the merged candidate state (its nv is the norm of the column
     // at position p); the exact fallback reads the owner's copy in device memory
@@ -522,6 +533,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
           for (int i = s + threadIdx.x; i < m; i += NT) oslot[i] = src[i];
         }
         T.sync();
+        if (T.bad) break;
       }
       pcol = oslot;
     }
@@ -706,6 +718,7 @@ __device__ inline int t_lu_blocked(Team<WG>& T, int m, double* A, int lda, int* 
       }
     }
     T.sync();
+    if (T.bad) return 1;  // member 0's status and pivots may be stale
     const int st = *(volatile int*)status;
     if (st) return st;
     // the panel's row swaps on every other column, in step order, then the U12 rows of the
@@ -742,6 +755,7 @@ __device__ inline int t_lu_blocked(Team<WG>& T, int m, double* A, int lda, int* 
       }
     }
     T.sync();
+    if (T.bad) return 1;
     if (c1 >= m) break;
     // A22 -= L21 U12 in 64 x 64 tiles (taken by the members in turn), each wave a 32 x 32
     // quarter as 2 x 2 FP64 MFMA 16x16x4 blocks accumulating onto the current entries
@@ -794,6 +808,7 @@ __device__ inline int t_lu_blocked(Team<WG>& T, int m, double* A, int lda, int* 
           }
     }
     T.sync();
+    if (T.bad) return 1;
   }
   return 0;
 }
