@@ -74,11 +74,16 @@ typedef struct {
   int32_t device;      /* HIP device ordinal */
   void* stream;        /* hipStream_t, NULL = default stream */
   int32_t prec;        /* aifmm_precision (default AIFMM_FP64) */
+  double matvec_tol;   /* eps_G of the H^2 operator (aifmm_matvec_h2, the operator of aifmm_gmres):
+                          0 (default) = the NNCA at tol itself; otherwise aifmm_build also builds a
+                          second NNCA of the same tree at this tolerance for the product (Sec. 4:
+                          the GMRES products use the NNCA-based H^2 product at tolerance eps_G) */
 } aifmm_options;
 
 typedef struct aifmm_system aifmm_system;
 
-/* Fill *opt with defaults (dim 2, leaf 64, depth auto, device 0, default stream, FP64). */
+/* Fill *opt with defaults (dim 2, leaf 64, depth auto, device 0, default stream, FP64, no
+ * separate matvec tolerance). */
 aifmm_status aifmm_options_default(aifmm_options* opt);
 
 /* Build the tree (Sec. 2.1), neighbour and interaction lists (Sec. 2.2, eta = sqrt(d)), the
@@ -96,17 +101,28 @@ aifmm_status aifmm_factor(aifmm_system* s);
 aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx);
 
 /* y = A x with every kernel entry evaluated in FP64 (exact product, O(N^2) work; used for
- * residuals and as the operator of aifmm_gmres).  Same layouts as aifmm_solve. */
+ * residuals, and the operator of aifmm_gmres when op is NULL).  Same layouts as aifmm_solve. */
 aifmm_status aifmm_matvec(aifmm_system* s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy);
 
+/* y = A~ x with the NNCA-based H^2 product (Sec. 2.3, the operator table: P2M, M2M, M2L, L2L, L2P
+ * over the interaction lists of every level, P2P of the leaf neighbours evaluated exactly) at the
+ * system's matvec tolerance (opt.matvec_tol, else tol).  Valid after aifmm_build (independent of
+ * aifmm_factor).  Same layouts as aifmm_solve.  O(N) work per column. */
+aifmm_status aifmm_matvec_h2(aifmm_system* s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy);
+
 /* Solve A x = b to relative residual ||A x - b|| / ||b|| <= rtol for every column with
- * right-preconditioned flexible GMRES(restart) in FP64: operator aifmm_matvec, preconditioner
- * the factored system's aifmm_solve (AIFMM as a preconditioner, Sec. 4, Experiment 5).  x is
- * an output (the iteration starts from 0).  iters[nrhs] and relres[nrhs] (may be NULL) receive
- * per-column iteration counts and true relative residuals.  AIFMM_ERR_NOCONV if some column
- * is above rtol after maxit iterations (x then holds the last iterate). */
-aifmm_status aifmm_gmres(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int32_t restart,
-                         int32_t maxit, double* x, int64_t ldx, int32_t* iters, double* relres);
+ * right-preconditioned flexible GMRES(restart) in FP64 (AIFMM as a preconditioner, Sec. 4,
+ * Experiment 5): preconditioner the factored system prec (its aifmm_solve), operator the H^2
+ * product of op (aifmm_matvec_h2 of op: its NNCA at its matvec tolerance eps_G) or, when op is
+ * NULL, prec's exact product (aifmm_matvec).  op may be prec itself (a system built with
+ * matvec_tol and factored) or another system built from the same points, kernel and options
+ * (AIFMM_ERR_ARG otherwise).  The stopping residual is the operator's, recomputed from b - A x at
+ * every restart and at the end.  x is an output (the iteration starts from 0).  iters[nrhs] and
+ * relres[nrhs] (may be NULL) receive per-column iteration counts and final relative residuals.
+ * AIFMM_ERR_NOCONV if some column is above rtol after maxit iterations (x then holds the last
+ * iterate).  Calls on the two systems are serialized with their other calls. */
+aifmm_status aifmm_gmres(aifmm_system* op, aifmm_system* prec, const double* b, int64_t nrhs, int64_t ldb, double rtol,
+                         int32_t restart, int32_t maxit, double* x, int64_t ldx, int32_t* iters, double* relres);
 
 /* Tree depth L. */
 aifmm_status aifmm_get_depth(const aifmm_system* s, int32_t* L);
@@ -130,6 +146,24 @@ enum {
   AIFMM_STAT_COUNT = 16
 };
 aifmm_status aifmm_get_stats(const aifmm_system* s, double* stats /* AIFMM_STAT_COUNT */);
+/* Figures of one level (2 <= level <= L) of the last factorization, into an array of doubles
+ * (AIFMM_LSTAT_COUNT slots).  Device times are HIP-event times of the level's launches on the
+ * system's stream.  Flop and byte counts are the algorithmic ones of the elimination per box
+ * (R coupled rows, C coupled columns, n = x size, m = n + k): Schur update 2 R n C flops and
+ * 8 (R n + n C + 2 R C) bytes, pivot-block solve 2 m^2 C (as executed 2 m^2 (C + n): W also holds
+ * Piv^{-1}[:, x_b] for the solve phase), pivot-block LU (2/3) m^3; the compressions' pivoted QRs
+ * (4 (rows - s)(cols - s) per pivot step s), Q formations (4 rows q rank) and coefficient products.
+ * CRIT_STEPS sums over the compression rounds the longest pivot-step chain of the round (the
+ * dependent barrier steps), PIVOT_STEPS counts all pivot steps.  AIFMM_ERR_STATE before
+ * aifmm_factor. */
+enum {
+  AIFMM_LSTAT_FACTOR_S = 0, AIFMM_LSTAT_SCHUR_FLOPS = 1, AIFMM_LSTAT_SCHUR_BYTES = 2, AIFMM_LSTAT_TRSM_FLOPS = 3,
+  AIFMM_LSTAT_TRSM_FLOPS_IMPL = 4, AIFMM_LSTAT_LU_FLOPS = 5, AIFMM_LSTAT_SCHUR_KERNEL_S = 6,
+  AIFMM_LSTAT_TRSM_KERNEL_S = 7, AIFMM_LSTAT_COMPRESS_KERNEL_S = 8, AIFMM_LSTAT_COMPRESS_FLOPS = 9,
+  AIFMM_LSTAT_COMPRESSIONS = 10, AIFMM_LSTAT_ROUNDS = 11, AIFMM_LSTAT_CRIT_STEPS = 12, AIFMM_LSTAT_PIVOT_STEPS = 13,
+  AIFMM_LSTAT_BOXES = 14, AIFMM_LSTAT_COUNT = 16
+};
+aifmm_status aifmm_get_level_stats(const aifmm_system* s, int32_t level, double* out /* AIFMM_LSTAT_COUNT */);
 /* Decision log of the last factorization (the decision-margin record of the compressions):
  * one record per compression of the static schedule, in launch order.  rec gets 10 ints per
  * compression: level, box i being eliminated, kind (0 = P2P pair (i, j), 1 = P2L pair (r, i)),
@@ -168,7 +202,8 @@ aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t
  * (8 + 60 when rtol > 0)) fits in hbm_budget next to the running ones (0 = 90% of the free
  * device memory at creation; a batch alone is always admitted).  rtol > 0 solves every
  * request to that relative residual with flexible GMRES(30) preconditioned by the factors
- * (aifmm_gmres); rtol = 0 uses the direct solve (aifmm_solve).  While served, the systems
+ * (aifmm_gmres with the system's own operator: its H^2 product when it was built with a
+ * matvec tolerance, else the exact product); rtol = 0 uses the direct solve (aifmm_solve).  While served, the systems
  * must not be used through other calls.
  * Errors: AIFMM_ERR_ARG (NULL, nsys <= 0, a system listed twice, max_cols <= 0, rtol < 0),
  * AIFMM_ERR_STATE (a system not factored), AIFMM_ERR_DEVICE (stream creation failed). */

@@ -62,6 +62,8 @@ def lib():
         L.oracle_row_set.argtypes = [vp, i32, i32, vp]
         L.oracle_row_set.restype = i32
         L.oracle_kexp.argtypes = [vp, i64, vp]
+        L.oracle_h2_matvec.argtypes = [vp, vp, i64, vp]
+        L.oracle_h2_matvec.restype = i32
         L.oracle_error.argtypes = [vp]
         L.oracle_error.restype = ctypes.c_char_p
         for name in ["oracle_depth"]:
@@ -251,6 +253,15 @@ class System:
         if st:
             raise RuntimeError("dense_extended failed")
         return M, xc
+
+    def h2_matvec(self, x):
+        """NNCA-based H^2 product with the system's operators (oracle_h2_matvec)."""
+        x2 = np.asfortranarray(x.reshape(self.N, -1), dtype=np.float64)
+        y = np.zeros_like(x2, order="F")
+        st = lib().oracle_h2_matvec(self.h, _p(x2), x2.shape[1], _p(y))
+        if st:
+            raise RuntimeError(f"h2 matvec status {st}")
+        return y.reshape(x.shape)
 
     def factor(self):
         st = lib().oracle_factor(self.h)

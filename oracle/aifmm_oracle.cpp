@@ -1328,6 +1328,82 @@ bool solve(oracle_sys& s, const double* b, int64_t nrhs, double* x) {
   return true;
 }
 
+// NNCA-based H^2 product y = A~ x (Sec. 2.3, the operator table): the far field of every
+// interaction-list pair (B, D) at every level through the nested operators, the near field of
+// the leaf neighbours exactly.  Upward pass: multipoles q_B = V_B^* x_B at the leaf (P2M) and
+// q_P = sum over children c of V^dagger*_c q_c above (M2M); M2L: l_B = sum over D in IL(B) of
+// A_BD q_D; downward pass: l_c += U^dagger_c l_P (L2L), then y_B = U_B l_B (L2P) plus
+// sum over X in N(B) of K_BX x_X (P2P).  x, y: N x nrhs column-major, original point order.
+void h2_matvec(oracle_sys& s, const double* x, int nrhs, double* y) {
+  int d = s.d, L = s.L;
+  std::vector<std::vector<Mat>> q(L + 1), loc(L + 1);
+  for (int l = L; l >= 2; --l) {
+    Level& lv = s.lev[l];
+    q[l].assign(lv.nb, Mat());
+    loc[l].assign(lv.nb, Mat());
+    for (int b = 0; b < lv.nb; ++b) {
+      int k = lv.knn[b];
+      loc[l][b] = Mat(k, nrhs);
+      if (l == L) {
+        const std::vector<int64_t>& t = lv.pts[b];
+        Mat xb((int)t.size(), nrhs);
+        for (size_t r = 0; r < t.size(); ++r)
+          for (int c = 0; c < nrhs; ++c) xb.at((int)r, c) = x[c * s.N + t[r]];
+        q[l][b] = k > 0 ? mul(lv.Vs[b], xb) : Mat(0, nrhs);
+      } else {
+        Level& dn = s.lev[l + 1];
+        Mat acc(k, nrhs);
+        for (int ch = 0; ch < (1 << d); ++ch) {
+          int c = (b << d) | ch;
+          if (k == 0 || dn.knn[c] == 0) continue;
+          Mat t = mul(dn.Vds[c], q[l + 1][c]);
+          for (size_t u = 0; u < t.a.size(); ++u) acc.a[u] += t.a[u];
+        }
+        q[l][b] = acc;
+      }
+    }
+  }
+  for (int l = 2; l <= L; ++l) {
+    Level& lv = s.lev[l];
+    for (int b = 0; b < lv.nb; ++b) {
+      if (lv.knn[b] == 0) continue;
+      for (size_t e = 0; e < lv.il[b].size(); ++e) {
+        int D = lv.il[b][e];
+        if (lv.knn[D] == 0) continue;
+        Mat t = mul(lv.m2l[b][e], q[l][D]);
+        for (size_t u = 0; u < t.a.size(); ++u) loc[l][b].a[u] += t.a[u];
+      }
+      if (l < L) {
+        Level& dn = s.lev[l + 1];
+        for (int ch = 0; ch < (1 << d); ++ch) {
+          int c = (b << d) | ch;
+          if (dn.knn[c] == 0) continue;
+          Mat t = mul(dn.Ud[c], loc[l][b]);
+          for (size_t u = 0; u < t.a.size(); ++u) loc[l + 1][c].a[u] += t.a[u];
+        }
+      }
+    }
+  }
+  Level& lv = s.lev[L];
+  for (int64_t q0 = 0; q0 < s.N * nrhs; ++q0) y[q0] = 0.0;
+  for (int b = 0; b < lv.nb; ++b) {
+    const std::vector<int64_t>& t = lv.pts[b];
+    if (t.empty()) continue;
+    Mat yb((int)t.size(), nrhs);
+    if (lv.knn[b] > 0) yb = mul(lv.U[b], loc[L][b]);
+    for (int X : lv.nbr[b]) {
+      const std::vector<int64_t>& u = lv.pts[X];
+      for (size_t r = 0; r < t.size(); ++r)
+        for (size_t j = 0; j < u.size(); ++j) {
+          double a = s.K(t[r], u[j]);
+          for (int c = 0; c < nrhs; ++c) yb.at((int)r, c) += a * x[c * s.N + u[j]];
+        }
+    }
+    for (size_t r = 0; r < t.size(); ++r)
+      for (int c = 0; c < nrhs; ++c) y[c * s.N + t[r]] = yb.at((int)r, c);
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -1581,6 +1657,12 @@ int64_t oracle_trace_ranks(oracle_sys* s, int* ranks, double* ratio, int64_t cap
     for (int t = 0; t < 8; ++t) ratio[q * 8 + t] = s->trace_ratio[q][t];
   }
   return n;
+}
+int oracle_h2_matvec(oracle_sys* s, const double* x, int64_t nrhs, double* y) {
+  g_mode = s->mode;
+  if (!s->err.empty() || s->lev.empty() || s->lev[s->L].U.empty()) return 4;
+  h2_matvec(*s, x, (int)nrhs, y);
+  return 0;
 }
 int64_t oracle_far_fill_count(oracle_sys* s) { return s->far_fill; }
 int64_t oracle_rhs_violations(oracle_sys* s) { return s->rhs_violations; }

@@ -83,6 +83,10 @@ int    oracle_elim_order(oracle_sys* s, int level, int* order);
 /* dense extended matrix before elimination (small problems only). Writes dim into *dim;
    if out != NULL fills the dim x dim matrix and xcols[N] = column of x_m for original point m */
 int    oracle_dense_extended(oracle_sys* s, int64_t* dim, double* out, int64_t* xcols);
+/* NNCA-based H^2 product y = A~ x with the system's NNCA operators at its tolerance (P2M,
+   M2M, M2L, L2L, L2P over the interaction lists, P2P over the leaf neighbours); x, y: N x nrhs
+   column-major, original order.  Valid after create (independent of factor); 0 on success */
+int    oracle_h2_matvec(oracle_sys* s, const double* x, int64_t nrhs, double* y);
 int    oracle_factor(oracle_sys* s);
 int    oracle_solve(oracle_sys* s, const double* b, int64_t nrhs, double* x);
 /* compression trace: rows of 4 ints (level, box being eliminated, kind 0=P2P 1=P2L, partner) */

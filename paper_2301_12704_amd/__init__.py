@@ -17,6 +17,9 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_SINGULAR", 4: "ERR_STAT
 STAT_NAMES = ["build_s", "factor_s", "solve_s", "schur_flops", "schur_bytes", "trsm_flops", "lu_flops",
               "device_bytes", "schur_kernel_s", "schur_launches", "compress_kernel_s", "compress_launches", "gmres_s",
               "trsm_kernel_s", "trsm_launches"]
+LSTAT_NAMES = ["factor_s", "schur_flops", "schur_bytes", "trsm_flops", "trsm_flops_impl", "lu_flops", "schur_kernel_s",
+               "trsm_kernel_s", "compress_kernel_s", "compress_flops", "compressions", "rounds", "crit_steps",
+               "pivot_steps", "boxes"]
 
 
 class AifmmError(RuntimeError):
@@ -31,7 +34,8 @@ class _Kernel(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("prec", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("prec", ctypes.c_int32),
+                ("matvec_tol", ctypes.c_double)]
 
 
 _lib = None
@@ -57,11 +61,15 @@ def lib():
         L.aifmm_get_depth.argtypes = [vp, ctypes.POINTER(i32)]
         L.aifmm_get_ranks.argtypes = [vp, i32, vp]
         L.aifmm_get_stats.argtypes = [vp, vp]
+        L.aifmm_get_level_stats.argtypes = [vp, i32, vp]
+        L.aifmm_get_level_stats.restype = ctypes.c_int
         L.aifmm_get_trace.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.aifmm_get_trace.restype = ctypes.c_int
         L.aifmm_matvec.argtypes = [vp, vp, i64, i64, vp, i64]
         L.aifmm_matvec.restype = ctypes.c_int
-        L.aifmm_gmres.argtypes = [vp, vp, i64, i64, d, i32, i32, vp, i64, vp, vp]
+        L.aifmm_matvec_h2.argtypes = [vp, vp, i64, i64, vp, i64]
+        L.aifmm_matvec_h2.restype = ctypes.c_int
+        L.aifmm_gmres.argtypes = [vp, vp, vp, i64, i64, d, i32, i32, vp, i64, vp, vp]
         L.aifmm_gmres.restype = ctypes.c_int
         L.aifmm_get_nnca.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.aifmm_get_nnca.restype = ctypes.c_int
@@ -102,7 +110,8 @@ def _ptr(a):
 class System:
     """One N-body system A x = b, A_ij = kappa(|p_i - p_j|) + shift delta_ij (aifmm_build)."""
 
-    def __init__(self, points, kernel, tol, leaf_size=64, depth=0, device=0, stream=None, precision="fp64"):
+    def __init__(self, points, kernel, tol, leaf_size=64, depth=0, device=0, stream=None, precision="fp64",
+                 matvec_tol=0.0):
         self._h = None
         if hasattr(points, "data_ptr"):
             pts = points.contiguous()
@@ -117,6 +126,8 @@ class System:
         opt.dim, opt.leaf_size, opt.depth, opt.device = d, leaf_size, depth, device
         opt.stream = stream
         opt.prec = {"fp64": 0, "fp32": 1}[precision]
+        opt.matvec_tol = float(matvec_tol)
+        self.matvec_tol = float(matvec_tol)
         k = _Kernel(KERNELS[kernel[0]], float(kernel[1]), float(kernel[2]))
         h = ctypes.c_void_p()
         _check(lib().aifmm_build(_ptr(pts), n, k, float(tol), ctypes.byref(opt), ctypes.byref(h)))
@@ -159,15 +170,27 @@ class System:
         _check(lib().aifmm_matvec(self._h, _ptr(x2), x2.shape[1], self.N, _ptr(y), self.N), self._h)
         return y.reshape(np.shape(x))
 
-    def gmres(self, b, rtol=1e-10, restart=30, maxit=200, raise_on_noconv=True):
-        """FGMRES to ||Ax-b||/||b|| <= rtol, preconditioned by the factorization.
+    def matvec_h2(self, x):
+        """y = A~ x, the NNCA-based H^2 product at the system's matvec tolerance."""
+        x2 = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(self.N, -1))
+        y = np.zeros_like(x2, order="F")
+        _check(lib().aifmm_matvec_h2(self._h, _ptr(x2), x2.shape[1], self.N, _ptr(y), self.N), self._h)
+        return y.reshape(np.shape(x))
+
+    def gmres(self, b, rtol=1e-10, restart=30, maxit=200, raise_on_noconv=True, op="auto"):
+        """FGMRES to ||Ax-b||/||b|| <= rtol, preconditioned by the factorization.  op: the
+        System whose H^2 product is the operator; "auto" = this system's own when it was built
+        with a matvec tolerance, else the exact product; None = the exact product.
         Returns (x, iters, relres)."""
+        if isinstance(op, str):
+            op = self if self.matvec_tol > 0 else None
+        oph = op._h if op is not None else None
         b2 = np.asfortranarray(np.asarray(b, dtype=np.float64).reshape(self.N, -1))
         x = np.zeros_like(b2, order="F")
         it = np.zeros(b2.shape[1], np.int32)
         rr = np.zeros(b2.shape[1])
-        st = lib().aifmm_gmres(self._h, _ptr(b2), b2.shape[1], self.N, float(rtol), restart, maxit, _ptr(x), self.N,
-                               _ptr(it), _ptr(rr))
+        st = lib().aifmm_gmres(oph, self._h, _ptr(b2), b2.shape[1], self.N, float(rtol), restart, maxit, _ptr(x),
+                               self.N, _ptr(it), _ptr(rr))
         if st != 0 and (raise_on_noconv or st != 6):
             _check(st, self._h)
         return x.reshape(np.shape(b)), it, rr
@@ -198,6 +221,12 @@ class System:
         rat = np.zeros((max(n, 1), 8))
         _check(lib().aifmm_get_trace(self._h, _ptr(rec), _ptr(rat), n, ctypes.byref(cnt)), self._h)
         return rec[:n], rat[:n]
+
+    def level_stats(self, level):
+        """Per-level figures of the last factorization (aifmm_get_level_stats)."""
+        out = np.zeros(16)
+        _check(lib().aifmm_get_level_stats(self._h, level, _ptr(out)), self._h)
+        return dict(zip(LSTAT_NAMES, out[: len(LSTAT_NAMES)]))
 
     def stats(self):
         out = np.zeros(16)

@@ -7,6 +7,8 @@
 #include <thread>
 #include <vector>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -55,6 +57,7 @@ aifmm_status aifmm_options_default(aifmm_options* opt) {
   opt->device = 0;
   opt->stream = nullptr;
   opt->prec = AIFMM_FP64;
+  opt->matvec_tol = 0.0;
   return AIFMM_OK;
 }
 
@@ -73,6 +76,7 @@ aifmm_status aifmm_build(const double* points, int64_t n, aifmm_kernel kernel, d
   if (o.prec != AIFMM_FP64 && o.prec != AIFMM_FP32) return fail(nullptr, AIFMM_ERR_ARG, "bad precision");
   if (!(kernel.scale > 0.0) || !std::isfinite(kernel.shift)) return fail(nullptr, AIFMM_ERR_ARG, "bad kernel scale/shift");
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(nullptr, AIFMM_ERR_ARG, "tol must be in (0, 1)");
+  if (!(o.matvec_tol >= 0.0) || !(o.matvec_tol < 1.0)) return fail(nullptr, AIFMM_ERR_ARG, "matvec_tol must be in [0, 1)");
   if (n > (int64_t)1 << 30) return fail(nullptr, AIFMM_ERR_ARG, "n too large");
   aifmm_system* s = new (std::nothrow) aifmm_system();
   if (!s) return fail(nullptr, AIFMM_ERR_NOMEM, "host allocation failed");
@@ -95,7 +99,25 @@ aifmm_status aifmm_build(const double* points, int64_t n, aifmm_kernel kernel, d
   if (s->L > (o.dim == 2 ? 10 : 7)) { delete s; return fail(nullptr, AIFMM_ERR_ARG, "tree too deep"); }
   aifmm_status st = guarded(s, [&] {
     AIFMM_HIP(hipSetDevice(s->device));
-    aifmm::build_system(*s, points, is_device_ptr(points));
+    bool dev = is_device_ptr(points);
+    aifmm::build_system(*s, points, dev);
+    if (o.matvec_tol > 0.0 && o.matvec_tol != tol) {
+      // the H^2 operator: the same tree with its own NNCA at the matvec tolerance
+      std::unique_ptr<aifmm_system> op(new aifmm_system());
+      op->d = s->d;
+      op->N = s->N;
+      op->leaf = s->leaf;
+      op->L = s->L;
+      op->device = s->device;
+      op->stream = s->stream;
+      op->tol = o.matvec_tol;
+      op->prec = AIFMM_FP64;
+      op->K = s->K;
+      aifmm::build_system(*op, points, dev);
+      s->stats.build_s += op->stats.build_s;
+      s->op = std::move(op);
+    }
+    s->matvec_tol = o.matvec_tol > 0.0 ? o.matvec_tol : tol;
   });
   if (st != AIFMM_OK) {
     g_err = s->err;
@@ -182,17 +204,41 @@ aifmm_status aifmm_matvec(aifmm_system* s, const double* x, int64_t nrhs, int64_
   });
 }
 
-aifmm_status aifmm_gmres(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int32_t restart,
-                         int32_t maxit, double* x, int64_t ldx, int32_t* iters, double* relres) {
+aifmm_status aifmm_matvec_h2(aifmm_system* s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy) {
   if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
   std::lock_guard<std::mutex> lk(s->use);
+  if (!x || !y || nrhs <= 0 || ldx < s->N || ldy < s->N || nrhs > 4096) return fail(s, AIFMM_ERR_ARG, "bad x/y/nrhs/ld");
+  return guarded(s, [&] {
+    AIFMM_HIP(hipSetDevice(s->device));
+    aifmm::h2_matvec_system(*s, x, nrhs, ldx, y, ldy, is_device_ptr(x), is_device_ptr(y));
+  });
+}
+
+aifmm_status aifmm_gmres(aifmm_system* op, aifmm_system* prec, const double* b, int64_t nrhs, int64_t ldb, double rtol,
+                         int32_t restart, int32_t maxit, double* x, int64_t ldx, int32_t* iters, double* relres) {
+  aifmm_system* s = prec;
+  if (!s) return fail(nullptr, AIFMM_ERR_ARG, "preconditioner system is NULL");
+  std::unique_lock<std::mutex> la(s->use, std::defer_lock), lb;
+  if (op && op != s) {
+    lb = std::unique_lock<std::mutex>(op->use, std::defer_lock);
+    std::lock(la, lb);
+  } else {
+    la.lock();
+  }
   if (!s->factored) return fail(s, AIFMM_ERR_STATE, "gmres before factor");
   if (!b || !x || nrhs <= 0 || ldb < s->N || ldx < s->N || nrhs > 4096 || !(rtol > 0.0) || restart <= 0 || maxit <= 0)
     return fail(s, AIFMM_ERR_ARG, "bad b/x/nrhs/ld/rtol/restart/maxit");
+  if (op && op != s &&
+      (op->N != s->N || op->d != s->d || op->L != s->L || op->leaf_off != s->leaf_off || op->K.kind != s->K.kind ||
+       op->K.scale != s->K.scale || op->K.shift != s->K.shift || op->device != s->device))
+    return fail(s, AIFMM_ERR_ARG, "operator and preconditioner systems differ (points, tree, kernel or device)");
   auto t0 = std::chrono::steady_clock::now();
   aifmm_status st = guarded(s, [&] {
     AIFMM_HIP(hipSetDevice(s->device));
-    aifmm::gmres_system(*s, b, nrhs, ldb, rtol, restart, maxit, x, ldx, iters, relres, is_device_ptr(b), is_device_ptr(x));
+    if (op && op != s && op->d_perm.download(op->stream) != s->d_perm.download(s->stream))
+      throw aifmm::Error{AIFMM_ERR_ARG, "operator and preconditioner systems order the points differently"};
+    aifmm::gmres_op_system(op, *s, b, nrhs, ldb, rtol, restart, maxit, x, ldx, iters, relres, is_device_ptr(b),
+                           is_device_ptr(x));
   });
   s->stats.gmres_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;
@@ -233,6 +279,30 @@ aifmm_status aifmm_get_stats(const aifmm_system* s, double* stats) {
   stats[AIFMM_STAT_GMRES_S] = s->stats.gmres_s;
   stats[AIFMM_STAT_TRSM_KERNEL_S] = s->stats.trsm_kernel_s;
   stats[AIFMM_STAT_TRSM_LAUNCHES] = s->stats.trsm_launches;
+  return AIFMM_OK;
+}
+
+aifmm_status aifmm_get_level_stats(const aifmm_system* s, int32_t level, double* out) {
+  if (!s || !out) return fail(nullptr, AIFMM_ERR_ARG, "NULL argument");
+  if (!s->factored) return fail(nullptr, AIFMM_ERR_STATE, "no factorization");
+  if (level < 2 || level > s->L || level >= (int)s->stats.lvl.size()) return fail(nullptr, AIFMM_ERR_ARG, "level out of range");
+  const aifmm::LevelStats& v = s->stats.lvl[level];
+  for (int q = 0; q < AIFMM_LSTAT_COUNT; ++q) out[q] = 0.0;
+  out[AIFMM_LSTAT_FACTOR_S] = v.factor_s;
+  out[AIFMM_LSTAT_SCHUR_FLOPS] = v.schur_flops;
+  out[AIFMM_LSTAT_SCHUR_BYTES] = v.schur_bytes;
+  out[AIFMM_LSTAT_TRSM_FLOPS] = v.trsm_flops;
+  out[AIFMM_LSTAT_TRSM_FLOPS_IMPL] = v.trsm_flops_impl;
+  out[AIFMM_LSTAT_LU_FLOPS] = v.lu_flops;
+  out[AIFMM_LSTAT_SCHUR_KERNEL_S] = v.schur_s;
+  out[AIFMM_LSTAT_TRSM_KERNEL_S] = v.trsm_s;
+  out[AIFMM_LSTAT_COMPRESS_KERNEL_S] = v.compress_s;
+  out[AIFMM_LSTAT_COMPRESS_FLOPS] = v.compress_flops;
+  out[AIFMM_LSTAT_COMPRESSIONS] = v.compressions;
+  out[AIFMM_LSTAT_ROUNDS] = v.rounds;
+  out[AIFMM_LSTAT_CRIT_STEPS] = v.crit_steps;
+  out[AIFMM_LSTAT_PIVOT_STEPS] = v.pivot_steps;
+  out[AIFMM_LSTAT_BOXES] = v.boxes;
   return AIFMM_OK;
 }
 

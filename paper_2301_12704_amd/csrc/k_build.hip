@@ -450,6 +450,10 @@ void build_system(aifmm_system& s, const double* pts_in, bool on_device) {
     hipLaunchKernelGGL(k_aca, dim3(nb), dim3(WG), 0, st, aa);
     launch_check("aca");
     lv.knn = lv.d_k.download(st);
+    lv.d_knn.upload(lv.knn, st);
+    lv.koff_nn.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) lv.koff_nn[b + 1] = lv.koff_nn[b] + lv.knn[b];
+    lv.d_koff_nn.upload(lv.koff_nn, st);
     std::vector<int> flag = s.d_flag.download(st);
     if (flag[3]) throw Error{AIFMM_ERR_CAPACITY, "ACA row set or rank above the workgroup capacity at level " + std::to_string(l)};
     acaws.release();

@@ -73,6 +73,133 @@ __global__ void __launch_bounds__(MV_T) k_matvec(KernelDesc K, const double* __r
     for (int c = 0; c < nc; ++c) y[i * nr + c0 + c] = acc[c];
 }
 
+// ------------------------------------------------------------------------------------------
+// NNCA-based H^2 product (Sec. 2.3, the operator table; the paper's GMRES operator in Sec. 4):
+// far field through the nested NNCA operators of every interaction-list pair, near field of
+// the leaf neighbours evaluated exactly.  u = v and a symmetric kernel give V = U, so the
+// upward pass applies U^T (P2M at the leaf, M2M above) and the downward pass U (L2L, L2P).
+// Vectors are row-major (row, column) in tree order: the points at the leaf, the NNCA ranks of
+// the boxes in box order above (the rows of a box's U are the points of the box at the leaf and
+// the stacked incoming pivots of its children above, so the rows of box b start at T_off[b]
+// in both the level's input and the children's rank vector).
+// ------------------------------------------------------------------------------------------
+
+// P2M / M2M: q[koff[b] + j] = sum_r U_b[r][j] src[T_off[b] + r]; one workgroup per box.
+__global__ void __launch_bounds__(WG) k_h2_up(const double* __restrict__ U, const int64_t* __restrict__ U_off,
+                                             const int* __restrict__ T_off, const int* __restrict__ k,
+                                             const int64_t* __restrict__ koff, const double* __restrict__ src,
+                                             double* __restrict__ q, int nr) {
+  const int b = blockIdx.x, kb = k[b];
+  if (kb == 0) return;
+  const int t0 = T_off[b], m = T_off[b + 1] - t0;
+  const double* Ub = U + U_off[b];
+  for (int idx = threadIdx.x; idx < kb * nr; idx += WG) {
+    const int j = idx / nr, c = idx - j * nr;
+    double acc = 0.0;
+    for (int r = 0; r < m; ++r) acc = fma(Ub[(size_t)r * kb + j], src[(size_t)(t0 + r) * nr + c], acc);
+    q[(size_t)(koff[b] + j) * nr + c] = acc;
+  }
+}
+
+// M2L: loc[koff[b] + j] (+)= sum over D in IL(b) of sum_i A_bD[j][i] q[koff[D] + i].
+__global__ void __launch_bounds__(WG) k_h2_m2l(const double* __restrict__ M, const int64_t* __restrict__ M_off,
+                                              const int* __restrict__ il_off, const int* __restrict__ il,
+                                              const int* __restrict__ k, const int64_t* __restrict__ koff,
+                                              const double* __restrict__ q, double* __restrict__ loc, int nr, int add) {
+  const int b = blockIdx.x, kb = k[b];
+  if (kb == 0) return;
+  for (int idx = threadIdx.x; idx < kb * nr; idx += WG) {
+    const int j = idx / nr, c = idx - j * nr;
+    double acc = 0.0;
+    for (int e = il_off[b]; e < il_off[b + 1]; ++e) {
+      const int D = il[e], kd = k[D];
+      const double* Me = M + M_off[e] + (size_t)j * kd;
+      const double* qd = q + (size_t)koff[D] * nr + c;
+      for (int i = 0; i < kd; ++i) acc = fma(Me[i], qd[(size_t)i * nr], acc);
+    }
+    double* o = loc + (size_t)(koff[b] + j) * nr + c;
+    *o = add ? *o + acc : acc;
+  }
+}
+
+// L2L / L2P: out[T_off[b] + r] = sum_j U_b[r][j] loc[koff[b] + j] for every row r of box b (the
+// children's locals above the leaf, the points of the leaf at the leaf); rows of a box of rank
+// 0 get 0.
+__global__ void __launch_bounds__(WG) k_h2_down(const double* __restrict__ U, const int64_t* __restrict__ U_off,
+                                               const int* __restrict__ T_off, const int* __restrict__ k,
+                                               const int64_t* __restrict__ koff, const double* __restrict__ loc,
+                                               double* __restrict__ out, int nr) {
+  const int b = blockIdx.x, kb = k[b];
+  const int t0 = T_off[b], m = T_off[b + 1] - t0;
+  const double* Ub = U + U_off[b];
+  for (int idx = threadIdx.x; idx < m * nr; idx += WG) {
+    const int r = idx / nr, c = idx - r * nr;
+    double acc = 0.0;
+    for (int j = 0; j < kb; ++j) acc = fma(Ub[(size_t)r * kb + j], loc[(size_t)(koff[b] + j) * nr + c], acc);
+    out[(size_t)(t0 + r) * nr + c] = acc;
+  }
+}
+
+// P2P: y[p] += sum over X in N(b) of sum over the points s of X of A_ps x[s], every entry
+// evaluated (one wave per leaf box; a lane per target point, the sources of a neighbour staged
+// through LDS in tiles, the right-hand sides in blocks of MV_R columns).
+constexpr int P2P_T = 64;
+template <int KIND, int D>
+__global__ void __launch_bounds__(P2P_T) k_h2_p2p(KernelDesc K, const double* __restrict__ pts,
+                                                 const int* __restrict__ box_off, const int* __restrict__ nbr_off,
+                                                 const int* __restrict__ nbr, const double* __restrict__ x,
+                                                 double* __restrict__ y, int nr) {
+  __shared__ double sp[P2P_T * D];
+  __shared__ double sx[P2P_T * MV_R];
+  const int b = blockIdx.x;
+  const int p0 = box_off[b], np = box_off[b + 1] - p0;
+  const double s2 = K.scale * K.scale;
+  for (int r0 = 0; r0 < np; r0 += P2P_T) {
+    const int i = p0 + r0 + (int)threadIdx.x;
+    const bool live = r0 + (int)threadIdx.x < np;
+    double pi[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) pi[t] = live ? pts[(size_t)i * D + t] : 0.0;
+    for (int c0 = 0; c0 < nr; c0 += MV_R) {
+      const int nc = min(MV_R, nr - c0);
+      double acc[MV_R];
+#pragma unroll
+      for (int c = 0; c < MV_R; ++c) acc[c] = 0.0;
+      for (int e = nbr_off[b]; e < nbr_off[b + 1]; ++e) {
+        const int X = nbr[e];
+        const int q0 = box_off[X], nq = box_off[X + 1] - q0;
+        for (int s0 = 0; s0 < nq; s0 += P2P_T) {
+          const int cnt = min(P2P_T, nq - s0);
+          __syncthreads();
+          for (int u = threadIdx.x; u < cnt * D; u += P2P_T) sp[u] = pts[(size_t)(q0 + s0) * D + u];
+          for (int u = threadIdx.x; u < cnt * MV_R; u += P2P_T) {
+            const int jj = u / MV_R, c = u - jj * MV_R;
+            sx[u] = c < nc ? x[(size_t)(q0 + s0 + jj) * nr + c0 + c] : 0.0;
+          }
+          __syncthreads();
+          if (live) {
+            const int dj = i - (q0 + s0);  // the diagonal when the target is in this tile
+            for (int jj = 0; jj < cnt; ++jj) {
+              double r2 = 0.0;
+#pragma unroll
+              for (int t = 0; t < D; ++t) {
+                const double z = pi[t] - sp[jj * D + t];
+                r2 = fma(z, z, r2);
+              }
+              double v = KIND == 0 ? dexp(-sqrt(r2) / K.scale) : rsqrt_nr(r2 + s2);
+              if (jj == dj) v += K.shift;
+#pragma unroll
+              for (int c = 0; c < MV_R; ++c) acc[c] = fma(v, sx[jj * MV_R + c], acc[c]);
+            }
+          }
+        }
+      }
+      if (live)
+        for (int c = 0; c < nc; ++c) y[(size_t)i * nr + c0 + c] += acc[c];
+    }
+  }
+}
+
 // column dot products: out[c] = sum_i a[i, c] b[i, c]  (row-major N x nr), partial sums per block
 __global__ void k_coldot(const double* a, const double* b, int64_t N, int nr, double* part) {
   __shared__ double sh[WG / WAVE + 1];
@@ -121,6 +248,47 @@ void matvec_tree(aifmm_system& s, const double* x, int nr, double* y) {
   AIFMM_HIP(hipGetLastError());
 }
 
+// y = A~ x with the H^2 operator of s (its matvec-tolerance NNCA when it has one, else its own)
+// for tree-ordered row-major vectors.  Kernels only on s's stream; the q / l work vectors are
+// the operator's (kept across calls).
+void h2_matvec_tree(aifmm_system& s, const double* x, int nr, double* y, hipStream_t st) {
+  aifmm_system& S = s.op ? *s.op : s;
+  const int L = S.L;
+  H2Cache& hc = S.hc;
+  if (nr > hc.nr_cap) {
+    hc.q.clear();
+    hc.loc.clear();
+    hc.q.resize(L + 1);
+    hc.loc.resize(L + 1);
+    for (int l = 2; l <= L; ++l) {
+      int64_t K = std::max<int64_t>(1, S.lev[l].koff_nn.back());
+      hc.q[l].alloc((size_t)K * nr);
+      hc.loc[l].alloc((size_t)K * nr);
+    }
+    hc.nr_cap = nr;
+  }
+  for (int l = L; l >= 2; --l) {  // upward pass: P2M at the leaf, M2M above
+    LevelDev& lv = S.lev[l];
+    const double* src = l == L ? x : hc.q[l + 1].p;
+    hipLaunchKernelGGL(k_h2_up, dim3(lv.nb), dim3(WG), 0, st, lv.d_Unn.p, lv.d_Unn_off.p, lv.d_T_off.p, lv.d_knn.p,
+                       lv.d_koff_nn.p, src, hc.q[l].p, nr);
+  }
+  for (int l = 2; l <= L; ++l) {  // M2L, then L2L into the children (downward pass)
+    LevelDev& lv = S.lev[l];
+    // level 2 starts the locals; below it they already hold the parent's L2L contribution
+    hipLaunchKernelGGL(k_h2_m2l, dim3(lv.nb), dim3(WG), 0, st, lv.d_m2l_nn.p, lv.d_m2l_nn_off.p, lv.d_il_off.p,
+                       lv.d_il.p, lv.d_knn.p, lv.d_koff_nn.p, hc.q[l].p, hc.loc[l].p, nr, l > 2 ? 1 : 0);
+    double* out = l < L ? hc.loc[l + 1].p : y;  // L2L writes the children's locals, L2P writes y
+    hipLaunchKernelGGL(k_h2_down, dim3(lv.nb), dim3(WG), 0, st, lv.d_Unn.p, lv.d_Unn_off.p, lv.d_T_off.p, lv.d_knn.p,
+                       lv.d_koff_nn.p, hc.loc[l].p, out, nr);
+  }
+  LevelDev& lf = S.lev[L];  // P2P near field of the leaf neighbours
+  auto kern = S.K.kind == 0 ? (S.d == 2 ? k_h2_p2p<0, 2> : k_h2_p2p<0, 3>) : (S.d == 2 ? k_h2_p2p<1, 2> : k_h2_p2p<1, 3>);
+  hipLaunchKernelGGL(kern, dim3(lf.nb), dim3(P2P_T), 0, st, S.K, S.d_pts.p, lf.d_T_off.p, lf.d_nbr_off.p, lf.d_nbr.p, x,
+                     y, nr);
+  AIFMM_HIP(hipGetLastError());
+}
+
 static std::vector<double> coldots(aifmm_system& s, const double* a, const double* b, int nr, DBuf<double>& part) {
   int nblk = 256;
   if (part.n < (size_t)nblk * nr) part.alloc((size_t)nblk * nr);
@@ -160,11 +328,42 @@ void matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ldx, 
   AIFMM_HIP(hipStreamSynchronize(st));
 }
 
+void h2_matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy, bool x_dev,
+                      bool y_dev) {
+  hipStream_t st = s.stream;
+  int nr = (int)nrhs;
+  int64_t N = s.N;
+  DBuf<double> xin, xt, yt, yout;
+  const double* xs = x;
+  int64_t ldxs = ldx;
+  if (!x_dev) {
+    xin.alloc((size_t)N * nr);
+    h2d_cols(xin.p, x, ldx, N, nr, st);
+    xs = xin.p;
+    ldxs = N;
+  }
+  xt.alloc((size_t)N * nr);
+  yt.alloc((size_t)N * nr);
+  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xs, ldxs, s.d_perm.p, N, nr, xt.p);
+  h2_matvec_tree(s, xt.p, nr, yt.p, st);
+  if (y_dev) {
+    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, yt.p, s.d_perm.p, N, nr, y, ldy);
+  } else {
+    yout.alloc((size_t)N * nr);
+    hipLaunchKernelGGL(k_perm_rows_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, yt.p, s.d_perm.p, N, nr, yout.p, N);
+    d2h_cols(y, ldy, yout.p, N, nr, st);
+  }
+  AIFMM_HIP(hipStreamSynchronize(st));
+}
+
 // Right-preconditioned flexible GMRES(m) with modified Gram-Schmidt, all right-hand sides
 // advanced together (each with its own Hessenberg matrix); the preconditioner is the AIFMM
-// solve in tree order.  Stops per column on the true relative residual <= rtol.
-void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int restart, int maxit,
-                  double* x, int64_t ldx, int32_t* iters, double* relres, bool b_dev, bool x_dev) {
+// solve of s in tree order, the operator the H^2 product of op (the exact product of s when op
+// is null; op's tree is s's tree: same points and options).  Stops per column on the relative
+// residual of the operator <= rtol, recomputed from b - A x at every restart and at the end.
+void gmres_op_system(aifmm_system* op, aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol,
+                     int restart, int maxit, double* x, int64_t ldx, int32_t* iters, double* relres, bool b_dev,
+                     bool x_dev) {
   hipStream_t st = s.stream;
   int nr = (int)nrhs, m = std::max(1, restart);
   int64_t N = s.N;
@@ -214,13 +413,17 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
     set_alpha(a);
     hipLaunchKernelGGL(k_scale_cols, dim3(cdiv(vec, WG)), dim3(WG), 0, st, N, nr, dalpha.p, xx, yy);
   };
+  auto apply = [&](const double* xx, double* yy) {
+    if (op) h2_matvec_tree(*op, xx, nr, yy, st);
+    else matvec_tree(s, xx, nr, yy);
+  };
   int total = 0;
   bool x_zero = true;  // x is still the zero start, so A x = 0 and r = b exactly
   while (true) {
     // true residual r = b - A x
     AIFMM_HIP(hipMemcpyAsync(r.p, bt.p, sizeof(double) * vec, hipMemcpyDeviceToDevice, st));
     if (!x_zero) {
-      matvec_tree(s, xt.p, nr, w.p);
+      apply(xt.p, w.p);
       axpy(std::vector<double>(nr, -1.0), w.p, r.p);
     }
     std::vector<double> beta = coldots(s, r.p, r.p, nr, part);
@@ -242,7 +445,7 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
     int j = 0;
     for (; j < m && total < maxit; ++j, ++total) {
       solve_tree(s, V[j].p, nr, Z[j].p);  // Z_j = M^{-1} V_j
-      matvec_tree(s, Z[j].p, nr, w.p);
+      apply(Z[j].p, w.p);
       for (int i = 0; i <= j; ++i) {
         std::vector<double> h = coldots(s, V[i].p, w.p, nr, part);
         for (int c = 0; c < nr; ++c) H[(size_t)i * m + j][c] = h[c];
@@ -313,6 +516,13 @@ void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
   bool ok = true;
   for (int c = 0; c < nr; ++c) ok = ok && rel[c] <= rtol;
   if (!ok) throw Error{AIFMM_ERR_NOCONV, "GMRES did not reach the requested residual within maxit"};
+}
+
+// FGMRES with the system's own operator: its H^2 product when it was built with a matvec
+// tolerance, else the exact product.
+void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int restart, int maxit,
+                  double* x, int64_t ldx, int32_t* iters, double* relres, bool b_dev, bool x_dev) {
+  gmres_op_system(s.op ? &s : nullptr, s, b, nrhs, ldb, rtol, restart, maxit, x, ldx, iters, relres, b_dev, x_dev);
 }
 
 }  // namespace aifmm

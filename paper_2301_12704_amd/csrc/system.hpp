@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <cstdio>
 #include <string>
@@ -170,6 +171,9 @@ struct LevelDev {
   DBuf<double> d_m2l_nn;       // A_BD, k_B x k_D, one per IL entry
   std::vector<int64_t> m2l_nn_off;
   DBuf<int64_t> d_m2l_nn_off;
+  DBuf<int> d_knn;             // NNCA ranks on the device (d_k changes during the factorization)
+  std::vector<int64_t> koff_nn;  // prefix of the NNCA ranks (rows of the H^2 product's q and l)
+  DBuf<int64_t> d_koff_nn;
   // live block store (allocated when the level is eliminated)
   DBuf<double> slab;
   DBuf<int64_t> d_near_slot, d_p2_slot, d_il_slot;   // per CSR entry
@@ -253,6 +257,13 @@ struct SolveCache {
   DBuf<double> G;
 };
 
+// Work vectors of the H^2 product (multipoles q and locals l of every level), grown to the
+// largest right-hand-side count seen.
+struct H2Cache {
+  int nr_cap = 0;
+  std::vector<DBuf<double>> q, loc;
+};
+
 // FGMRES workspace kept across calls (grown to the largest right-hand-side count seen), so a
 // served system allocates nothing per request once warm.
 struct GmresCache {
@@ -262,7 +273,23 @@ struct GmresCache {
   std::vector<DBuf<double>> V, Z;
 };
 
+// Figures of one level's factorization (device times are HIP-event times of the launches).
+struct LevelStats {
+  double factor_s = 0;                    // wall time of the level
+  double schur_flops = 0, schur_bytes = 0;  // Schur update: 2 R n C flops, 8 (R n + n C + 2 R C) bytes per box
+  double trsm_flops = 0;                  // pivot-block solve, algorithmic 2 m^2 C per box
+  double trsm_flops_impl = 0;             // as executed, 2 m^2 (C + n) (W also holds Piv^{-1}[:, x_b])
+  double lu_flops = 0;                    // (2/3) m^3 per box
+  double schur_s = 0, trsm_s = 0, compress_s = 0;
+  double compress_flops = 0;              // pivoted QRs, Q formations and coefficient products as executed
+  double compressions = 0, rounds = 0;
+  double crit_steps = 0;                  // sum over rounds of the longest pivot-step chain of the round
+  double pivot_steps = 0;                 // all pivot steps of the level's pivoted QRs
+  double boxes = 0;
+};
+
 struct Stats {
+  std::vector<LevelStats> lvl;            // by level (2..L used)
   double build_s = 0, factor_s = 0, solve_s = 0;
   double schur_flops = 0, schur_bytes = 0, trsm_flops = 0, lu_flops = 0;
   double schur_kernel_s = 0, compress_kernel_s = 0;   // event-timed device time of the last factor
@@ -302,6 +329,11 @@ struct aifmm_system {
   aifmm::GmresCache gc;           // FGMRES vectors
   std::vector<aifmm::TraceRec> trace;
   size_t device_bytes = 0;
+  // the H^2 operator: NNCA of the same points at the matvec tolerance (absent: this system's own
+  // NNCA at tol is the operator)
+  std::unique_ptr<aifmm_system> op;
+  double matvec_tol = 0.0;
+  aifmm::H2Cache hc;
 };
 
 namespace aifmm {
@@ -316,6 +348,12 @@ void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x);
 void prepare_solve(aifmm_system& s);
 // k_gmres.hip
 void matvec_tree(aifmm_system& s, const double* x, int nr, double* y);
+void h2_matvec_tree(aifmm_system& s, const double* x, int nr, double* y, hipStream_t st);
+void h2_matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy, bool x_dev,
+                      bool y_dev);
+void gmres_op_system(aifmm_system* op, aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol,
+                     int restart, int maxit, double* x, int64_t ldx, int32_t* iters, double* relres, bool b_dev,
+                     bool x_dev);
 void matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy, bool x_dev,
                    bool y_dev);
 void gmres_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol, int restart, int maxit,

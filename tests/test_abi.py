@@ -68,3 +68,21 @@ def test_server_argument_errors_without_device(lib):
     assert L.aifmm_server_wait(None, 1, None, 1, None, None, None, None) == 1
     assert L.aifmm_server_stats(None, None, None, None) == 1
     L.aifmm_server_destroy(None)
+
+
+def test_binding_argument_counts_match_header():
+    """Every function the binding declares takes as many arguments as include/aifmm.h says."""
+    import paper_2301_12704_amd as A
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    decl = {}
+    for m in re.finditer(r"\b(aifmm_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", text):
+        args = m.group(2).strip()
+        decl[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    L = A.lib()
+    checked = 0
+    for name, n in decl.items():
+        at = getattr(L, name).argtypes
+        if at is not None:
+            assert len(at) == n, f"{name}: binding has {len(at)} argument types, header {n}"
+            checked += 1
+    assert checked >= 20

@@ -56,7 +56,7 @@ def test_leading_dimension_above_n():
     xg = _padded(np.zeros((n, nr)), ld, extra)
     it = np.zeros(nr, np.int32)
     rr = np.zeros(nr)
-    st = L.aifmm_gmres(g._h, b.ctypes.data_as(vp), nr, ld, 1e-10, 30, 100, xg.ctypes.data_as(vp), ld,
+    st = L.aifmm_gmres(None, g._h, b.ctypes.data_as(vp), nr, ld, 1e-10, 30, 100, xg.ctypes.data_as(vp), ld,
                        it.ctypes.data_as(vp), rr.ctypes.data_as(vp))
     assert st == 0
     xr, _, _ = g.gmres(c["b"], rtol=1e-10)

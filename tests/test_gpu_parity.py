@@ -26,7 +26,22 @@ CASES = [
     ("ragged_2000", 2000, 2, 3, ("exp", 1.0, 0.1), 1e-8, 2, 22),
     ("exp_half_L4", 8192, 2, 4, ("exp", 0.5, 0.05), 1e-8, 1, 23),
     ("3d_L2", 3000, 3, 2, ("invmq", 3000 ** (-1.0 / 3.0), 1.0), 1e-6, 2, 24),
+    # 3D with a non-leaf level: the level-2 boxes stack the children's ranks (8 children each)
+    ("3d_L3", 2048, 3, 3, ("invmq", 2048 ** (-1.0 / 3.0), 1.0), 1e-5, 2, 26),
 ]
+
+# Switches of the library that change which kernel path runs, never an operation's order:
+# compression columns in the workspace instead of LDS, with teams of up to 48 members (the
+# shapes the large workloads run) or of at most 4, lone workgroups only, and pivot-block LU
+# panels factored in device memory instead of LDS (the path of pivot blocks above ~1050 rows).
+SWITCHES = [
+    ("workspace_columns_large_teams", {"AIFMM_NO_LDS_COLUMNS": "1", "AIFMM_TEAM_ELEMS": "1024"}),
+    ("workspace_columns_small_teams", {"AIFMM_NO_LDS_COLUMNS": "1", "AIFMM_TEAM_ELEMS": "1024",
+                                       "AIFMM_TEAM_MAX": "2"}),
+    ("no_teams", {"AIFMM_NO_TEAMS": "1"}),
+    ("lu_panels_in_memory", {"AIFMM_NO_LDS_PANELS": "1"}),
+]
+SWITCH_CASES = [c for c in CASES if c[0] in ("invmq_L3", "exp_half_L4", "3d_L3")]
 
 
 def _run(n, d, depth, kernel, tol, nrhs, seed, pts=None):
@@ -84,6 +99,38 @@ def test_parity(case):
     g, o, pts, b = _run(n, d, depth, kernel, tol, nrhs, seed)
     err, res = _compare(g, o, pts, b, kernel)
     print(f"solution error vs oracle {err:.3e}, residual {res:.3e}")
+
+
+@pytest.mark.parametrize("case", SWITCH_CASES, ids=[c[0] for c in SWITCH_CASES])
+@pytest.mark.parametrize("switch", SWITCHES, ids=[w[0] for w in SWITCHES])
+def test_parity_kernel_paths(case, switch, monkeypatch):
+    """The same bar on the kernel paths the switches select (bit-exact ranks and pivots)."""
+    for k, v in switch[1].items():
+        monkeypatch.setenv(k, v)
+    print(f"switch {switch[0]}", flush=True)
+    _, n, d, depth, kernel, tol, nrhs, seed = case
+    g, o, pts, b = _run(n, d, depth, kernel, tol, nrhs, seed)
+    err, res = _compare(g, o, pts, b, kernel)
+    print(f"solution error vs oracle {err:.3e}, residual {res:.3e}")
+
+
+def test_team_abort_reports_device_error(monkeypatch):
+    """A team barrier that gives up raises the abort flag; the kernels then stop using data
+    exchanged through the team and run to their end, and the factorization returns
+    AIFMM_ERR_DEVICE.  Forced from the host: the flag is raised before the level's first
+    launch, so every team barrier falls through at once (no wait is timed out)."""
+    monkeypatch.setenv("AIFMM_DEBUG_ABORT", "1")
+    c = I.small_case(8192, d=2, depth=4, tol=1e-8, kernel=("exp", 0.5, 0.05), nrhs=1, seed=37)
+    print("case abort n=8192 depth 4", flush=True)
+    g = A.System(c["pts"], c["kernel"], c["tol"], 64, 4)
+    with pytest.raises(A.AifmmError) as e:
+        g.factor()
+    assert e.value.status == 5 and "barrier" in str(e.value)
+    g.close()
+    monkeypatch.delenv("AIFMM_DEBUG_ABORT")
+    g = A.System(c["pts"], c["kernel"], c["tol"], 64, 4)
+    g.factor()  # the next factorization on the device is unaffected
+    g.close()
 
 
 def test_empty_and_sparse_boxes():
