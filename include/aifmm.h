@@ -100,6 +100,19 @@ aifmm_status aifmm_factor(aifmm_system* s);
 /* x = (factored A)^{-1} b for nrhs right-hand sides (Sec. 3.4). */
 aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): aifmm_solve with b and x in device memory and every
+ * work buffer of the solve carved from one fixed scratch array per GPU (64 MiB, a static device
+ * array that the GPU holds until the process ends).  No allocation and no graph: only kernel
+ * launches and a stream synchronization.  Same layouts and result as aifmm_solve.  Errors:
+ * AIFMM_ERR_ARG for a host pointer or bad sizes, AIFMM_ERR_STATE before aifmm_factor,
+ * AIFMM_ERR_CAPACITY when N, the tree and nrhs need more scratch than the maximum (about
+ * 8 bytes x nrhs x (N + the ranks' and pivot blocks' rows); the message states both sizes).
+ * Every call on a GPU shares that GPU's scratch array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other systems, other threads or streams) race and must be
+ * serialized by the caller. */
+aifmm_status aifmm_solve_noalloc(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx);
+
 /* y = A x with every kernel entry evaluated in FP64 (exact product, O(N^2) work; used for
  * residuals, and the operator of aifmm_gmres when op is NULL).  Same layouts as aifmm_solve. */
 aifmm_status aifmm_matvec(aifmm_system* s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy);

@@ -65,6 +65,8 @@ def lib():
         L.aifmm_get_level_stats.restype = ctypes.c_int
         L.aifmm_get_trace.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.aifmm_get_trace.restype = ctypes.c_int
+        L.aifmm_solve_noalloc.argtypes = [vp, vp, i64, i64, vp, i64]
+        L.aifmm_solve_noalloc.restype = ctypes.c_int
         L.aifmm_matvec.argtypes = [vp, vp, i64, i64, vp, i64]
         L.aifmm_matvec.restype = ctypes.c_int
         L.aifmm_matvec_h2.argtypes = [vp, vp, i64, i64, vp, i64]

@@ -194,6 +194,21 @@ aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t
   });
 }
 
+aifmm_status aifmm_solve_noalloc(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x,
+                                 int64_t ldx) {
+  if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
+  std::lock_guard<std::mutex> lk(s->use);
+  if (!s->factored) return fail(s, AIFMM_ERR_STATE, "solve before factor");
+  if (!b || !x || nrhs <= 0 || ldb < s->N || ldx < s->N) return fail(s, AIFMM_ERR_ARG, "bad b/x/nrhs/ld");
+  if (nrhs > 4096) return fail(s, AIFMM_ERR_ARG, "nrhs too large");
+  return guarded(s, [&] {
+    AIFMM_HIP(hipSetDevice(s->device));
+    if (!is_device_ptr(b) || !is_device_ptr(x))
+      throw aifmm::Error{AIFMM_ERR_ARG, "the allocation-free solve takes device pointers only"};
+    aifmm::solve_system_noalloc(*s, b, nrhs, ldb, x, ldx);
+  });
+}
+
 aifmm_status aifmm_matvec(aifmm_system* s, const double* x, int64_t nrhs, int64_t ldx, double* y, int64_t ldy) {
   if (!s) return fail(nullptr, AIFMM_ERR_ARG, "system is NULL");
   std::lock_guard<std::mutex> lk(s->use);

@@ -537,4 +537,86 @@ void prepare_solve(aifmm_system& s) {
   AIFMM_HIP(hipStreamSynchronize(s.stream));
 }
 
+// ---- allocation-free solve --------------------------------------------------------------
+// Work buffers of aifmm_solve_noalloc: one static array per device (the loader places a copy
+// on every GPU the library runs on).  In host code the array's name is only a stand-in: its
+// device address is looked up once per device with hipGetSymbolAddress and used from then on.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_ptr;  // by device ordinal, nullptr until looked up
+
+// The scratch array's device address on the current device (looked up on its first use there).
+static double* scratch_on_current_device() {
+  int dev = 0;
+  AIFMM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error{AIFMM_ERR_DEVICE, std::string("scratch address lookup failed: ") + hipGetErrorString(e)};
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+size_t noalloc_max_bytes() { return kNoAllocBytes; }
+
+// Bytes of scratch a solve of nr columns needs: the tree-ordered solution (N x nr) and the work
+// buffers, each region rounded up to 256 bytes.
+size_t noalloc_need_bytes(aifmm_system& s, int nr) {
+  std::vector<int64_t> rsz, wsz;
+  int64_t gsz = 0;
+  solve_buf_sizes(s, nr, rsz, wsz, gsz);
+  auto up = [](int64_t n) { return (size_t)((n + 31) & ~int64_t(31)); };
+  size_t tot = up(s.N * nr) + up(gsz);
+  for (int l = 2; l <= s.L; ++l) tot += 2 * up(rsz[l - 1]) + up(wsz[l]);
+  return tot * sizeof(double);
+}
+
+// aifmm_solve on device buffers with every work buffer carved from the scratch array: kernels
+// only (no allocation, no graph); b and x are device memory.
+void solve_system_noalloc(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = s.stream;
+  int nr = (int)nrhs;
+  int64_t N = s.N;
+  if (!s.sc.built) throw Error{AIFMM_ERR_STATE, "solve plan missing (factor first)"};
+  size_t need = noalloc_need_bytes(s, nr);
+  if (need > kNoAllocBytes)
+    throw Error{AIFMM_ERR_CAPACITY, "allocation-free solve needs " + std::to_string(need) + " bytes of scratch for " +
+                                        std::to_string(nr) + " columns; the maximum is " +
+                                        std::to_string(kNoAllocBytes)};
+  double* base = scratch_on_current_device();
+  std::vector<int64_t> rsz, wsz;
+  int64_t gsz = 0;
+  solve_buf_sizes(s, nr, rsz, wsz, gsz);
+  size_t off = 0;
+  auto take = [&](int64_t n) {
+    double* p = base + off;
+    off += (size_t)((n + 31) & ~int64_t(31));
+    return p;
+  };
+  double* xt = take(N * nr);
+  SolveBufs B;
+  B.R.assign(s.L + 1, nullptr);
+  B.X.assign(s.L + 1, nullptr);
+  B.W.assign(s.L + 1, nullptr);
+  for (int l = s.L; l >= 2; --l) {
+    B.R[l - 1] = take(rsz[l - 1]);
+    B.X[l - 1] = take(rsz[l - 1]);
+    B.W[l] = take(wsz[l]);
+  }
+  B.G = take(gsz);
+  hipLaunchKernelGGL(k_perm_in, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, b, ldb, s.d_perm.p, N, nr, xt);
+  solve_tree_launch(s, xt, nr, xt, B);
+  hipLaunchKernelGGL(k_perm_out, dim3(cdiv(N * nr, WG)), dim3(WG), 0, st, xt, s.d_perm.p, N, nr, x, ldx);
+  AIFMM_HIP(hipStreamSynchronize(st));
+  launch_check("allocation-free solve");
+  s.stats.solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 }  // namespace aifmm

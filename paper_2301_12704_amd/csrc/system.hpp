@@ -346,6 +346,9 @@ void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, d
                   bool b_dev, bool x_dev);
 void solve_tree(aifmm_system& s, const double* rhs, int nr, double* x);
 void prepare_solve(aifmm_system& s);
+size_t noalloc_max_bytes();
+size_t noalloc_need_bytes(aifmm_system& s, int nr);
+void solve_system_noalloc(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx);
 // k_gmres.hip
 void matvec_tree(aifmm_system& s, const double* x, int nr, double* y);
 void h2_matvec_tree(aifmm_system& s, const double* x, int nr, double* y, hipStream_t st);
