@@ -129,9 +129,14 @@ aifmm_status aifmm_matvec_h2(aifmm_system* s, const double* x, int64_t nrhs, int
  * product of op (aifmm_matvec_h2 of op: its NNCA at its matvec tolerance eps_G) or, when op is
  * NULL, prec's exact product (aifmm_matvec).  op may be prec itself (a system built with
  * matvec_tol and factored) or another system built from the same points, kernel and options
- * (AIFMM_ERR_ARG otherwise).  The stopping residual is the operator's, recomputed from b - A x at
- * every restart and at the end.  x is an output (the iteration starts from 0).  iters[nrhs] and
- * relres[nrhs] (may be NULL) receive per-column iteration counts and final relative residuals.
+ * (AIFMM_ERR_ARG otherwise).  The iteration stops on the operator's residual, recomputed from
+ * b - A x at every restart.  With an H^2 operator the result is then checked with the exact
+ * product, whose residual the H^2 product's error (about eps_G |A|) hides: while a column's exact
+ * residual is above rtol, the exact residual is solved for with the same FGMRES and added (at
+ * most three times), so the returned residuals are exact ones.  x is an output (the iteration
+ * starts from 0).  iters[nrhs] and relres[nrhs] (may be NULL) receive per-column iteration counts
+ * (all FGMRES steps) and final relative residuals under the exact product (op NULL: the
+ * operator is the exact product).
  * AIFMM_ERR_NOCONV if some column is above rtol after maxit iterations (x then holds the last
  * iterate).  Calls on the two systems are serialized with their other calls. */
 aifmm_status aifmm_gmres(aifmm_system* op, aifmm_system* prec, const double* b, int64_t nrhs, int64_t ldb, double rtol,

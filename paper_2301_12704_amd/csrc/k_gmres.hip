@@ -23,54 +23,67 @@ __device__ inline double rsqrt_nr(double x) {
   return y;
 }
 
+typedef double mv_dbl4 __attribute__((ext_vector_type(4)));
+__device__ inline mv_dbl4 mv_mfma(double a, double b, mv_dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // y[i, c] = sum_j A_ij x[j, c] for the points in tree order; x, y row-major (N x nr).
-// One target per thread; sources staged through LDS in tiles; every entry evaluated, the
-// sources of a target in ascending order.  KIND and the dimension D are template arguments so
-// the inner loop holds no branch but the diagonal's.
+// Every entry is evaluated once: a wave owns 16 targets and a block of MV_R right-hand sides;
+// lane (fr, fk) evaluates the entry of target fr and source 4 s + fk as the A operand of one FP64
+// MFMA 16x16x4 per step s, the staged right-hand sides of the four sources are the B operand.
+// The MFMA adds its four products one fused multiply-add at a time in ascending k, so every
+// output is the ascending fused multiply-add chain over the sources, as a sequential loop.
+// KIND and the dimension D are template arguments.
 constexpr int MV_T = 256, MV_S = 256, MV_R = 16;
 template <int KIND, int D>
 __global__ void __launch_bounds__(MV_T) k_matvec(KernelDesc K, const double* __restrict__ pts, int64_t N,
                                                  const double* __restrict__ x, int nr, double* __restrict__ y) {
   __shared__ double sp[MV_S * D];
   __shared__ double sx[MV_S * MV_R];
-  int64_t i = (int64_t)blockIdx.x * MV_T + threadIdx.x;
-  int c0 = blockIdx.y * MV_R;
-  int nc = std::min(MV_R, nr - c0);
-  double acc[MV_R];
-#pragma unroll
-  for (int c = 0; c < MV_R; ++c) acc[c] = 0.0;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, fr = lane % 16, fk = lane / 16;
+  const int64_t tile0 = (int64_t)blockIdx.x * (MV_T / WAVE * 16) + wv * 16;
+  const int64_t i = tile0 + fr;  // the target of this lane's A rows
+  const int c0 = blockIdx.y * MV_R;
+  const int nc = min(MV_R, nr - c0);
   double pi[D];
 #pragma unroll
   for (int t = 0; t < D; ++t) pi[t] = i < N ? pts[i * D + t] : 0.0;
   const double s2 = K.scale * K.scale;
+  mv_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int64_t j0 = 0; j0 < N; j0 += MV_S) {
-    int cnt = (int)std::min<int64_t>(MV_S, N - j0);
+    const int cnt = (int)std::min<int64_t>(MV_S, N - j0);
     __syncthreads();
     for (int q = threadIdx.x; q < cnt * D; q += MV_T) sp[q] = pts[j0 * D + q];
-    for (int q = threadIdx.x; q < cnt * MV_R; q += MV_T) {
-      int jj = q / MV_R, c = q % MV_R;
-      sx[q] = c < nc ? x[(j0 + jj) * nr + c0 + c] : 0.0;
+    for (int q = threadIdx.x; q < MV_S * MV_R; q += MV_T) {  // rows past cnt are zero
+      const int jj = q / MV_R, c = q % MV_R;
+      sx[q] = (jj < cnt && c < nc) ? x[(j0 + jj) * nr + c0 + c] : 0.0;
     }
     __syncthreads();
-    if (i < N) {
-      const int dj = (i >= j0 && i < j0 + cnt) ? (int)(i - j0) : -1;  // the diagonal in this tile
+    const int steps = (cnt + 3) / 4;
 #pragma unroll 4
-      for (int jj = 0; jj < cnt; ++jj) {
+    for (int st = 0; st < steps; ++st) {
+      const int jj = 4 * st + fk;
+      double v = 0.0;
+      if (jj < cnt && i < N) {
         double r2 = 0.0;
 #pragma unroll
         for (int t = 0; t < D; ++t) {
-          double z = pi[t] - sp[jj * D + t];
+          const double z = pi[t] - sp[jj * D + t];
           r2 = fma(z, z, r2);
         }
-        double v = KIND == 0 ? dexp(-sqrt(r2) / K.scale) : rsqrt_nr(r2 + s2);
-        if (jj == dj) v += K.shift;
-#pragma unroll
-        for (int c = 0; c < MV_R; ++c) acc[c] = fma(v, sx[jj * MV_R + c], acc[c]);
+        v = KIND == 0 ? dexp(-sqrt(r2) / K.scale) : rsqrt_nr(r2 + s2);
+        if (j0 + jj == i) v += K.shift;
       }
+      acc = mv_mfma(v, sx[jj * MV_R + fr], acc);
     }
   }
-  if (i < N)
-    for (int c = 0; c < nc; ++c) y[i * nr + c0 + c] = acc[c];
+  // output (lane, q): target tile0 + fk + 4 q, column c0 + fr
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t t = tile0 + fk + 4 * q;
+    if (t < N && fr < nc) y[t * nr + c0 + fr] = acc[q];
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -84,7 +97,11 @@ __global__ void __launch_bounds__(MV_T) k_matvec(KernelDesc K, const double* __r
 // in both the level's input and the children's rank vector).
 // ------------------------------------------------------------------------------------------
 
-// P2M / M2M: q[koff[b] + j] = sum_r U_b[r][j] src[T_off[b] + r]; one workgroup per box.
+// The per-box products below are 16 x 16 output tiles on FP64 MFMA 16x16x4 (16 rows of the
+// result, 16 right-hand sides), one wave per tile, the tiles of a box spread over the waves of
+// blockIdx.y; K runs in steps of 4 (terms past K are exact zeros).
+
+// P2M / M2M: q[koff[b] + j] = sum_r U_b[r][j] src[T_off[b] + r].
 __global__ void __launch_bounds__(WG) k_h2_up(const double* __restrict__ U, const int64_t* __restrict__ U_off,
                                              const int* __restrict__ T_off, const int* __restrict__ k,
                                              const int64_t* __restrict__ koff, const double* __restrict__ src,
@@ -93,11 +110,24 @@ __global__ void __launch_bounds__(WG) k_h2_up(const double* __restrict__ U, cons
   if (kb == 0) return;
   const int t0 = T_off[b], m = T_off[b + 1] - t0;
   const double* Ub = U + U_off[b];
-  for (int idx = threadIdx.x; idx < kb * nr; idx += WG) {
-    const int j = idx / nr, c = idx - j * nr;
-    double acc = 0.0;
-    for (int r = 0; r < m; ++r) acc = fma(Ub[(size_t)r * kb + j], src[(size_t)(t0 + r) * nr + c], acc);
-    q[(size_t)(koff[b] + j) * nr + c] = acc;
+  const int lane = threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
+  const int tr = (kb + 15) / 16, tc = (nr + 15) / 16;
+  for (int t = blockIdx.y * (WG / WAVE) + threadIdx.x / WAVE; t < tr * tc; t += gridDim.y * (WG / WAVE)) {
+    const int R0 = (t / tc) * 16, C0 = (t % tc) * 16;
+    const bool rok = R0 + fr < kb, cok = C0 + fr < nr;
+    mv_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      const int r = k0 + fk;
+      const double a = (rok && r < m) ? Ub[(size_t)r * kb + R0 + fr] : 0.0;
+      const double bb = (cok && r < m) ? src[(size_t)(t0 + r) * nr + C0 + fr] : 0.0;
+      acc = mv_mfma(a, bb, acc);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = R0 + fk + 4 * u, c = C0 + fr;
+      if (j < kb && c < nr) q[(size_t)(koff[b] + j) * nr + c] = acc[u];
+    }
   }
 }
 
@@ -108,17 +138,32 @@ __global__ void __launch_bounds__(WG) k_h2_m2l(const double* __restrict__ M, con
                                               const double* __restrict__ q, double* __restrict__ loc, int nr, int add) {
   const int b = blockIdx.x, kb = k[b];
   if (kb == 0) return;
-  for (int idx = threadIdx.x; idx < kb * nr; idx += WG) {
-    const int j = idx / nr, c = idx - j * nr;
-    double acc = 0.0;
+  const int lane = threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
+  const int tr = (kb + 15) / 16, tc = (nr + 15) / 16;
+  for (int t = blockIdx.y * (WG / WAVE) + threadIdx.x / WAVE; t < tr * tc; t += gridDim.y * (WG / WAVE)) {
+    const int R0 = (t / tc) * 16, C0 = (t % tc) * 16;
+    const bool rok = R0 + fr < kb, cok = C0 + fr < nr;
+    mv_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
     for (int e = il_off[b]; e < il_off[b + 1]; ++e) {
       const int D = il[e], kd = k[D];
-      const double* Me = M + M_off[e] + (size_t)j * kd;
-      const double* qd = q + (size_t)koff[D] * nr + c;
-      for (int i = 0; i < kd; ++i) acc = fma(Me[i], qd[(size_t)i * nr], acc);
+      const double* Me = M + M_off[e] + (size_t)(R0 + fr) * kd;
+      const double* qd = q + (size_t)koff[D] * nr + C0 + fr;
+#pragma unroll 4
+      for (int k0 = 0; k0 < kd; k0 += 4) {
+        const int i = k0 + fk;
+        const double a = (rok && i < kd) ? Me[i] : 0.0;
+        const double bb = (cok && i < kd) ? qd[(size_t)i * nr] : 0.0;
+        acc = mv_mfma(a, bb, acc);
+      }
     }
-    double* o = loc + (size_t)(koff[b] + j) * nr + c;
-    *o = add ? *o + acc : acc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = R0 + fk + 4 * u, c = C0 + fr;
+      if (j < kb && c < nr) {
+        double* o = loc + (size_t)(koff[b] + j) * nr + c;
+        *o = add ? *o + acc[u] : acc[u];
+      }
+    }
   }
 }
 
@@ -132,11 +177,25 @@ __global__ void __launch_bounds__(WG) k_h2_down(const double* __restrict__ U, co
   const int b = blockIdx.x, kb = k[b];
   const int t0 = T_off[b], m = T_off[b + 1] - t0;
   const double* Ub = U + U_off[b];
-  for (int idx = threadIdx.x; idx < m * nr; idx += WG) {
-    const int r = idx / nr, c = idx - r * nr;
-    double acc = 0.0;
-    for (int j = 0; j < kb; ++j) acc = fma(Ub[(size_t)r * kb + j], loc[(size_t)(koff[b] + j) * nr + c], acc);
-    out[(size_t)(t0 + r) * nr + c] = acc;
+  const int lane = threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
+  const int tr = (m + 15) / 16, tc = (nr + 15) / 16;
+  for (int t = blockIdx.y * (WG / WAVE) + threadIdx.x / WAVE; t < tr * tc; t += gridDim.y * (WG / WAVE)) {
+    const int R0 = (t / tc) * 16, C0 = (t % tc) * 16;
+    const bool rok = R0 + fr < m, cok = C0 + fr < nr;
+    const double* Ur = Ub + (size_t)(R0 + fr) * kb;
+    mv_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < kb; k0 += 4) {
+      const int j = k0 + fk;
+      const double a = (rok && j < kb) ? Ur[j] : 0.0;
+      const double bb = (cok && j < kb) ? loc[(size_t)(koff[b] + j) * nr + C0 + fr] : 0.0;
+      acc = mv_mfma(a, bb, acc);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = R0 + fk + 4 * u, c = C0 + fr;
+      if (r < m && c < nr) out[(size_t)(t0 + r) * nr + c] = acc[u];
+    }
   }
 }
 
@@ -200,6 +259,11 @@ __global__ void __launch_bounds__(P2P_T) k_h2_p2p(KernelDesc K, const double* __
   }
 }
 
+__global__ void k_zero_vec(double* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 // column dot products: out[c] = sum_i a[i, c] b[i, c]  (row-major N x nr), partial sums per block
 __global__ void k_coldot(const double* a, const double* b, int64_t N, int nr, double* part) {
   __shared__ double sh[WG / WAVE + 1];
@@ -242,7 +306,7 @@ static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1
 
 // y = A x for tree-ordered row-major vectors
 void matvec_tree(aifmm_system& s, const double* x, int nr, double* y) {
-  dim3 grid(cdiv(s.N, MV_T), cdiv(nr, MV_R));
+  dim3 grid(cdiv(s.N, MV_T / WAVE * 16), cdiv(nr, MV_R));
   auto kern = s.K.kind == 0 ? (s.d == 2 ? k_matvec<0, 2> : k_matvec<0, 3>) : (s.d == 2 ? k_matvec<1, 2> : k_matvec<1, 3>);
   hipLaunchKernelGGL(kern, grid, dim3(MV_T), 0, s.stream, s.K, s.d_pts.p, s.N, x, nr, y);
   AIFMM_HIP(hipGetLastError());
@@ -267,20 +331,32 @@ void h2_matvec_tree(aifmm_system& s, const double* x, int nr, double* y, hipStre
     }
     hc.nr_cap = nr;
   }
+  // tile groups per box (four tiles of 16 x 16 each): enough workgroups at the coarse levels
+  auto groups = [&](int rows) {
+    int64_t t = (int64_t)((rows + 15) / 16) * ((nr + 15) / 16);
+    return (unsigned)std::max<int64_t>(1, (t + 3) / 4);
+  };
   for (int l = L; l >= 2; --l) {  // upward pass: P2M at the leaf, M2M above
     LevelDev& lv = S.lev[l];
     const double* src = l == L ? x : hc.q[l + 1].p;
-    hipLaunchKernelGGL(k_h2_up, dim3(lv.nb), dim3(WG), 0, st, lv.d_Unn.p, lv.d_Unn_off.p, lv.d_T_off.p, lv.d_knn.p,
-                       lv.d_koff_nn.p, src, hc.q[l].p, nr);
+    int kmax = 0;
+    for (int kb : lv.knn) kmax = std::max(kmax, kb);
+    hipLaunchKernelGGL(k_h2_up, dim3(lv.nb, groups(kmax)), dim3(WG), 0, st, lv.d_Unn.p, lv.d_Unn_off.p, lv.d_T_off.p,
+                       lv.d_knn.p, lv.d_koff_nn.p, src, hc.q[l].p, nr);
   }
   for (int l = 2; l <= L; ++l) {  // M2L, then L2L into the children (downward pass)
     LevelDev& lv = S.lev[l];
+    int kmax = 0, mmax = 0;
+    for (int b = 0; b < lv.nb; ++b) {
+      kmax = std::max(kmax, lv.knn[b]);
+      mmax = std::max(mmax, lv.T_off[b + 1] - lv.T_off[b]);
+    }
     // level 2 starts the locals; below it they already hold the parent's L2L contribution
-    hipLaunchKernelGGL(k_h2_m2l, dim3(lv.nb), dim3(WG), 0, st, lv.d_m2l_nn.p, lv.d_m2l_nn_off.p, lv.d_il_off.p,
-                       lv.d_il.p, lv.d_knn.p, lv.d_koff_nn.p, hc.q[l].p, hc.loc[l].p, nr, l > 2 ? 1 : 0);
+    hipLaunchKernelGGL(k_h2_m2l, dim3(lv.nb, groups(kmax)), dim3(WG), 0, st, lv.d_m2l_nn.p, lv.d_m2l_nn_off.p,
+                       lv.d_il_off.p, lv.d_il.p, lv.d_knn.p, lv.d_koff_nn.p, hc.q[l].p, hc.loc[l].p, nr, l > 2 ? 1 : 0);
     double* out = l < L ? hc.loc[l + 1].p : y;  // L2L writes the children's locals, L2P writes y
-    hipLaunchKernelGGL(k_h2_down, dim3(lv.nb), dim3(WG), 0, st, lv.d_Unn.p, lv.d_Unn_off.p, lv.d_T_off.p, lv.d_knn.p,
-                       lv.d_koff_nn.p, hc.loc[l].p, out, nr);
+    hipLaunchKernelGGL(k_h2_down, dim3(lv.nb, groups(mmax)), dim3(WG), 0, st, lv.d_Unn.p, lv.d_Unn_off.p,
+                       lv.d_T_off.p, lv.d_knn.p, lv.d_koff_nn.p, hc.loc[l].p, out, nr);
   }
   LevelDev& lf = S.lev[L];  // P2P near field of the leaf neighbours
   auto kern = S.K.kind == 0 ? (S.d == 2 ? k_h2_p2p<0, 2> : k_h2_p2p<0, 3>) : (S.d == 2 ? k_h2_p2p<1, 2> : k_h2_p2p<1, 3>);
@@ -357,53 +433,24 @@ void h2_matvec_system(aifmm_system& s, const double* x, int64_t nrhs, int64_t ld
 }
 
 // Right-preconditioned flexible GMRES(m) with modified Gram-Schmidt, all right-hand sides
-// advanced together (each with its own Hessenberg matrix); the preconditioner is the AIFMM
-// solve of s in tree order, the operator the H^2 product of op (the exact product of s when op
-// is null; op's tree is s's tree: same points and options).  Stops per column on the relative
-// residual of the operator <= rtol, recomputed from b - A x at every restart and at the end.
-void gmres_op_system(aifmm_system* op, aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol,
-                     int restart, int maxit, double* x, int64_t ldx, int32_t* iters, double* relres, bool b_dev,
-                     bool x_dev) {
+// advanced together (each with its own Hessenberg matrix), from x = 0: the preconditioner is the
+// AIFMM solve of s in tree order, the operator apply(); column c stops once its residual
+// b - A x (recomputed from x at every restart and at the end) is <= tgt[c].  rhs, x: tree-ordered
+// row-major device vectors (N x nr).  its[c] accumulates the iterations; res[c] gets the final
+// residual norms.  Returns the iterations used (the largest over the columns).
+template <class Apply>
+static int fgmres_tree(aifmm_system& s, Apply apply, const double* rhs, int nr, const std::vector<double>& tgt,
+                       int restart, int maxit, double* x, std::vector<int>& its, std::vector<double>& res) {
   hipStream_t st = s.stream;
-  int nr = (int)nrhs, m = std::max(1, restart);
-  int64_t N = s.N;
-  size_t vec = (size_t)N * nr;
+  const int m = std::max(1, restart);
+  const int64_t N = s.N;
+  const size_t vec = (size_t)N * nr;
   GmresCache& G = s.gc;
-  if (nr > G.nr_cap || m > G.m_cap) {
-    int nc = std::max(nr, G.nr_cap), mc = std::max(m, G.m_cap);
-    size_t v2 = (size_t)N * nc;
-    G.bt.alloc(v2);
-    G.xt.alloc(v2);
-    G.r.alloc(v2);
-    G.w.alloc(v2);
-    G.dalpha.alloc(nc);
-    G.V.clear();
-    G.Z.clear();
-    G.V.resize(mc + 1);
-    G.Z.resize(mc);
-    for (auto& v : G.V) v.alloc(v2);
-    for (auto& z : G.Z) z.alloc(v2);
-    G.nr_cap = nc;
-    G.m_cap = mc;
-  }
-  DBuf<double>&bt = G.bt, &xt = G.xt, &r = G.r, &w = G.w, &part = G.part, &dalpha = G.dalpha;
+  DBuf<double>&r = G.r, &w = G.w, &part = G.part, &dalpha = G.dalpha;
   std::vector<DBuf<double>>&V = G.V, &Z = G.Z;
-  const double* bs = b;
-  int64_t ldbs = ldb;
-  if (!b_dev) {  // host b: its N rows per column staged compactly
-    if ((int64_t)G.bin.n < N * nr) G.bin.alloc((size_t)N * nr);
-    h2d_cols(G.bin.p, b, ldb, N, nr, st);
-    bs = G.bin.p;
-    ldbs = N;
-  }
-  xt.zero(st);
-  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(vec, WG)), dim3(WG), 0, st, bs, ldbs, s.d_perm.p, N, nr, bt.p);
-  std::vector<double> bnorm = coldots(s, bt.p, bt.p, nr, part);
-  for (auto& v : bnorm) v = std::sqrt(v);
-  std::vector<int> done(nr, 0), its(nr, 0);
-  std::vector<double> rel(nr, 1.0);
   auto set_alpha = [&](const std::vector<double>& a) {
     AIFMM_HIP(hipMemcpyAsync(dalpha.p, a.data(), sizeof(double) * nr, hipMemcpyHostToDevice, st));
+    AIFMM_HIP(hipStreamSynchronize(st));  // the host vector may go out of scope
   };
   auto axpy = [&](const std::vector<double>& a, const double* xx, double* yy) {
     set_alpha(a);
@@ -413,25 +460,22 @@ void gmres_op_system(aifmm_system* op, aifmm_system& s, const double* b, int64_t
     set_alpha(a);
     hipLaunchKernelGGL(k_scale_cols, dim3(cdiv(vec, WG)), dim3(WG), 0, st, N, nr, dalpha.p, xx, yy);
   };
-  auto apply = [&](const double* xx, double* yy) {
-    if (op) h2_matvec_tree(*op, xx, nr, yy, st);
-    else matvec_tree(s, xx, nr, yy);
-  };
+  hipLaunchKernelGGL(k_zero_vec, dim3(cdiv(vec, WG)), dim3(WG), 0, st, x, (int64_t)vec);
+  std::vector<int> done(nr, 0);
   int total = 0;
-  bool x_zero = true;  // x is still the zero start, so A x = 0 and r = b exactly
+  bool x_zero = true;  // x is still the zero start, so A x = 0 and r = rhs exactly
   while (true) {
-    // true residual r = b - A x
-    AIFMM_HIP(hipMemcpyAsync(r.p, bt.p, sizeof(double) * vec, hipMemcpyDeviceToDevice, st));
+    AIFMM_HIP(hipMemcpyAsync(r.p, rhs, sizeof(double) * vec, hipMemcpyDeviceToDevice, st));
     if (!x_zero) {
-      apply(xt.p, w.p);
+      apply(x, w.p);
       axpy(std::vector<double>(nr, -1.0), w.p, r.p);
     }
     std::vector<double> beta = coldots(s, r.p, r.p, nr, part);
     bool all = true;
     for (int c = 0; c < nr; ++c) {
       beta[c] = std::sqrt(beta[c]);
-      rel[c] = bnorm[c] > 0 ? beta[c] / bnorm[c] : 0.0;
-      done[c] = rel[c] <= rtol;
+      res[c] = beta[c];
+      done[c] = beta[c] <= tgt[c];
       all = all && done[c];
     }
     if (all || total >= maxit) break;
@@ -478,7 +522,7 @@ void gmres_op_system(aifmm_system* op, aifmm_system& s, const double* b, int64_t
         g[j][c] = cs[j][c] * g[j][c];
         if (!done[c]) {
           ++its[c];
-          if (std::fabs(g[j + 1][c]) > rtol * 0.5 * bnorm[c]) conv = false;
+          if (std::fabs(g[j + 1][c]) > 0.5 * tgt[c]) conv = false;
         }
       }
       if (conv) { ++j; ++total; break; }
@@ -496,9 +540,94 @@ void gmres_op_system(aifmm_system* op, aifmm_system& s, const double* b, int64_t
     for (int i = 0; i < j; ++i) {
       std::vector<double> a(nr);
       for (int c = 0; c < nr; ++c) a[c] = done[c] ? 0.0 : H[(size_t)i * m][c];
-      axpy(a, Z[i].p, xt.p);
+      axpy(a, Z[i].p, x);
     }
     if (j > 0) x_zero = false;
+  }
+  return total;
+}
+
+// FGMRES to relative residual rtol (module comment above fgmres_tree) with the H^2 product of op
+// as the operator (the exact product of s when op is null; op's tree is s's tree: same points
+// and options).  With an H^2 operator the result is then checked with the exact product: the H^2
+// product carries an error of about eps_G |A|, which FGMRES cannot see, so while the exact
+// residual of a column is above rtol the exact residual is solved for (FGMRES with the same
+// operator) and added, at most three times.  relres reports the exact residual of each column.
+void gmres_op_system(aifmm_system* op, aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double rtol,
+                     int restart, int maxit, double* x, int64_t ldx, int32_t* iters, double* relres, bool b_dev,
+                     bool x_dev) {
+  hipStream_t st = s.stream;
+  int nr = (int)nrhs, m = std::max(1, restart);
+  int64_t N = s.N;
+  size_t vec = (size_t)N * nr;
+  GmresCache& G = s.gc;
+  if (nr > G.nr_cap || m > G.m_cap) {
+    int nc = std::max(nr, G.nr_cap), mc = std::max(m, G.m_cap);
+    size_t v2 = (size_t)N * nc;
+    G.bt.alloc(v2);
+    G.xt.alloc(v2);
+    G.r.alloc(v2);
+    G.w.alloc(v2);
+    G.rx.alloc(v2);
+    G.cx.alloc(v2);
+    G.dalpha.alloc(nc);
+    G.V.clear();
+    G.Z.clear();
+    G.V.resize(mc + 1);
+    G.Z.resize(mc);
+    for (auto& v : G.V) v.alloc(v2);
+    for (auto& z : G.Z) z.alloc(v2);
+    G.nr_cap = nc;
+    G.m_cap = mc;
+  }
+  DBuf<double>&bt = G.bt, &xt = G.xt, &part = G.part;
+  const double* bs = b;
+  int64_t ldbs = ldb;
+  if (!b_dev) {  // host b: its N rows per column staged compactly
+    if ((int64_t)G.bin.n < N * nr) G.bin.alloc((size_t)N * nr);
+    h2d_cols(G.bin.p, b, ldb, N, nr, st);
+    bs = G.bin.p;
+    ldbs = N;
+  }
+  hipLaunchKernelGGL(k_perm_rows_in, dim3(cdiv(vec, WG)), dim3(WG), 0, st, bs, ldbs, s.d_perm.p, N, nr, bt.p);
+  std::vector<double> bnorm = coldots(s, bt.p, bt.p, nr, part);
+  for (auto& v : bnorm) v = std::sqrt(v);
+  std::vector<int> its(nr, 0);
+  std::vector<double> res(nr, 0.0), tgt(nr), rel(nr, 0.0);
+  for (int c = 0; c < nr; ++c) tgt[c] = rtol * bnorm[c];
+  auto apply_op = [&](const double* xx, double* yy) {
+    if (op) h2_matvec_tree(*op, xx, nr, yy, st);
+    else matvec_tree(s, xx, nr, yy);
+  };
+  int total = fgmres_tree(s, apply_op, bt.p, nr, tgt, restart, maxit, xt.p, its, res);
+  for (int c = 0; c < nr; ++c) rel[c] = bnorm[c] > 0 ? res[c] / bnorm[c] : 0.0;
+  if (op) {
+    for (int round = 0;; ++round) {
+      // exact residual rx = b - A x
+      matvec_tree(s, xt.p, nr, G.w.p);
+      AIFMM_HIP(hipMemcpyAsync(G.rx.p, bt.p, sizeof(double) * vec, hipMemcpyDeviceToDevice, st));
+      std::vector<double> neg(nr, -1.0);
+      AIFMM_HIP(hipMemcpyAsync(G.dalpha.p, neg.data(), sizeof(double) * nr, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_axpy_cols, dim3(cdiv(vec, WG)), dim3(WG), 0, st, N, nr, G.dalpha.p, G.w.p, G.rx.p);
+      std::vector<double> rn = coldots(s, G.rx.p, G.rx.p, nr, part);
+      bool ok = true;
+      std::vector<double> t2(nr);
+      for (int c = 0; c < nr; ++c) {
+        rn[c] = std::sqrt(rn[c]);
+        rel[c] = bnorm[c] > 0 ? rn[c] / bnorm[c] : 0.0;
+        // the correction solve stops at half the allowed residual (columns already within
+        // rtol get a zero correction)
+        t2[c] = rel[c] <= rtol ? rn[c] : 0.5 * tgt[c];
+        ok = ok && rel[c] <= rtol;
+      }
+      if (ok || round >= 3 || total >= maxit) break;
+      std::vector<double> res2(nr, 0.0);
+      total += fgmres_tree(s, apply_op, G.rx.p, nr, t2, restart, maxit - total, G.cx.p, its, res2);
+      std::vector<double> one(nr, 1.0);
+      AIFMM_HIP(hipMemcpyAsync(G.dalpha.p, one.data(), sizeof(double) * nr, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_axpy_cols, dim3(cdiv(vec, WG)), dim3(WG), 0, st, N, nr, G.dalpha.p, G.cx.p, xt.p);
+      AIFMM_HIP(hipStreamSynchronize(st));
+    }
   }
   for (int c = 0; c < nr; ++c) {
     if (iters) iters[c] = its[c];

@@ -270,6 +270,7 @@ struct GmresCache {
   int nr_cap = 0, m_cap = 0;
   int64_t ld_cap = 0;
   DBuf<double> bin, bt, xt, r, w, part, dalpha, xo;
+  DBuf<double> rx, cx;  // exact residual and correction of the refinement with an H^2 operator
   std::vector<DBuf<double>> V, Z;
 };
 
