@@ -1023,7 +1023,17 @@ bool eliminate(oracle_sys& s, int l, int i) {
     s.err = "singular self-block at level " + std::to_string(l) + " box " + std::to_string(i);
     return false;
   }
-  F.W = lu_solve(F.LU, F.perm, Rb, 1, !(g_mode & MODE_ASC_BACK));
+  if (g_mode & MODE_ASC_BACK) {
+    // textbook: substitution on the right-hand sides, ascending back substitution
+    F.W = lu_solve(F.LU, F.perm, Rb, 1, false);
+  } else {
+    // W = Piv^{-1} [rhs] as the product of the explicit inverse of the pivot block (formed by
+    // substitution on the identity's columns, column-oriented back substitution) with the
+    // right-hand sides, each element summed in ascending k
+    Mat Pinv = lu_solve(F.LU, F.perm, eye(m, 1.0), -1, true);
+    F.W = mul(Pinv, Rb, 1);
+    g_flops[1] += 2.0 * m * m * m;
+  }
   Mat Upd = mul(Cb, F.W, 2);
   // scatter: A[O_r, O_c] -= A[O_r, (x_i, z_i)] Piv^{-1} A[(X_i, Y_i), O_c]
   {

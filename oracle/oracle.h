@@ -58,7 +58,10 @@ oracle_sys* oracle_create(const double* pts, int64_t n, int d, int kind, double 
                              the Cody-Waite / Taylor routine;
      ORACLE_MODE_ASC_SUMS    row sums of the pivoted QRs and Q formations as one ascending
                              chain instead of sixteen interleaved chains and a tree;
-     ORACLE_MODE_ASC_BACK    back substitution of the pivot blocks in ascending column order;
+     ORACLE_MODE_ASC_BACK    the pivot-block solve W = Piv^{-1} [rhs] as substitution on the
+                             right-hand sides with ascending back substitution, instead of the
+                             product of the explicit inverse (formed by substitution on the
+                             identity's columns, column-oriented back substitution) with them;
      ORACLE_MODE_SEQUENTIAL  the Algorithm's order box by box (each compression applied in full,
                              then the elimination) instead of colour rounds.
    ORACLE_MODE_TEXTBOOK = all four. */

@@ -354,15 +354,17 @@ __device__ inline int64_t near_entry(const LevelPtrs& P, int p, int q) {
   return -1;
 }
 
-// Pivot block [[K_bb, U_b],[V_b^*, 0]], right-hand sides [A[X_b, O_c] | E | I] and the
-// coupled column blocks A[O_r, x_b] of box b (one workgroup per box).
+// Pivot block [[K_bb, U_b],[V_b^*, 0]] (into the factor store), right-hand sides
+// [A[X_b, O_c] | E | I] (into the colour's workspace, ld C + n) and the coupled column blocks
+// A[O_r, x_b] of box b (GS workgroups per box).
 constexpr int GS = 16;  // workgroups per box of k_elim_gather
-__global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __restrict__ boxes) {
+__global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __restrict__ boxes, double* rws,
+                                                   int64_t rstride) {
   int b = boxes[blockIdx.x];
   int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
   int n = P.n[b], k = P.k[b], m = n + k;
   double* Piv = P.fslab + P.fLU[b];
-  double* W = P.fslab + P.fW[b];
+  double* W = rws + (size_t)blockIdx.x * rstride;  // the right-hand sides [A[X_b, O_c] | E | I]
   double* Cb = P.fslab + P.fC[b];
   // column (co) and coupled-row (ro) offsets of the groups, the group sizes and source blocks
   __shared__ int co[29], ro[29], cdim[28];
@@ -621,27 +623,118 @@ k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int ti
   }
 }
 
-// W = Piv^{-1} [rhs] for the pivot block of every box of a colour, with the LU factors of
-// k_elim_lu (row permutation in fpiv).  One wave owns 16 columns of W and walks the rows in
-// blocks of 16, left-looking.  Forward (unit lower L): a block's rows start from the permuted
-// right-hand side, take the terms of every earlier row through FP64 MFMA 16x16x4 in ascending
-// column order, then the in-block terms one at a time (16 lanes, one column each), so every
-// element is the ascending fused multiply-add chain of the forward substitution; the result
-// goes to the workspace X (the layout of W).  Backward (upper U): a block's rows take the terms
-// of every later row through MFMA in descending column order (four columns per MFMA, highest
-// first), then the in-block terms in descending order and the division by the diagonal: the
-// column-oriented back substitution, element by element.  The wave's stores are fenced before
-// its later blocks read them; waves share nothing, so the workgroup never synchronises.
-constexpr int TW = 4;  // waves per workgroup
-__global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int* __restrict__ boxes, const int* flag,
-                                                         double* tws, int64_t tstride) {
+// W = Piv^{-1} [rhs] for every box of a colour: (m x m, ld m, from k_elim_trsm) times the
+// right-hand sides (m x (C + n), ld C + n, from k_elim_gather) into the factor store's W.  The
+// tiles of the Schur update: 64 x 64 per workgroup, 2 x 2 blocks of FP64 MFMA 16x16x4 per wave, K
+// chunks of 16 through LDS with the next chunk prefetched into registers, XCD-aware tile order;
+// every element is the ascending fused multiply-add chain over k from zero.
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5)))
+k_elim_wgemm(LevelPtrs P, const int* __restrict__ boxes, const int* flag, const double* __restrict__ pws,
+             int64_t pstride, const double* __restrict__ rws, int64_t rstride) {
   if (flag[0]) return;
   const int b = boxes[blockIdx.y];
   const int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
-  const int n = P.n[b], k = P.k[b], m = n + k;
+  const int n = P.n[b], m = n + P.k[b];
   int C = 0;
   for (int g = 0; g < G; ++g) C += grp_rows(P, g, G, b, P.grp_box[g0 + g], P.grp_elim[g0 + g]);
   const int ldw = C + n;
+  __shared__ double As[ST][SK + 1];
+  __shared__ double Bs[SK][ST + 1];
+  const int tiles_r = (m + ST - 1) / ST, tcn = (ldw + ST - 1) / ST;
+  const int nt = tiles_r * tcn, per = (nt + 7) / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (m == 0 || blockIdx.x >= 8 * per || t >= nt) return;
+  constexpr int SG = 8;
+  const int grp = t / (SG * tcn), rem = t - grp * SG * tcn;
+  const int gh = min(SG, tiles_r - grp * SG);
+  const int r0 = (grp * SG + rem % gh) * ST, c0 = (rem / gh) * ST;
+  const double* Pinv = pws + (size_t)blockIdx.y * pstride + pstride / 2;
+  const double* R = rws + (size_t)blockIdx.y * rstride;
+  double* W = P.fslab + P.fW[b];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int wr = (wv / 2) * (ST / 2), wc = (wv % 2) * (ST / 2);
+  const int fr = lane % 16, fk = lane / 16;
+  dbl4 acc[BL][BL];
+#pragma unroll
+  for (int i = 0; i < BL; ++i)
+#pragma unroll
+    for (int j = 0; j < BL; ++j) acc[i][j] = dbl4{0, 0, 0, 0};
+  constexpr int NA = ST * SK / WG, NBv = SK * ST / WG;
+  double ra[NA], rb[NBv];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      int idx = threadIdx.x + u * WG;
+      int gr = r0 + idx / SK, gk = k0 + idx % SK;
+      ra[u] = (gr < m && gk < m) ? Pinv[(size_t)gr * m + gk] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NBv; ++u) {
+      int idx = threadIdx.x + u * WG;
+      int gk = k0 + idx / ST, gc = c0 + idx % ST;
+      rb[u] = (gk < m && gc < ldw) ? R[(size_t)gk * ldw + gc] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < m; k0 += SK) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      int idx = threadIdx.x + u * WG;
+      As[idx / SK][idx % SK] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NBv; ++u) {
+      int idx = threadIdx.x + u * WG;
+      Bs[idx / ST][idx % ST] = rb[u];
+    }
+    __syncthreads();
+    if (k0 + SK < m) fetch(k0 + SK);
+#pragma unroll
+    for (int k4 = 0; k4 < SK; k4 += 4) {
+      double a[BL], bb[BL];
+#pragma unroll
+      for (int i = 0; i < BL; ++i) a[i] = As[wr + 16 * i + fr][k4 + fk];
+#pragma unroll
+      for (int j = 0; j < BL; ++j) bb[j] = Bs[k4 + fk][wc + 16 * j + fr];
+#pragma unroll
+      for (int i = 0; i < BL; ++i)
+#pragma unroll
+        for (int j = 0; j < BL; ++j) acc[i][j] = mfma16(a[i], bb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  // output (lane, q) of block (i, j): row wr + 16 i + lane / 16 + 4 q, column wc + 16 j + lane % 16
+#pragma unroll
+  for (int i = 0; i < BL; ++i)
+#pragma unroll
+    for (int j = 0; j < BL; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + wr + 16 * i + fk + 4 * q, c = c0 + wc + 16 * j + fr;
+        if (r < m && c < ldw) W[(size_t)r * ldw + c] = acc[i][j][q];
+      }
+}
+
+// Piv^{-1} for the pivot block of every box of a colour, with the LU factors of k_elim_lu (row
+// permutation in fpiv): the substitution on the columns of the identity, Piv^{-1} =
+// U^{-1} L^{-1} P.  One wave owns 16 columns and walks the rows in blocks of 16, left-looking.
+// Forward (unit lower L): a block's rows start from the permuted identity, take the terms of
+// every earlier row through FP64 MFMA 16x16x4 in ascending column order, then the in-block terms
+// one at a time (16 lanes, one column each), so every element is the ascending fused
+// multiply-add chain of the forward substitution; the result goes to the workspace X.  Backward
+// (upper U): a block's rows take the terms of every later row through MFMA in descending column
+// order (four columns per MFMA, highest first), then the in-block terms in descending order and
+// the division by the diagonal: the column-oriented back substitution, element by element; the
+// result is the inverse, m x m with ld m, after X in the box's workspace.  The wave's stores are
+// fenced before its later blocks read them; waves share nothing, so the workgroup never
+// synchronises.  W = Piv^{-1} [rhs] is then one product (k_elim_wgemm).
+constexpr int TW = 4;  // waves per workgroup
+__global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int* __restrict__ boxes, const int* flag,
+                                                         double* pws, int64_t pstride) {
+  if (flag[0]) return;
+  const int b = boxes[blockIdx.y];
+  const int n = P.n[b], k = P.k[b], m = n + k;
+  const int ldw = m;  // the identity's columns
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const int c0 = (blockIdx.x * TW + wv) * 16;
   if (c0 >= ldw || m == 0) return;  // the whole wave
@@ -650,8 +743,8 @@ __global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int*
   const bool cok = col < ldw;
   const double* A = P.fslab + P.fLU[b];
   const int* perm = P.fpiv + P.fpiv_off[b];
-  double* W = P.fslab + P.fW[b];
-  double* X = tws + (size_t)blockIdx.y * tstride;
+  double* X = pws + (size_t)blockIdx.y * pstride;  // forward results, m x m
+  double* W = X + pstride / 2;                     // the inverse, m x m
   __shared__ double xs_all[TW][16][17], ls_all[TW][16][17];
   double(*xs)[17] = xs_all[wv];
   double(*ls)[17] = ls_all[wv];
@@ -702,7 +795,7 @@ __global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int*
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int r = R0 + fk + 4 * q;
-      acc[q] = (r < m && cok) ? W[(size_t)perm[r] * ldw + col] : 0.0;
+      acc[q] = (r < m && cok && perm[r] == col) ? 1.0 : 0.0;  // row perm[r] of the identity
     }
     const bool aok = R0 + fr < m;
     const double* Ar = A + (size_t)(R0 + fr) * m;
@@ -1489,12 +1582,12 @@ static void count_flops(aifmm_system& s, int l) {
     double n = lv.n[b], m = lv.n[b] + lv.kfin[b];
     s.stats.schur_flops += 2.0 * R * n * C;
     s.stats.schur_bytes += 8.0 * (R * n + n * C + 2.0 * R * C);
-    s.stats.trsm_flops += 2.0 * m * m * (C + n);
+    s.stats.trsm_flops += 2.0 * m * m * m + 2.0 * m * m * (C + n);
     s.stats.lu_flops += 2.0 * m * m * m / 3.0;
     ls.schur_flops += 2.0 * R * n * C;
     ls.schur_bytes += 8.0 * (R * n + n * C + 2.0 * R * C);
     ls.trsm_flops += 2.0 * m * m * C;
-    ls.trsm_flops_impl += 2.0 * m * m * (C + n);
+    ls.trsm_flops_impl += 2.0 * m * m * m + 2.0 * m * m * (C + n);
     ls.lu_flops += 2.0 * m * m * m / 3.0;
   }
 }
@@ -1602,7 +1695,8 @@ static void factor_levels(aifmm_system& s) {
     DBuf<double> ws, scratch;
     ws.alloc((size_t)maxcol * wsz);
     scratch.alloc((size_t)XG * (WG / WAVE) * wstride);
-    // forward results of the pivot-block solves of one colour (a W-sized block per box) and the
+    // the right-hand sides of the pivot-block solves of one colour (a W-sized block per box),
+    // the forward results and inverses of the pivot blocks (two m x m blocks per box), and the
     // LDS of the row permutation of each pivot-block LU
     int64_t tstride = 2;
     int maxmc = 1;
@@ -1610,8 +1704,10 @@ static void factor_levels(aifmm_system& s) {
       tstride = std::max(tstride, (int64_t)2 * lv.n[b] * (lv.Ccap[b] + lv.n[b]));
       maxmc = std::max(maxmc, 2 * lv.n[b]);
     }
-    DBuf<double> tws;
+    DBuf<double> tws, pws;
     tws.alloc((size_t)maxcol * tstride);
+    const int64_t pstride = (int64_t)2 * maxmc * maxmc;
+    pws.alloc((size_t)maxcol * pstride);
     // LU: LDS panels where they fit (up to 140 KB beside the kernel's static LDS), and the
     // permutation
     const size_t lu_perm = (size_t)2 * maxmc * sizeof(int);
@@ -1816,7 +1912,7 @@ static void factor_levels(aifmm_system& s) {
       }
       int nbox = Pl.col_off[c + 1] - Pl.col_off[c];
       const int* boxes = d_order.p + Pl.col_off[c];
-      hipLaunchKernelGGL(k_elim_gather, dim3(nbox, GS), dim3(WG), 0, st, P, boxes);
+      hipLaunchKernelGGL(k_elim_gather, dim3(nbox, GS), dim3(WG), 0, st, P, boxes, tws.p, tstride);
       {
         // teams of up to 16 co-resident workgroups per pivot block
         const int Gl = (lu_coop > 0) ? std::max(1, std::min(16, lu_coop / std::max(1, nbox))) : 1;
@@ -1836,8 +1932,13 @@ static void factor_levels(aifmm_system& s) {
       }
       auto te = ev_pair(trs_ev);
       AIFMM_HIP(hipEventRecord(te.first, st));
-      hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(lv.Cmax, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes, s.d_flag.p,
-                         tws.p, tstride);
+      hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(maxmc, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes, s.d_flag.p,
+                         pws.p, pstride);
+      {
+        const int wt = (int)(cdiv(maxmc, ST) * (int64_t)cdiv(lv.Cmax, ST));
+        hipLaunchKernelGGL(k_elim_wgemm, dim3(8 * cdiv(wt, 8), nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, pws.p,
+                           pstride, tws.p, tstride);
+      }
       AIFMM_HIP(hipEventRecord(te.second, st));
       int tiles_c = cdiv(lv.Cmax, ST), tiles_r = cdiv(std::max(1, lv.Rmax), ST);
       int tiles_x = 8 * cdiv((int64_t)tiles_r * tiles_c, 8);
