@@ -864,6 +864,191 @@ __global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int*
   }
 }
 
+// The same inverse, right-looking: a workgroup of NW waves owns a strip of 16 columns of the
+// identity and keeps all of the strip's rows in FP64 MFMA accumulators, row block i (16 rows)
+// in wave i mod NW (PMB blocks per wave, so m <= 256 NW).  Forward, block by block: the owner of
+// block j, whose rows have taken the terms of every earlier block, adds the in-block terms one
+// at a time (16 lanes, one column each) and publishes the finished block in LDS; after one
+// workgroup barrier every wave adds the block's terms to its later blocks through MFMA, four
+// columns per MFMA in ascending order.  Backward likewise from the last block, with the terms
+// of later blocks in descending column order and the division by the diagonal at the end of
+// each element's chain; the finished blocks are the rows of the inverse.  Every element thus
+// receives exactly the fused multiply-add sequence of the column-oriented substitution (the
+// MFMA slots past the matrix add exact zeros), the same as k_elim_trsm, while a strip's chain
+// of dependent steps is spread over NW waves and the factors are read once per strip.
+// Accumulators are indexed by constants only: a wave's array is rotated by one position each
+// time it finishes a block, so the block it works on next is always in position 0 (position p
+// holds the wave's block (p + rot) mod PMB).  PMB (blocks per wave) sets the register footprint:
+// the host takes the shape with the fewest registers that holds the level's largest block.
+template <int NW, int PMB>
+__global__ void __launch_bounds__(NW * WAVE) k_elim_pinv(LevelPtrs P, const int* __restrict__ boxes, const int* flag,
+                                                         double* pws, int64_t pstride) {
+  if (flag[0]) return;
+  const int b = boxes[blockIdx.y];
+  const int m = P.n[b] + P.k[b];
+  const int c0 = blockIdx.x * 16;
+  if (c0 >= m) return;  // the whole workgroup
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int fr = lane % 16, fk = lane / 16;
+  const int col = c0 + fr;
+  const bool cok = col < m;
+  const double* A = P.fslab + P.fLU[b];
+  const int* perm = P.fpiv + P.fpiv_off[b];
+  double* W = pws + (size_t)blockIdx.y * pstride + pstride / 2;  // the inverse, m x m, ld m
+  const int nblk = (m + 15) / 16;
+  if (nblk > PMB * NW) return;      // the host sizes the launch so that this never happens
+  constexpr int HC = PMB < 8 ? PMB : 8;  // blocks whose factor operands are loaded together
+  __shared__ double xs[2][16][17];  // the finished block of the step, alternating with its parity
+  __shared__ double ts[16][17];     // the owner's block before its in-block terms
+  __shared__ double ls[16][17];     // the diagonal 16 x 16 block of the factors
+  dbl4 acc[PMB];
+  int rot = 0;
+  auto rot_left = [&]() {
+    dbl4 t = acc[0];
+#pragma unroll
+    for (int u = 0; u + 1 < PMB; ++u) acc[u] = acc[u + 1];
+    acc[PMB - 1] = t;
+    rot = rot + 1 == PMB ? 0 : rot + 1;
+  };
+  auto rot_right = [&]() {
+    dbl4 t = acc[PMB - 1];
+#pragma unroll
+    for (int u = PMB - 1; u > 0; --u) acc[u] = acc[u - 1];
+    acc[0] = t;
+    rot = rot == 0 ? PMB - 1 : rot - 1;
+  };
+  // forward: the rows of the permuted identity (row r holds e_{perm[r]})
+#pragma unroll
+  for (int u = 0; u < PMB; ++u) {
+    const int i = wv + NW * u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * i + fk + 4 * q;
+      acc[u][q] = (i < nblk && r < m && cok && perm[r] == col) ? 1.0 : 0.0;
+    }
+  }
+  // the owner's block (position 0) and the diagonal block of the factors into LDS
+  auto stage = [&](int R0, int nr) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ts[fk + 4 * q][fr] = acc[0][q];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int idx = lane + WAVE * v, i = idx / 16, t = idx % 16;
+      ls[i][t] = (i < nr && t < nr) ? A[(size_t)(R0 + i) * m + R0 + t] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
+  int step = 0;
+  for (int j = 0; j < nblk; ++j, ++step) {
+    const int R0 = 16 * j, nr = min(16, m - R0), p = step & 1;
+    if (wv == j % NW) {
+      stage(R0, nr);
+      if (lane < 16) {
+        double x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = ts[r][lane];
+#pragma unroll
+        for (int r = 1; r < 16; ++r)
+#pragma unroll
+          for (int t = 0; t < r; ++t)
+            if (r < nr) x[r] = fma(-ls[r][t], x[t], x[r]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xs[p][r][lane] = x[r];
+      }
+      __builtin_amdgcn_wave_barrier();
+      // the finished rows stay in the accumulators for the backward pass
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[0][q] = xs[p][fk + 4 * q][fr];
+      rot_left();
+    }
+    __syncthreads();
+    double bx[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) bx[s] = xs[p][4 * s + fk][fr];
+    // later blocks i > j: slot fk of MFMA s takes column R0 + 4 s + fk of the factors
+#pragma unroll
+    for (int h = 0; h < PMB; h += HC) {
+      double la[HC][4];
+#pragma unroll
+      for (int u = h; u < h + HC; ++u) {
+        const int uu = u + rot < PMB ? u + rot : u + rot - PMB;
+        const int i = wv + NW * uu, row = 16 * i + fr;
+        const bool on = i > j && i < nblk && row < m;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int t = R0 + 4 * s + fk;
+          la[u - h][s] = (on && t < m) ? -A[(size_t)row * m + t] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = h; u < h + HC; ++u) {
+        const int uu = u + rot < PMB ? u + rot : u + rot - PMB;
+        const int i = wv + NW * uu;
+        if (i > j && i < nblk)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc[u] = mfma16(la[u - h][s], bx[s], acc[u]);
+      }
+    }
+  }
+  // the wave's blocks in descending order: its block u sits in position 0 once rot == u
+  for (int j = nblk - 1; j >= 0; --j, ++step) {
+    const int R0 = 16 * j, nr = min(16, m - R0), p = step & 1;
+    if (wv == j % NW) {
+      while (rot != j / NW) rot_right();
+      stage(R0, nr);
+      if (lane < 16) {
+        double x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = ts[r][lane];
+#pragma unroll
+        for (int r = 15; r >= 0; --r)
+          if (r < nr) {
+            double v = x[r];
+#pragma unroll
+            for (int t = 15; t > r; --t)
+              if (t < nr) v = fma(-ls[r][t], x[t], v);
+            x[r] = v / ls[r][r];
+          }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          xs[p][r][lane] = x[r];
+          if (cok && r < nr) W[(size_t)(R0 + r) * m + col] = x[r];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if (j == 0) break;
+    // earlier blocks i < j: slot fk of MFMA s takes column R0 + 15 - 4 s - fk (descending)
+    double bx[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) bx[s] = xs[p][15 - 4 * s - fk][fr];
+#pragma unroll
+    for (int h = 0; h < PMB; h += HC) {
+      double la[HC][4];
+#pragma unroll
+      for (int u = h; u < h + HC; ++u) {
+        const int uu = u + rot < PMB ? u + rot : u + rot - PMB;
+        const int i = wv + NW * uu, row = 16 * i + fr;
+        const bool on = i < j && row < m;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int t = R0 + 15 - 4 * s - fk;
+          la[u - h][s] = (on && t < m) ? -A[(size_t)row * m + t] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = h; u < h + HC; ++u) {
+        const int uu = u + rot < PMB ? u + rot : u + rot - PMB;
+        const int i = wv + NW * uu;
+        if (i < j)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc[u] = mfma16(la[u - h][s], bx[s], acc[u]);
+      }
+    }
+  }
+}
+
 // One 16-wide output slab of an in-place product on MFMA 16x16x4 of precision RT: out = opA opB
 // (M x N, K terms), element (i, k) of opA at A[i ai + k ak] and (k, j) of opB at B[k bk + j bj],
 // operands converted to RT.  In FP64 every element is the ascending fused multiply-add chain
@@ -1629,6 +1814,46 @@ static bool lu_panels_off() {
   return v && *v && *v != '0';
 }
 
+// Shape of the right-looking pivot-block inverse for pivot blocks of up to maxmc rows and
+// `strips` strips of 16 columns: nw waves per workgroup and pb row blocks per wave (16 pb nw >=
+// maxmc); nw = 0 selects the left-looking kernel (blocks of 513 to 1024 or above 2048 rows, or
+// the test switch AIFMM_PINV_LEFT).  AIFMM_PINV_SHAPE=<nw>x<pb> forces one of the compiled shapes.
+static void pinv_shape(int maxmc, int64_t strips, int& nw, int& pb) {
+  nw = pb = 0;
+  const char* v = getenv("AIFMM_PINV_LEFT");
+  if ((v && *v && *v != '0') || maxmc > 2048) return;
+  static const int shapes[][2] = {{1, 16}, {2, 16}, {4, 16}, {8, 16}, {2, 8}, {4, 8}, {8, 8}, {4, 4}, {8, 4}, {16, 4}};
+  const char* f = getenv("AIFMM_PINV_SHAPE");
+  if (f && *f) {
+    int a = 0, c = 0;
+    if (sscanf(f, "%dx%d", &a, &c) == 2)
+      for (auto& sh : shapes)
+        if (sh[0] == a && sh[1] == c && 16 * a * c >= maxmc) {
+          nw = a;
+          pb = c;
+          return;
+        }
+  }
+  // blocks of 513 to 1024 rows: the left-looking kernel (measured faster there, where a level has
+  // many boxes per colour); otherwise the fewest blocks per wave that hold the block with at most
+  // 8 waves (fewer registers, more workgroups per compute unit), then more waves per strip while
+  // the grid stays within about one pass over the device's wave slots
+  if (maxmc > 512 && maxmc <= 1024) return;
+  const int nblk = (maxmc + 15) / 16;
+  for (int c : {4, 8, 16}) {
+    int a = 1;
+    while (a < 8 && 16 * a * c < maxmc) a *= 2;
+    if (16 * a * c < maxmc) continue;
+    while (a < (c == 4 ? 16 : 8) && 2 * a <= nblk && strips * 2 * a <= 4096) a *= 2;
+    for (auto& sh : shapes)
+      if (sh[0] == a && sh[1] == c) {
+        nw = a;
+        pb = c;
+        return;
+      }
+  }
+}
+
 // test switch: raise the team abort flag from the host before a level's first launch
 static bool debug_abort() {
   const char* v = getenv("AIFMM_DEBUG_ABORT");
@@ -1932,8 +2157,26 @@ static void factor_levels(aifmm_system& s) {
       }
       auto te = ev_pair(trs_ev);
       AIFMM_HIP(hipEventRecord(te.first, st));
-      hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(maxmc, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes, s.d_flag.p,
-                         pws.p, pstride);
+      {
+        // right-looking inverse on strips of 16 columns (shape from pinv_shape), else the
+        // left-looking kernel
+        const int nblk = cdiv(maxmc, 16);
+        int nw = 0, pb = 0;
+        pinv_shape(maxmc, nblk * nbox, nw, pb);
+        int* flagp = s.d_flag.p;
+        const dim3 pg(nblk, nbox);
+#define AIFMM_PINV(NW_, PB_)                                                                            \
+  else if (nw == NW_ && pb == PB_) hipLaunchKernelGGL((k_elim_pinv<NW_, PB_>), pg, dim3(NW_ * WAVE), 0, st, P, \
+                                                      boxes, flagp, pws.p, pstride);
+        if (nw == 0)
+          hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(maxmc, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes,
+                             s.d_flag.p, pws.p, pstride);
+        AIFMM_PINV(1, 16) AIFMM_PINV(2, 16) AIFMM_PINV(4, 16) AIFMM_PINV(8, 16)
+        AIFMM_PINV(2, 8) AIFMM_PINV(4, 8) AIFMM_PINV(8, 8)
+        AIFMM_PINV(4, 4) AIFMM_PINV(8, 4) AIFMM_PINV(16, 4)
+#undef AIFMM_PINV
+        else throw Error{AIFMM_ERR_STATE, "no pivot-inverse kernel of the chosen shape"};
+      }
       {
         const int wt = (int)(cdiv(maxmc, ST) * (int64_t)cdiv(lv.Cmax, ST));
         hipLaunchKernelGGL(k_elim_wgemm, dim3(8 * cdiv(wt, 8), nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, pws.p,

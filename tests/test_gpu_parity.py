@@ -1,7 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
 Bar (from the method's required outputs): per-level box -> rank tables bit-exact (NNCA ranks,
-pivot lists and the ranks chosen by every compression), solution relative error <= 1e-8
+pivot lists and the ranks chosen by every compression), the decision ratios |R_kk| / (eps_A |R_11|)
+of every pivoted QR bit-identical (so every operation on the rank-deciding path agrees, not only
+the decisions), solution relative error <= 1e-8
 against the oracle's solution, and the brute-force residual of the GPU solution no worse than the
 oracle's (0.1%; the solve sums in a blocked order).  Both sides execute the same IEEE operation sequence on the
 rank-deciding path (explicit fused multiply-adds, no contraction elsewhere), so the decisions
@@ -32,14 +34,17 @@ CASES = [
 
 # Switches of the library that change which kernel path runs, never an operation's order:
 # compression columns in the workspace instead of LDS, with teams of up to 48 members (the
-# shapes the large workloads run) or of at most 4, lone workgroups only, and pivot-block LU
-# panels factored in device memory instead of LDS (the path of pivot blocks above ~1050 rows).
+# shapes the large workloads run) or of at most 4, lone workgroups only, pivot-block LU
+# panels factored in device memory instead of LDS (the path of pivot blocks above ~1050 rows),
+# and the pivot-block inverse by the left-looking kernel (the small cases otherwise take the
+# right-looking one).
 SWITCHES = [
     ("workspace_columns_large_teams", {"AIFMM_NO_LDS_COLUMNS": "1", "AIFMM_TEAM_ELEMS": "1024"}),
     ("workspace_columns_small_teams", {"AIFMM_NO_LDS_COLUMNS": "1", "AIFMM_TEAM_ELEMS": "1024",
                                        "AIFMM_TEAM_MAX": "2"}),
     ("no_teams", {"AIFMM_NO_TEAMS": "1"}),
     ("lu_panels_in_memory", {"AIFMM_NO_LDS_PANELS": "1"}),
+    ("pivot_inverse_left_looking", {"AIFMM_PINV_LEFT": "1"}),
 ]
 SWITCH_CASES = [c for c in CASES if c[0] in ("invmq_L3", "exp_half_L4", "3d_L3")]
 
@@ -68,11 +73,19 @@ def _compare(g, o, pts, b, kernel):
             np.testing.assert_array_equal(si, osi, err_msg=f"column pivots level {l} box {box}")
     g.factor()
     o.factor()
-    grec, _ = g.trace()
+    grec, grat = g.trace()
     otr = o.trace()
     ork, ora = o.trace_ranks()
     assert len(grec) == len(otr)
     gmap = {tuple(r[:4]): r[4:] for r in grec}
+    rmap = {tuple(r[:4]): q for q, r in enumerate(grec)}
+    # the decision ratios |R_kk| / (eps_A |R_11|) of every pivoted QR, as a measure of how far the
+    # two sides' arithmetic agrees beyond the ranks (identical when every operation agrees)
+    rd = [np.max(np.abs(grat[rmap[tuple(otr[q])]] - ora[q]) / np.maximum(np.abs(ora[q]), 1e-300))
+          for q in range(len(otr)) if tuple(otr[q]) in rmap]
+    if rd:
+        print(f"decision ratios: {np.mean(np.array(rd) == 0):.3f} identical, max rel diff {max(rd):.3e}", flush=True)
+        assert max(rd) == 0.0, "decision ratios differ from the oracle's: the arithmetic is not the same"
     for q in range(len(otr)):
         key = tuple(otr[q])
         assert key in gmap, f"compression {key} missing on the device"
