@@ -93,10 +93,15 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   const bool split = G > 1;
   const int GA = G / 2;
   const bool inA = T.member < GA;
-  Team<CT> S;
+  // the team that runs a chain: the half-team when split, else the lone workgroup (G == 1, whose
+  // barrier keeps no state); one object initialised from selected values, so it stays in
+  // registers
+  Team<CT> C;
   if (split)
-    S.init(inA ? T.member : T.member - GA, inA ? GA : G - GA, ctr + nent + 2 * e + (inA ? 0 : 1),
+    C.init(inA ? T.member : T.member - GA, inA ? GA : G - GA, ctr + nent + 2 * e + (inA ? 0 : 1),
            part + (size_t)e * 4 * G + 2 * G + (inA ? 0 : 2 * GA), abort);
+  else
+    C.init(0, 1, ctr + e, part + (size_t)e * 4 * G, abort);
   RoundEntry R = ent[e];
   int* tr = P.trace + (tbase + e) * 6;
   double* trr = P.trace_ratio + (tbase + e) * 8;
@@ -149,9 +154,6 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     // two chains: RRQR1 -> Q1 -> RRQR3 and RRQR2 -> Q2 -> RRQR4 (sub-teams A and B, or one
     // after the other on a lone workgroup)
     int r1 = 0, r2 = 0, r3 = 0, r4 = 0;
-    // the team that runs a chain: a copy (without a split the team is a lone workgroup, whose
-    // barrier keeps no state; with one, only the half-team runs the chain)
-    Team<CT> C = split ? S : T;
     if (!split || inA) {
       // RRQR1: [U_i | P2P_ij] = U~_i L_ij
       int ld = ki + nj;
@@ -271,9 +273,6 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
     double* Ari = P.slab + P.il_slot[R.e_ji];  // (Z_r, y_i): kr x ki, ld ni
     int ld = ki + kr;
     int r5 = 0, r6 = 0;
-    // the team that runs a chain: a copy (without a split the team is a lone workgroup, whose
-    // barrier keeps no state; with one, only the half-team runs the chain)
-    Team<CT> C = split ? S : T;
     if (!split || inA) {
       // RRQR: [V_i | P2L_ri^*] = V~_i R_ri
       t_copy(C, ni, ki, V_i, ni, M, ld);

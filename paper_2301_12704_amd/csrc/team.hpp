@@ -32,7 +32,7 @@ struct Team {
   bool bad = false;           // the abort flag was seen at the last barrier: data exchanged through
                               // the team may be stale, so callers stop using it and exit
 
-  __device__ void init(int member_, int G_, unsigned* ctr_, Cand* part_, int* abort_) {
+  __device__ __attribute__((always_inline)) void init(int member_, int G_, unsigned* ctr_, Cand* part_, int* abort_) {
     member = member_;
     G = G_;
     gtid = member * NT + (int)threadIdx.x;
@@ -51,7 +51,7 @@ struct Team {
   // after the wait and the workgroup takes its value through LDS, so bad is uniform over the
   // workgroup (members of a team may see the flag at different barriers; once raised it stays
   // raised, so every later barrier of every member falls through and sets bad).
-  __device__ void sync(unsigned max_spins = 1u << 24) {
+  __device__ __attribute__((always_inline)) void sync(unsigned max_spins = 1u << 24) {
     __shared__ int s_bad;
     __syncthreads();
     if (G == 1) return;
@@ -77,7 +77,7 @@ struct Team {
   }
 
   // Publish one value per member and return all G of them (the same array on every thread).
-  __device__ const Cand* exchange(const Cand& c) {
+  __device__ __attribute__((always_inline)) const Cand* exchange(const Cand& c) {
     Cand* p = part + slot * G;
     if (threadIdx.x == 0) p[member] = c;
     sync();
@@ -86,7 +86,7 @@ struct Team {
   }
 
   // Team-wide argmax (ties to the lowest index); the same value on every thread of the team.
-  __device__ ValIdx argmax(ValIdx x, ValIdx* shv) {
+  __device__ __attribute__((always_inline)) ValIdx argmax(ValIdx x, ValIdx* shv) {
     ValIdx r = wg_argmax<NT>(x, shv);
     if (G == 1) return r;
     const Cand* all = exchange(Cand{r.v, 0.0, r.i, 0});
