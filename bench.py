@@ -55,20 +55,27 @@ def schur_counters(config):
     return rec
 
 
-def cpu_baseline(cfg, n_sample=8192, depth=4):
-    """The oracle (plain FP64 C++, one thread) on a bounded sample of the same workload:
-    N=8192 points, depth 4, same kernel, tolerance, leaf size and 16 right-hand sides; its
-    factor + solve seconds are scaled by the point-count ratio (a lower bound, since the
-    ranks at coarse levels grow with N)."""
+def cpu_baseline(cfg, samples=((4096, 3), (8192, 4))):
+    """The oracle (plain FP64 C++, one thread, as it stands) on bounded samples of the same
+    workload: the same kernel, tolerance, leaf size and right-hand sides at N=4096 (depth 3) and
+    N=8192 (depth 4); factor + direct solve seconds.  The value for the workload's N is the larger
+    sample's time scaled by the point-count ratio (a lower bound: coarse-level ranks keep growing
+    with N); the estimate with the growth exponent measured between the two samples is given
+    beside it.  Both are labelled as extrapolations."""
+    import math
     import oracle
-    c = I.small_case(n_sample, d=cfg["d"], depth=depth, tol=cfg["tol"], kernel=cfg["kernel"], nrhs=cfg["nrhs"],
-                     seed=cfg["seed"])
-    s = oracle.System(c["pts"], c["kernel"], c["tol"], cfg["leaf"], depth)
-    t0 = time.perf_counter()
-    s.factor()
-    s.solve(c["b"])
-    t = time.perf_counter() - t0
-    scale = cfg["n"] / n_sample
+    times = []
+    for n_s, depth in samples:
+        c = I.small_case(n_s, d=cfg["d"], depth=depth, tol=cfg["tol"], kernel=cfg["kernel"], nrhs=cfg["nrhs"],
+                         seed=cfg["seed"])
+        s = oracle.System(c["pts"], c["kernel"], c["tol"], cfg["leaf"], depth)
+        t0 = time.perf_counter()
+        s.factor()
+        s.solve(c["b"])
+        times.append(time.perf_counter() - t0)
+    (n0, _), (n1, d1) = samples
+    alpha = math.log(times[1] / times[0]) / math.log(n1 / n0)
+    scale = (cfg["n"] / n1) ** alpha
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -77,12 +84,43 @@ def cpu_baseline(cfg, n_sample=8192, depth=4):
                 break
     except OSError:
         pass
-    return {"value": round(t * scale, 3), "unit": "s", "cores": 1, "kind": "oracle",
-            "host_cpu": model, "host_nproc": os.cpu_count(), "measured_s": round(t, 3),
-            "extrapolated": f"x{scale:.0f} by point count from the sample (a lower bound: coarse-level ranks grow "
-                            f"with N)",
-            "sample": f"N={n_sample} depth {depth} same kernel/tol/leaf, {cfg['nrhs']} RHS: factor+direct solve "
-                      f"{t:.2f} s on 1 core, x{scale:.0f} (point-count ratio, lower bound)"}
+    lin = cfg["n"] / n1
+    return {"value": round(times[1] * lin, 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_nproc": os.cpu_count(),
+            "measured_s": {f"N={n}": round(t, 3) for (n, _), t in zip(samples, times)},
+            "extrapolated": f"value = N={n1} time x {lin:.0f} (point-count ratio: a lower bound, since cost per point "
+                            f"grows with N); with the growth exponent {alpha:.2f} measured between N={n0} and N={n1} "
+                            f"the estimate is {times[1] * scale:.0f} s; neither is a measurement at N={cfg['n']}",
+            "growth_exponent": round(alpha, 3),
+            "estimate_by_exponent_s": round(times[1] * scale, 1),
+            "sample": f"N={n0} (depth {samples[0][1]}) and N={n1} (depth {d1}), same kernel/tol/leaf, {cfg['nrhs']} RHS: "
+                      f"oracle factor + direct solve on 1 core, {times[0]:.2f} s and {times[1]:.2f} s"}
+
+
+def precision_form(A, name, rtol):
+    """Precision form against the plain FP64 form on the same GPU: the factorization in FP32
+    (compressions and Schur updates in FP32 on MFMA) and in FP64, each the preconditioner of FP64
+    FGMRES with the FP64 NNCA-based product (eps_G 1e-10, certified by the exact product) to
+    relative residual rtol; time to solution = factor + FGMRES."""
+    cfg = I.config(name)
+    pts, b = cfg["pts"], cfg["b"]
+    out = {"workload": f"{name}: N={cfg['n']} uniform [-1,1]^{cfg['d']}, kernel {cfg['kernel'][0]} scale "
+                       f"{cfg['kernel'][1]:.4g} shift {cfg['kernel'][2]}, leaf {cfg['leaf']} depth {cfg['depth']}, "
+                       f"tol {cfg['tol']}, {cfg['nrhs']} RHS to {rtol}", "matvec_tol": 1e-10}
+    for prec in ("fp32", "fp64"):
+        s = A.System(pts, cfg["kernel"], cfg["tol"], cfg["leaf"], cfg["depth"], precision=prec, matvec_tol=1e-10)
+        t0 = time.perf_counter()
+        s.factor()
+        t1 = time.perf_counter()
+        x, its, rr = s.gmres(b, rtol=rtol, restart=30, maxit=200)
+        t2 = time.perf_counter()
+        true = np.linalg.norm(s.matvec(x) - b, axis=0) / np.linalg.norm(b, axis=0)
+        s.close()
+        out[prec] = {"factor_s": round(t1 - t0, 3), "gmres_s": round(t2 - t1, 3), "time_to_rtol_s": round(t2 - t0, 3),
+                     "gmres_iters_max": int(max(its)), "relres_exact_max": float(max(true))}
+        log(f"precision form {name} {prec}: factor {t1 - t0:.2f} s, FGMRES {t2 - t1:.2f} s")
+    out["fp32_speedup"] = round(out["fp64"]["time_to_rtol_s"] / out["fp32"]["time_to_rtol_s"], 3)
+    return out
 
 
 def copy_calibration(mib):
@@ -226,6 +264,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching-form measurement")
+    ap.add_argument("--precision-config", default="c3_reduced",
+                    help="workload of the precision-form comparison (c3 = the full-size 3D workload)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-form measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a fill and five plain device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -355,6 +396,8 @@ def main():
         out["served"] = serve(A)
     if not args.no_batch:
         out["batched"] = batched(A)
+    if not args.no_precision:
+        out["precision_form"] = precision_form(A, args.precision_config, args.rtol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))

@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "dense_wg.hpp"
 #include "system.hpp"
@@ -120,10 +122,11 @@ struct AcaArgs {
   int* piv_c;
   int* rank;             // k_b
   int* flag;             // [3] capacity flag
+  int b0;                // first box of the launch (workgroup x takes box b0 + x); ws starts at its ws_off
 };
 
 __global__ void __launch_bounds__(WG) k_aca(AcaArgs a) {
-  int b = blockIdx.x;
+  int b = a.b0 + blockIdx.x;
   int t0 = a.T_off[b], m = a.T_off[b + 1] - t0;
   int64_t fbase = a.F_off[b];
   int n = (int)(a.F_off[b + 1] - fbase);
@@ -131,7 +134,7 @@ __global__ void __launch_bounds__(WG) k_aca(AcaArgs a) {
   if (m == 0 || n == 0) return;
   const int* T = a.T + t0;
   int kmax = m < n ? m : n;
-  double* U = a.ws + a.ws_off[b];          // kmax x m
+  double* U = a.ws + (a.ws_off[b] - a.ws_off[a.b0]);  // kmax x m
   double* V = U + (size_t)kmax * m;        // kmax x n
   double* r = V + (size_t)kmax * n;        // n  (residual row)
   double* du = r + n;                      // kmax
@@ -436,8 +439,23 @@ void build_system(aifmm_system& s, const double* pts_in, bool on_device) {
     DBuf<int64_t> d_F_off, d_ws_off;
     d_F_off.upload(F_off, st);
     d_ws_off.upload(ws_off, st);
+    // boxes in launches whose U/V workspaces together stay within a budget (half the free
+    // device memory, at most 32 GiB): in 3D a box's column space is every point of its ~189
+    // interaction-list boxes, so the whole level's workspace can exceed the device
+    int64_t budget = (int64_t)32 << 27;  // doubles
+    {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = std::min<int64_t>(budget, (int64_t)(fr / 2 / sizeof(double)));
+    }
+    std::vector<int> chunk{0};
+    int64_t wmax = 0;
+    for (int b = 0; b < nb; ++b) {
+      if (ws_off[b + 1] - ws_off[chunk.back()] > budget && b > chunk.back()) chunk.push_back(b);
+      wmax = std::max(wmax, ws_off[b + 1] - ws_off[chunk.back()]);
+    }
+    chunk.push_back(nb);
     DBuf<double> acaws;
-    acaws.alloc(ws_off[nb]);
+    acaws.alloc(std::max<int64_t>(1, wmax));
     DBuf<unsigned char> cused, rused;
     cused.alloc(std::max<int64_t>(1, F_off[nb]));
     rused.alloc(std::max<int64_t>(1, lv.T_off[nb]));
@@ -445,12 +463,19 @@ void build_system(aifmm_system& s, const double* pts_in, bool on_device) {
     lv.d_piv_c.alloc(std::max(1, lv.T_off[nb]));
     lv.d_k.alloc(nb);
     lv.d_kn.alloc(nb);
-    AcaArgs aa{s.K, s.d_pts.p, d, s.tol, lv.d_T.p, lv.d_T_off.p, lv.d_il_off.p, lv.d_il.p, d_box_off.p,
-               d_F_off.p, d_ws_off.p, acaws.p, cused.p, rused.p, lv.d_piv_r.p, lv.d_piv_c.p, lv.d_k.p, s.d_flag.p};
-    hipLaunchKernelGGL(k_aca, dim3(nb), dim3(WG), 0, st, aa);
-    launch_check("aca");
+    for (size_t c = 0; c + 1 < chunk.size(); ++c) {
+      AcaArgs aa{s.K, s.d_pts.p, d, s.tol, lv.d_T.p, lv.d_T_off.p, lv.d_il_off.p, lv.d_il.p, d_box_off.p,
+                 d_F_off.p, d_ws_off.p, acaws.p, cused.p, rused.p, lv.d_piv_r.p, lv.d_piv_c.p, lv.d_k.p, s.d_flag.p,
+                 chunk[c]};
+      hipLaunchKernelGGL(k_aca, dim3(chunk[c + 1] - chunk[c]), dim3(WG), 0, st, aa);
+      launch_check("aca");
+    }
     lv.knn = lv.d_k.download(st);
     lv.d_knn.upload(lv.knn, st);
+    if (const char* v = getenv("AIFMM_VERBOSE"); v && *v && *v != '0')
+      fprintf(stderr, "[aifmm] build level %d: cross approximation in %zu launch(es), workspace %.2f GB, max rank %d, at %.3f s\n",
+              l, chunk.size() - 1, wmax * 8e-9, *std::max_element(lv.knn.begin(), lv.knn.end()),
+              std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
     lv.koff_nn.assign(nb + 1, 0);
     for (int b = 0; b < nb; ++b) lv.koff_nn[b + 1] = lv.koff_nn[b] + lv.knn[b];
     lv.d_koff_nn.upload(lv.koff_nn, st);
