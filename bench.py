@@ -47,7 +47,7 @@ def schur_counters(config):
     except OSError:
         return None
     s = src.find("constexpr int ST = ")
-    e = src.find("// W = Piv^{-1} [rhs] for the pivot block of every box of a colour")
+    e = src.find("// W = Piv^{-1} [rhs] for every box of a colour")
     if config != "c2" or s < 0 or e < 0:
         return None
     if hashlib.sha256(src[s:e].encode()).hexdigest()[:16] != rec.get("source_sha256_16"):
