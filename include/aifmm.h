@@ -216,9 +216,16 @@ aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t
  * Each system gets a worker thread and a stream of its own (its previous stream is restored by
  * aifmm_server_destroy); requests for a system that arrive while a batch of it runs are merged,
  * FIFO and up to max_cols right-hand sides, into its next batch; batches of different systems
- * run concurrently.  A batch is admitted when its device workspace (about N x cols x 8 bytes x
- * (8 + 60 when rtol > 0)) fits in hbm_budget next to the running ones (0 = 90% of the free
- * device memory at creation; a batch alone is always admitted).  rtol > 0 solves every
+ * run concurrently.  Memory admission charges what the systems hold: each system's right-hand-
+ * side workspaces stay allocated at the size of its largest batch and are charged to hbm_budget
+ * while it is resident (0 = 90% of the free device memory at creation plus what the systems
+ * already hold).  A batch needs the growth of its system's workspaces (estimated as N x cols x
+ * 8 bytes x (8 + 60 when rtol > 0), less what the system holds); it is admitted when that
+ * growth fits in the device's free memory, read at every decision, and in the budget next to
+ * everything charged (a batch with no other batch running may exceed the budget).  When the
+ * growth does not fit in the free memory and no other batch runs, the batch's requests
+ * complete with AIFMM_ERR_BUSY (aifmm_server_wait returns it; x is left unchanged) and may be
+ * submitted again.  rtol > 0 solves every
  * request to that relative residual with flexible GMRES(30) preconditioned by the factors
  * (aifmm_gmres with the system's own operator: its H^2 product when it was built with a
  * matvec tolerance, else the exact product); rtol = 0 uses the direct solve (aifmm_solve).  While served, the systems
@@ -240,7 +247,8 @@ aifmm_status aifmm_server_submit(aifmm_server* srv, int32_t sys, const double* b
  * batch's solve.  A ticket is waited for once, by one thread. */
 aifmm_status aifmm_server_wait(aifmm_server* srv, int64_t ticket, double* x, int64_t ldx, double* latency_s,
                                int32_t* batch_cols, int32_t* iters, double* relres);
-/* Batches run so far, requests they served, and the peak device workspace admitted (bytes). */
+/* Batches run so far, requests they served, and the peak charged device bytes (the systems'
+ * retained right-hand-side workspaces plus admitted growth). */
 aifmm_status aifmm_server_stats(aifmm_server* srv, int64_t* batches, int64_t* requests, size_t* peak_bytes);
 /* Finish the queued requests, stop the workers and restore the systems' streams. */
 void aifmm_server_destroy(aifmm_server* srv);

@@ -5,18 +5,28 @@
 // batch runs are merged into that system's next batch.
 //
 // One worker thread per system, each on a stream of its own, so batches of different systems
-// overlap on the device.  A batch is admitted when its device workspace fits in the memory
-// budget next to the batches already running (and below the device's free memory); it then
-// runs to completion (direct solve, or flexible GMRES to the server's residual target) and
-// every request in it is completed with its own columns of the solution.
+// overlap on the device.  Memory admission charges what the systems actually hold: every
+// system's right-hand-side workspaces (solve buffers, FGMRES and H^2 vectors) stay allocated
+// between batches at the size of its largest batch, so they are charged to the budget while
+// the system is resident and never refunded.  A batch needs only the growth of its system's
+// workspaces beyond what it already holds (estimated from its columns); it is admitted when
+// that growth fits in the device's free memory, read again at every admission decision, and in
+// the budget next to everything charged (a batch with no other batch running may exceed the
+// budget, so a small budget serializes batches instead of starving them).  A batch whose
+// growth does not fit in the free memory even with no other batch running completes its
+// requests with AIFMM_ERR_BUSY.  After a batch its system's charge is set to what it holds.
+// Admitted batches run to completion (direct solve, or flexible GMRES to the server's residual
+// target) and every request in one is completed with its own columns of the solution.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -46,6 +56,8 @@ struct aifmm_server {
   std::vector<aifmm_system*> sys;
   std::vector<hipStream_t> own_streams, old_streams;
   size_t budget = 0, used = 0, peak = 0;
+  std::vector<size_t> held;  // per system: right-hand-side workspace bytes charged to used
+  int inflight = 0;          // batches admitted and not yet finished
   double rtol = 0.0;
   int max_cols = 64;
   std::mutex mu;
@@ -58,10 +70,18 @@ struct aifmm_server {
   int64_t batches = 0, batched_requests = 0;
   std::string err;
 
-  // device bytes a batch of nr columns needs beyond the resident factors
+  // estimated right-hand-side workspace bytes of a system serving batches of nr columns
   size_t need(const aifmm_system& s, int nr) const {
     int restart = rtol > 0 ? 30 : 0;
     return (size_t)s.N * nr * sizeof(double) * (size_t)(8 + 2 * restart);
+  }
+  // the device's free memory now (AIFMM_DEBUG_FREE_BYTES replaces it, to force the busy path
+  // from the host in tests)
+  static size_t free_bytes() {
+    if (const char* v = getenv("AIFMM_DEBUG_FREE_BYTES"); v && *v) return (size_t)strtoull(v, nullptr, 10);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 0;
+    return fr;
   }
 
   void worker(int i) {
@@ -83,9 +103,38 @@ struct aifmm_server {
           take.push_back(pending[i].front());
           pending[i].pop_front();
         }
-        bytes = need(s, cols);
-        cv_mem.wait(lk, [&] { return stop || used == 0 || used + bytes <= budget; });
+        const size_t est = need(s, cols);
+        bytes = est > held[i] ? est - held[i] : 0;  // growth beyond what the system holds
+        bool busy = false;
+        cv_mem.wait(lk, [&] {
+          if (stop) return true;
+          const bool fits_free = bytes == 0 || bytes <= free_bytes();
+          if (fits_free && (inflight == 0 || used + bytes <= budget)) return true;
+          if (inflight == 0) {  // nothing will free memory: the batch cannot run now
+            busy = true;
+            return true;
+          }
+          return false;
+        });
+        if (busy) {
+          auto now = clk::now();
+          for (int64_t t : take) {
+            Request& r = req[t];
+            r.t_done = now;
+            r.batch_cols = cols;
+            r.status = AIFMM_ERR_BUSY;
+            r.done = true;
+            r.b.clear();
+            r.b.shrink_to_fit();
+          }
+          err = "serving: a batch of " + std::to_string(cols) + " columns needs " + std::to_string(bytes) +
+                " more device bytes than are free";
+          lk.unlock();
+          cv_done.notify_all();
+          continue;
+        }
         used += bytes;
+        ++inflight;
         peak = std::max(peak, used);
       }
       // pack the batch
@@ -104,23 +153,31 @@ struct aifmm_server {
       }
       aifmm_status st = AIFMM_OK;
       std::string msg;
-      std::lock_guard<std::mutex> use(s.use);  // other calls on this system wait for the batch
-      try {
-        if (rtol > 0)
-          aifmm::gmres_system(s, B.data(), cols, N, rtol, 30, 500, X.data(), N, its.data(), rel.data(), false, false);
-        else
-          aifmm::solve_system(s, B.data(), cols, N, X.data(), N, false, false);
-      } catch (const aifmm::Error& e) {
-        st = e.st;
-        msg = e.msg;
-      } catch (const std::exception& e) {
-        st = AIFMM_ERR_DEVICE;
-        msg = e.what();
+      size_t now_held = 0;
+      {
+        std::lock_guard<std::mutex> use(s.use);  // other calls on this system wait for the batch
+        try {
+          if (rtol > 0)
+            aifmm::gmres_system(s, B.data(), cols, N, rtol, 30, 500, X.data(), N, its.data(), rel.data(), false, false);
+          else
+            aifmm::solve_system(s, B.data(), cols, N, X.data(), N, false, false);
+        } catch (const aifmm::Error& e) {
+          st = e.st;
+          msg = e.msg;
+        } catch (const std::exception& e) {
+          st = AIFMM_ERR_DEVICE;
+          msg = e.what();
+        }
+        now_held = aifmm::rhs_workspace_bytes(s);
       }
       auto now = clk::now();
       {
         std::lock_guard<std::mutex> lk(mu);
-        used -= bytes;
+        // the reservation is replaced by the system's actual holdings
+        used = used - bytes - held[i] + now_held;
+        held[i] = now_held;
+        peak = std::max(peak, used);
+        --inflight;
         int64_t c = 0;
         for (int64_t t : take) {
           Request& r = req[t];
@@ -157,13 +214,24 @@ aifmm_status aifmm_server_create(aifmm_system* const* systems, int32_t nsys, siz
     for (int j = 0; j < i; ++j)
       if (systems[j] == systems[i]) return AIFMM_ERR_ARG;
   }
-  if (hbm_budget == 0) {  // default: 90% of the device memory free now
+  // what the systems already hold in right-hand-side workspaces is charged from the start
+  size_t held0 = 0;
+  std::vector<size_t> held(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    std::lock_guard<std::mutex> use(systems[i]->use);
+    held[i] = aifmm::rhs_workspace_bytes(*systems[i]);
+    held0 += held[i];
+  }
+  if (hbm_budget == 0) {  // default: 90% of the device memory free now, plus what is already held
     size_t fr = 0, tot = 0;
     if (hipSetDevice(systems[0]->device) != hipSuccess || hipMemGetInfo(&fr, &tot) != hipSuccess) return AIFMM_ERR_DEVICE;
-    hbm_budget = fr / 10 * 9;
+    hbm_budget = fr / 10 * 9 + held0;
   }
   auto* srv = new aifmm_server();
   srv->sys.assign(systems, systems + nsys);
+  srv->held = held;
+  srv->used = held0;
+  srv->peak = held0;
   srv->budget = hbm_budget;
   srv->rtol = rtol;
   srv->max_cols = max_cols;
@@ -222,11 +290,12 @@ aifmm_status aifmm_server_wait(aifmm_server* srv, int64_t ticket, double* x, int
   srv->cv_done.wait(lk, [&] { return rp->done; });
   Request& r = *rp;
   aifmm_status st = r.status;
-  for (int64_t c = 0; c < r.nrhs; ++c) std::memcpy(x + c * ldx, r.x.data() + c * N, sizeof(double) * N);
+  if ((int64_t)r.x.size() == N * r.nrhs)  // a request refused as busy carries no solution
+    for (int64_t c = 0; c < r.nrhs; ++c) std::memcpy(x + c * ldx, r.x.data() + c * N, sizeof(double) * N);
   if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
   if (batch_cols) *batch_cols = r.batch_cols;
-  if (iters) std::copy(r.iters.begin(), r.iters.end(), iters);
-  if (relres) std::copy(r.relres.begin(), r.relres.end(), relres);
+  if (iters && (int64_t)r.iters.size() == r.nrhs) std::copy(r.iters.begin(), r.iters.end(), iters);
+  if (relres && (int64_t)r.relres.size() == r.nrhs) std::copy(r.relres.begin(), r.relres.end(), relres);
   srv->req.erase(ticket);
   return st;
 }

@@ -338,6 +338,26 @@ struct aifmm_system {
 };
 
 namespace aifmm {
+template <class T>
+inline size_t buf_bytes(const DBuf<T>& b) { return b.p ? b.n * sizeof(T) : 0; }
+template <class T>
+inline size_t buf_bytes(const std::vector<DBuf<T>>& v) {
+  size_t t = 0;
+  for (auto& b : v) t += buf_bytes(b);
+  return t;
+}
+// Device bytes a system holds in the workspaces that grow with the number of right-hand sides
+// (solve buffers, FGMRES vectors, H^2 work vectors, and those of its operator system); they
+// are kept between calls, so a served system keeps them while it is resident.
+inline size_t rhs_workspace_bytes(const aifmm_system& s) {
+  size_t t = buf_bytes(s.sc.R) + buf_bytes(s.sc.X) + buf_bytes(s.sc.W) + buf_bytes(s.sc.G);
+  const GmresCache& g = s.gc;
+  t += buf_bytes(g.bin) + buf_bytes(g.bt) + buf_bytes(g.xt) + buf_bytes(g.r) + buf_bytes(g.w) + buf_bytes(g.part) +
+       buf_bytes(g.dalpha) + buf_bytes(g.xo) + buf_bytes(g.rx) + buf_bytes(g.cx) + buf_bytes(g.V) + buf_bytes(g.Z);
+  t += buf_bytes(s.hc.q) + buf_bytes(s.hc.loc);
+  if (s.op) t += rhs_workspace_bytes(*s.op);
+  return t;
+}
 // build.hip
 void build_system(aifmm_system& s, const double* pts_host_or_dev, bool on_device);
 // factor.hip

@@ -106,8 +106,9 @@ def test_server_argument_errors():
 
 
 def test_admission_by_memory_budget():
-    """With a budget smaller than any batch, batches are admitted one at a time (a batch alone
-    is always admitted): the peak admitted workspace is one batch's, and results are unchanged."""
+    """With a budget smaller than any batch, batches are admitted one at a time (a batch with no
+    other running is admitted): results are unchanged, and the peak charge is what the systems
+    hold in retained workspaces plus at most one batch's growth."""
     sy = _systems()
     srv = A.Server([s for s, _ in sy], hbm_budget=1, rtol=0.0, max_cols=8)
     try:
@@ -117,8 +118,35 @@ def test_admission_by_memory_budget():
             x, _, bc, _, _ = srv.wait(t)
             np.testing.assert_array_equal(x, sy[sys][0].solve(b))
         st = srv.stats()
-        one_batch_max = max(s.N for s, _ in sy) * 8 * 8 * 8   # N x cols x 8 bytes x 8 vectors, cols <= 8
-        print("peak admitted bytes", st["peak_bytes"], "bound", one_batch_max)
-        assert 0 < st["peak_bytes"] <= one_batch_max
+        # retained solve workspaces of both systems at 8 columns, plus one batch's estimate
+        bound = sum(s.N for s, _ in sy) * 8 * 8 * 8 * 4 + max(s.N for s, _ in sy) * 8 * 8 * 8
+        print("peak charged bytes", st["peak_bytes"], "bound", bound)
+        assert 0 < st["peak_bytes"] <= bound
+    finally:
+        srv.close()
+
+
+def test_busy_when_device_memory_is_short(monkeypatch):
+    """A batch whose workspace growth does not fit in the device's free memory, with no other
+    batch running, completes its requests with AIFMM_ERR_BUSY instead of failing (the free
+    memory figure is forced to zero from the host); submitted again with memory available,
+    the same request is served and equals the direct solve."""
+    sy = _systems()
+    s0 = sy[0][0]
+    b = _rhs(s0.N, 4, 77)
+    monkeypatch.setenv("AIFMM_DEBUG_FREE_BYTES", "0")
+    srv = A.Server([s0], rtol=0.0, max_cols=8)
+    try:
+        t = srv.submit(0, b)
+        with pytest.raises(A.AifmmError) as ei:
+            srv.wait(t)
+        assert ei.value.status == 8
+    finally:
+        srv.close()
+    monkeypatch.delenv("AIFMM_DEBUG_FREE_BYTES")
+    srv = A.Server([s0], rtol=0.0, max_cols=8)
+    try:
+        x, _, _, _, _ = srv.wait(srv.submit(0, b))
+        np.testing.assert_array_equal(x, s0.solve(b))
     finally:
         srv.close()
