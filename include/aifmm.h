@@ -202,13 +202,17 @@ const char* aifmm_last_error(const aifmm_system* s);
 /* Free every resource of the system; NULL is accepted. */
 void aifmm_destroy(aifmm_system* s);
 
-/* Batching: factor n independent built systems concurrently (each as aifmm_factor).  nstreams
- * worker threads, each with a HIP stream of its own, take the systems in order, so the
- * factorizations of different systems overlap on the device; each system's own stream is
- * restored afterwards.  Every system is attempted; returns AIFMM_OK or the first failing
- * status (aifmm_last_error(system) tells each one's error).  AIFMM_ERR_ARG for NULL, n <= 0,
- * nstreams <= 0 or a system listed twice; AIFMM_ERR_STATE if one is already factored. */
-aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t nstreams);
+/* Batching: factor n independent built systems (each as aifmm_factor would, with the same
+ * results) in lockstep groups of up to `group` systems of one device and precision, taken in
+ * order.  A group runs on its first system's stream: step t handles level L_s - t of every
+ * system s of the group, and each launch of the step (a round of compressions of the
+ * efficient elimination, Sec. 3.3, its basis changes, the elimination phases of a colour,
+ * Sec. 3.2) carries the work of all of the group's systems, so many small systems fill the
+ * device together.  Groups run one after another; each system's own stream is restored.
+ * A failure fails its whole group (every system of it reports the error through
+ * aifmm_last_error); returns AIFMM_OK or the first failing status.  AIFMM_ERR_ARG for NULL,
+ * n <= 0, group <= 0 or a system listed twice; AIFMM_ERR_STATE if one is already factored. */
+aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t group);
 
 /* ---- Serving: resident factorizations, continuously batched solve requests ----------------
  * The factorization does not depend on the right-hand side (Sec. 3.4: the solve reuses the

@@ -236,10 +236,11 @@ class System:
         return dict(zip(STAT_NAMES, out[: len(STAT_NAMES)]))
 
 
-def factor_batch(systems, nstreams=4):
-    """Factor independent systems concurrently (aifmm_factor_batch)."""
+def factor_batch(systems, group=256):
+    """Factor independent systems in lockstep groups of up to `group` systems
+    (aifmm_factor_batch): each launch carries the work of every system of a group."""
     arr = (ctypes.c_void_p * len(systems))(*[s._h for s in systems])
-    st = lib().aifmm_factor_batch(arr, len(systems), int(nstreams))
+    st = lib().aifmm_factor_batch(arr, len(systems), int(group))
     if st != 0:
         bad = [i for i, s in enumerate(systems) if lib().aifmm_last_error(s._h)]
         raise AifmmError(st, f"batched factorization failed (systems with errors: {bad[:8]})")

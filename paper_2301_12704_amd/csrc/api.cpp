@@ -1,6 +1,7 @@
 // C ABI of the library (declarations and contracts in include/aifmm.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <atomic>
 #include <cmath>
@@ -145,41 +146,59 @@ aifmm_status aifmm_factor(aifmm_system* s) {
 // its own, take the systems in order; each system runs on its worker's stream and gets its
 // previous stream back.  Returns the first failing status (every system is still attempted;
 // aifmm_last_error of a system tells its own error).
-aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t nstreams) {
-  if (!systems || n <= 0 || nstreams <= 0) return fail(nullptr, AIFMM_ERR_ARG, "bad systems / n / nstreams");
+aifmm_status aifmm_factor_batch(aifmm_system* const* systems, int32_t n, int32_t group) {
+  if (!systems || n <= 0 || group <= 0) return fail(nullptr, AIFMM_ERR_ARG, "bad systems / n / group");
   for (int i = 0; i < n; ++i) {
     if (!systems[i]) return fail(nullptr, AIFMM_ERR_ARG, "a system is NULL");
     if (systems[i]->factored) return fail(systems[i], AIFMM_ERR_STATE, "already factored");
     for (int j = 0; j < i; ++j)
       if (systems[j] == systems[i]) return fail(nullptr, AIFMM_ERR_ARG, "a system is listed twice");
   }
-  int nw = std::min<int>(nstreams, n);
-  std::atomic<int> next{0};
-  std::vector<aifmm_status> st(n, AIFMM_OK);
-  std::vector<std::thread> pool;
-  std::atomic<int> stream_fail{0};
-  for (int w = 0; w < nw; ++w)
-    pool.emplace_back([&] {
-      hipStream_t own = nullptr;
-      if (hipSetDevice(systems[0]->device) != hipSuccess ||
-          hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) {
-        stream_fail = 1;
-        return;
-      }
-      for (int i; (i = next.fetch_add(1)) < n;) {
-        aifmm_system* s = systems[i];
-        hipStream_t old = s->stream;
-        s->stream = own;
-        st[i] = aifmm_factor(s);
-        s->stream = old;
-      }
-      (void)hipStreamDestroy(own);
+  // systems of one device and precision, in the given order, in groups of up to `group`
+  std::vector<std::vector<aifmm_system*>> groups;
+  {
+    std::vector<bool> taken(n, false);
+    for (int i = 0; i < n; ++i) {
+      if (taken[i]) continue;
+      std::vector<aifmm_system*> g;
+      for (int j = i; j < n && (int)g.size() < group; ++j)
+        if (!taken[j] && systems[j]->device == systems[i]->device && systems[j]->prec == systems[i]->prec) {
+          g.push_back(systems[j]);
+          taken[j] = true;
+        }
+      groups.push_back(std::move(g));
+    }
+  }
+  aifmm_status first = AIFMM_OK;
+  for (auto& g : groups) {
+    // every system of the group is locked (in address order) and runs on the first one's stream
+    std::vector<aifmm_system*> order(g);
+    std::sort(order.begin(), order.end());
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (aifmm_system* s : order) locks.emplace_back(s->use);
+    std::vector<hipStream_t> old;
+    for (aifmm_system* s : g) old.push_back(s->stream);
+    for (aifmm_system* s : g) s->stream = g[0]->stream;
+    aifmm_status st = guarded(g[0], [&] {
+      AIFMM_HIP(hipSetDevice(g[0]->device));
+      aifmm::factor_systems(g);
     });
-  for (auto& t : pool) t.join();
-  if (stream_fail) return fail(nullptr, AIFMM_ERR_DEVICE, "stream creation failed");
-  for (int i = 0; i < n; ++i)
-    if (st[i] != AIFMM_OK) return st[i];
-  return AIFMM_OK;
+    for (size_t q = 0; q < g.size(); ++q) g[q]->stream = old[q];
+    for (aifmm_system* s : g) {
+      if (st != AIFMM_OK) {
+        if (s != g[0]) fail(s, st, g[0]->err);
+        continue;
+      }
+      aifmm_status sp = guarded(s, [&] {
+        AIFMM_HIP(hipSetDevice(s->device));
+        aifmm::prepare_solve(*s);
+      });
+      if (sp == AIFMM_OK) s->factored = true;
+      else if (first == AIFMM_OK) first = sp;
+    }
+    if (st != AIFMM_OK && first == AIFMM_OK) first = st;
+  }
+  return first;
 }
 
 aifmm_status aifmm_solve(aifmm_system* s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx) {

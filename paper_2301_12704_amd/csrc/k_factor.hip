@@ -29,9 +29,11 @@ struct RoundEntry {
   int i, kind, partner;
   int e_ij, e_ji;  // M2L slot entries: (i, partner) and (partner, i)
   int f_ij, f_ji;  // fill slot entries: (i, partner) and (partner, i)
+  int sys, tidx;   // the system (index into the launch's level tables) and its trace record
 };
 struct XformEntry {
   int x, skip, pair, side;
+  int sys;
 };
 
 struct LevelPtrs {
@@ -69,7 +71,16 @@ struct LevelPtrs {
   const int64_t* fpiv_off;
   int* trace;        // per compression: r1 r2 r3 r4 k_i' k_j'
   double* trace_ratio;  // per compression: 4 x (kept, next) decision ratios
+  int* flag;         // the system's flags ([0] singular, [1] box, [2] level)
+  double tol;        // the system's eps_A
 };
+
+// Every factorization kernel reads the level tables of the system its work item belongs to:
+// PP holds one LevelPtrs per system of the launch (one system: PP[0]), and box lists come with
+// bsys, the system of each listed box (nullptr: every box of system 0).
+__device__ inline const LevelPtrs& sys_ptrs(const LevelPtrs* __restrict__ PP, const int* __restrict__ bsys, int item) {
+  return PP[bsys ? bsys[item] : 0];
+}
 
 // ------------------------------------------------------------------------------------------
 // compression of one pending pair per workgroup (CT threads)
@@ -79,10 +90,9 @@ constexpr int CT = 512;
 // R: arithmetic of the compression (double, or float in the precision form); the block store
 // stays FP64 and operands are converted on load / store.
 template <class RT>
-__global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* __restrict__ ent, int nent, double* ws,
-                                                 int64_t wsz, int cap, double tol, int64_t tbase, int G,
-                                                 unsigned* ctr, Cand* part, int* abort, int lds_cols,
-                                                 double* pubbuf) {
+__global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ PP, const RoundEntry* __restrict__ ent,
+                                                 int nent, double* ws, int64_t wsz, int cap, int G, unsigned* ctr,
+                                                 Cand* part, int* abort, int lds_cols, double* pubbuf) {
   int e = blockIdx.x / G;
   if (e >= nent) return;
   Team<CT> T;
@@ -103,8 +113,10 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   else
     C.init(0, 1, ctr + e, part + (size_t)e * 4 * G, abort);
   RoundEntry R = ent[e];
-  int* tr = P.trace + (tbase + e) * 6;
-  double* trr = P.trace_ratio + (tbase + e) * 8;
+  const LevelPtrs& P = PP[R.sys];
+  const double tol = P.tol;
+  int* tr = P.trace + (size_t)R.tidx * 6;
+  double* trr = P.trace_ratio + (size_t)R.tidx * 8;
   __shared__ ValIdx shv[CT / WAVE + 1];
   extern __shared__ double shm[];  // one reflector (cap), pivot positions (2 x 2cap ints), own norms (2cap)
   RT* vsh = (RT*)shm;
@@ -335,9 +347,12 @@ __global__ void __launch_bounds__(CT) k_compress(LevelPtrs P, const RoundEntry* 
   }
 }
 
-__global__ void k_commit(LevelPtrs P, const XformEntry* __restrict__ xe, int nx) {
+__global__ void k_commit(const LevelPtrs* __restrict__ PP, const XformEntry* __restrict__ xe, int nx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < nx) P.k[xe[t].x] = P.kn[xe[t].x];
+  if (t < nx) {
+    const LevelPtrs& P = PP[xe[t].sys];
+    P.k[xe[t].x] = P.kn[xe[t].x];
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -357,8 +372,9 @@ __device__ inline int64_t near_entry(const LevelPtrs& P, int p, int q) {
 // [A[X_b, O_c] | E | I] (into the colour's workspace, ld C + n) and the coupled column blocks
 // A[O_r, x_b] of box b (GS workgroups per box).
 constexpr int GS = 16;  // workgroups per box of k_elim_gather
-__global__ void __launch_bounds__(WG) k_elim_gather(LevelPtrs P, const int* __restrict__ boxes, double* rws,
-                                                   int64_t rstride) {
+__global__ void __launch_bounds__(WG) k_elim_gather(const LevelPtrs* __restrict__ PP, const int* __restrict__ bsys,
+                                                   const int* __restrict__ boxes, double* rws, int64_t rstride) {
+  const LevelPtrs& P = sys_ptrs(PP, bsys, blockIdx.x);
   int b = boxes[blockIdx.x];
   int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
   int n = P.n[b], k = P.k[b], m = n + k;
@@ -438,9 +454,12 @@ constexpr int LU_NB = 16;
 // Pivot-block LU of every box of a colour, G workgroups per box (a team, co-resident through a
 // cooperative launch when G > 1; ctr, status: one barrier counter, zero at launch, and one
 // status word per box).
-__global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restrict__ boxes, int* flag,
-                                                int64_t dyn_bytes, int G, unsigned* ctr, int* status, int* abort) {
+__global__ void __launch_bounds__(WG) k_elim_lu(const LevelPtrs* __restrict__ PP, const int* __restrict__ bsys,
+                                                const int* __restrict__ boxes, int64_t dyn_bytes, int G, unsigned* ctr,
+                                                int* status, int* abort) {
   const int e = blockIdx.x / G;
+  const LevelPtrs& P = sys_ptrs(PP, bsys, e);
+  int* flag = P.flag;
   int b = boxes[e];
   int m = P.n[b] + P.k[b];
   Team<WG> T;
@@ -454,7 +473,7 @@ __global__ void __launch_bounds__(WG) k_elim_lu(LevelPtrs P, const int* __restri
   int* pm = (int*)dyn;
   int* piv = P.fpiv + P.fpiv_off[b];
   const bool lp = (int64_t)m * (LU_NB + 1) * (int64_t)sizeof(double) <= dyn_bytes;
-  int st = t_lu_blocked<LU_NB>(T, m, P.fslab + P.fLU[b], m, piv, shv, sh, ipv, lp ? dyn : nullptr, status + e);
+  int st = t_lu_blocked<LU_NB>(T, m, P.fslab + P.fLU[b], m, piv, shv, sh, ipv, dyn, lp, status + e);
   __syncthreads();
   if (T.member != 0) return;
   if (st) {
@@ -506,10 +525,11 @@ template <bool F32> struct MfmaT { using T = double; using T4 = dbl4; };
 template <> struct MfmaT<true> { using T = float; using T4 = flt4; };
 template <bool F32>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5)))
-k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int tiles_c) {
+k_elim_schur(const LevelPtrs* __restrict__ PP, const int* __restrict__ bsys, const int* __restrict__ boxes, int tiles_c) {
   using TT = typename MfmaT<F32>::T;
   using TT4 = typename MfmaT<F32>::T4;
-  if (flag[0]) return;
+  const LevelPtrs& P = sys_ptrs(PP, bsys, blockIdx.y);
+  if (P.flag[0]) return;
   int b = boxes[blockIdx.y];
   int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
   int n = P.n[b];
@@ -628,9 +648,10 @@ k_elim_schur(LevelPtrs P, const int* __restrict__ boxes, const int* flag, int ti
 // chunks of 16 through LDS with the next chunk prefetched into registers, XCD-aware tile order;
 // every element is the ascending fused multiply-add chain over k from zero.
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5)))
-k_elim_wgemm(LevelPtrs P, const int* __restrict__ boxes, const int* flag, const double* __restrict__ pws,
-             int64_t pstride, const double* __restrict__ rws, int64_t rstride) {
-  if (flag[0]) return;
+k_elim_wgemm(const LevelPtrs* __restrict__ PP, const int* __restrict__ bsys, const int* __restrict__ boxes,
+             const double* __restrict__ pws, int64_t pstride, const double* __restrict__ rws, int64_t rstride) {
+  const LevelPtrs& P = sys_ptrs(PP, bsys, blockIdx.y);
+  if (P.flag[0]) return;
   const int b = boxes[blockIdx.y];
   const int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
   const int n = P.n[b], m = n + P.k[b];
@@ -728,9 +749,10 @@ k_elim_wgemm(LevelPtrs P, const int* __restrict__ boxes, const int* flag, const 
 // fenced before its later blocks read them; waves share nothing, so the workgroup never
 // synchronises.  W = Piv^{-1} [rhs] is then one product (k_elim_wgemm).
 constexpr int TW = 4;  // waves per workgroup
-__global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int* __restrict__ boxes, const int* flag,
-                                                         double* pws, int64_t pstride) {
-  if (flag[0]) return;
+__global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(const LevelPtrs* __restrict__ PP, const int* __restrict__ bsys,
+                                                         const int* __restrict__ boxes, double* pws, int64_t pstride) {
+  const LevelPtrs& P = sys_ptrs(PP, bsys, blockIdx.y);
+  if (P.flag[0]) return;
   const int b = boxes[blockIdx.y];
   const int n = P.n[b], k = P.k[b], m = n + k;
   const int ldw = m;  // the identity's columns
@@ -880,9 +902,10 @@ __global__ void __launch_bounds__(TW * WAVE) k_elim_trsm(LevelPtrs P, const int*
 // holds the wave's block (p + rot) mod PMB).  PMB (blocks per wave) sets the register footprint:
 // the host takes the shape with the fewest registers that holds the level's largest block.
 template <int NW, int PMB>
-__global__ void __launch_bounds__(NW * WAVE) k_elim_pinv(LevelPtrs P, const int* __restrict__ boxes, const int* flag,
-                                                         double* pws, int64_t pstride) {
-  if (flag[0]) return;
+__global__ void __launch_bounds__(NW * WAVE) k_elim_pinv(const LevelPtrs* __restrict__ PP, const int* __restrict__ bsys,
+                                                         const int* __restrict__ boxes, double* pws, int64_t pstride) {
+  const LevelPtrs& P = sys_ptrs(PP, bsys, blockIdx.y);
+  if (P.flag[0]) return;
   const int b = boxes[blockIdx.y];
   const int m = P.n[b] + P.k[b];
   const int c0 = blockIdx.x * 16;
@@ -1137,7 +1160,7 @@ __device__ inline void wave_xform_slab(int M, int N, int K, const TA* A, int64_t
 // per wave, through wave_xform_slab.  Work items (entry, block, slab) are spread over all
 // waves of the grid; wstride is each wave's workspace (doubles).
 template <class RT>
-__global__ void __launch_bounds__(WG) k_xform(LevelPtrs P, const XformEntry* __restrict__ xe, int nx, const double* ws,
+__global__ void __launch_bounds__(WG) k_xform(const LevelPtrs* __restrict__ PP, const XformEntry* __restrict__ xe, int nx, const double* ws,
                                               int64_t wsz, int cap, int maxblk, int nslab, int cols_side,
                                               double* scratch, int64_t wstride) {
   const int64_t gw = (int64_t)blockIdx.x * (WG / WAVE) + threadIdx.x / WAVE;
@@ -1150,6 +1173,7 @@ __global__ void __launch_bounds__(WG) k_xform(LevelPtrs P, const XformEntry* __r
     const int64_t task = item / nslab;
     const int t = (int)(task / maxblk), q = (int)(task - (int64_t)t * maxblk);
     const XformEntry X = xe[t];
+    const LevelPtrs& P = PP[X.sys];
     const int x = X.x;
     const int nil = P.il_off[x + 1] - P.il_off[x];
     if (q > nil || (q == nil && P.l == 2)) continue;
@@ -1192,8 +1216,10 @@ __global__ void __launch_bounds__(WG) k_xform(LevelPtrs P, const XformEntry* __r
 }
 
 // New rows Z_b: (Z_b, cols(q)) = W_z[:, cols(q)] for every coupled column group.
-__global__ void __launch_bounds__(WG) k_elim_zrow(LevelPtrs P, const int* __restrict__ boxes, const int* flag) {
-  if (flag[0]) return;
+__global__ void __launch_bounds__(WG) k_elim_zrow(const LevelPtrs* __restrict__ PP, const int* __restrict__ bsys,
+                                                 const int* __restrict__ boxes) {
+  const LevelPtrs& P = sys_ptrs(PP, bsys, blockIdx.x);
+  if (P.flag[0]) return;
   int b = boxes[blockIdx.x];
   int g0 = P.grp_off[b], G = P.grp_off[b + 1] - g0;
   int n = P.n[b], k = P.k[b];
@@ -1864,9 +1890,15 @@ static bool verbose() {
   return v && *v && *v != '0';
 }
 
-static void factor_levels(aifmm_system& s);
+static void factor_levels_multi(const std::vector<aifmm_system*>& S);
 
-void factor_system(aifmm_system& s) {
+// Factorization of one or more systems.  Several systems (same device and precision) are
+// factored in lockstep: step t handles level L_s - t of every system s that still has one, and
+// every launch of the step (a round of compressions, its basis changes and commits, the
+// elimination phases of a colour) carries the work of all of those systems at once, each work
+// item reading its own system's level tables.  Every element of every system is computed by
+// the same operations as when the system is factored alone, so the results are the same.
+void factor_systems(const std::vector<aifmm_system*>& S) {
   // buffers released during the factorization are freed after its last synchronization
   struct Defer {
     std::vector<void*> ptrs;
@@ -1878,40 +1910,174 @@ void factor_system(aifmm_system& s) {
       (void)hipStreamSynchronize(st);
       for (void* p : ptrs) (void)hipFree(p);
     }
-  } defer(s.stream);
-  factor_levels(s);
+  } defer(S[0]->stream);
+  factor_levels_multi(S);
 }
 
-static void factor_levels(aifmm_system& s) {
+void factor_system(aifmm_system& s) { factor_systems({&s}); }
+
+static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
   auto t0 = std::chrono::steady_clock::now();
   auto since = [&](std::chrono::steady_clock::time_point a) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
   };
-  hipStream_t st = s.stream;
-  int L = s.L;
-  s.stats.schur_flops = s.stats.schur_bytes = s.stats.trsm_flops = s.stats.lu_flops = 0;
-  s.stats.schur_kernel_s = s.stats.compress_kernel_s = s.stats.schur_launches = s.stats.compress_launches = 0;
-  s.stats.trsm_kernel_s = s.stats.trsm_launches = 0;
-  s.stats.lvl.assign(L + 1, LevelStats{});
-  s.trace.clear();
-  s.sc = SolveCache{};
-  s.d_flag.zero(st);
-  for (int l = L; l >= 2; --l) {
-    auto tl = std::chrono::steady_clock::now();
-    activate_level(s, l);
-    if (verbose()) fprintf(stderr, "[aifmm] level %d activated in %.3f s\n", l, since(tl));
-    LevelDev& lv = s.lev[l];
-    LevelPlan& Pl = s.plan[l];
-    if (l < L) s.lev[l + 1].slab.release();
-    LevelPtrs P = ptrs(s, l);
-    int cap = lv.nmax;
-    int64_t wsz = 22 * (int64_t)cap * cap + 10 * cap + 16;
-    int maxcol = 0;
-    for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) maxcol = std::max(maxcol, Pl.col_off[c + 1] - Pl.col_off[c]);
+  hipStream_t st = S[0]->stream;
+  const bool f32 = S[0]->prec == AIFMM_FP32;
+  int Lmax = 0;
+  for (aifmm_system* sp : S) {
+    aifmm_system& s = *sp;
+    if (s.stream != st || s.prec != S[0]->prec || s.device != S[0]->device)
+      throw Error{AIFMM_ERR_ARG, "systems factored together need one stream, device and precision"};
+    s.stats.schur_flops = s.stats.schur_bytes = s.stats.trsm_flops = s.stats.lu_flops = 0;
+    s.stats.schur_kernel_s = s.stats.compress_kernel_s = s.stats.schur_launches = s.stats.compress_launches = 0;
+    s.stats.trsm_kernel_s = s.stats.trsm_launches = 0;
+    s.stats.lvl.assign(s.L + 1, LevelStats{});
+    s.trace.clear();
+    s.sc = SolveCache{};
+    s.d_flag.zero(st);
+    Lmax = std::max(Lmax, s.L);
+  }
+  const bool multi = S.size() > 1;
+  // per system of a step: its level, its own schedule lists and its trace buffers
+  struct Run {
+    aifmm_system* s = nullptr;
+    int l = 0;
+    std::vector<RoundEntry> rent;
+    std::vector<XformEntry> xent;
+    std::vector<int64_t> r_off, x_off;  // per (colour, round)
+    std::vector<int> nrounds;           // per colour
+    std::vector<int64_t> rix0;          // per colour: index of its first round in r_off
+    DBuf<int> d_tr;
+    DBuf<double> d_trr;
+    std::chrono::steady_clock::time_point tl;
+  };
+  for (int step = 0; step + 2 <= Lmax; ++step) {
+    std::vector<Run> runs;
+    for (aifmm_system* sp : S)
+      if (sp->L - step >= 2) {
+        runs.emplace_back();
+        runs.back().s = sp;
+        runs.back().l = sp->L - step;
+      }
+    const int na = (int)runs.size();
+    std::vector<LevelPtrs> hP(na);
+    int cap = 1, maxblk = 1, kPmax = 1, maxmc = 1, Cmax = 0, Rmax = 0, ncol = 0;
+    int64_t tstride = 2;
+    for (int q = 0; q < na; ++q) {
+      Run& R = runs[q];
+      aifmm_system& s = *R.s;
+      const int l = R.l;
+      R.tl = std::chrono::steady_clock::now();
+      activate_level(s, l);
+      if (verbose() && !multi) fprintf(stderr, "[aifmm] level %d activated in %.3f s\n", l, since(R.tl));
+      LevelDev& lv = s.lev[l];
+      LevelPlan& Pl = s.plan[l];
+      if (l < s.L) s.lev[l + 1].slab.release();
+      cap = std::max(cap, lv.nmax);
+      for (int b = 0; b < lv.nb; ++b) {
+        maxblk = std::max(maxblk, Pl.il_off[b + 1] - Pl.il_off[b] + 1);
+        tstride = std::max(tstride, (int64_t)2 * lv.n[b] * (lv.Ccap[b] + lv.n[b]));
+        maxmc = std::max(maxmc, 2 * lv.n[b]);
+        if (l > 2) kPmax = std::max(kPmax, s.lev[l - 1].knn[b >> s.d]);
+      }
+      Cmax = std::max(Cmax, lv.Cmax);
+      Rmax = std::max(Rmax, lv.Rmax);
+      ncol = std::max(ncol, (int)Pl.col_off.size() - 1);
+      lv.d_order.upload(Pl.order, st);
+      // the system's static round and transform lists (pair: the entry's index in its round)
+      for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) {
+        R.nrounds.push_back((int)Pl.rounds[c].size());
+        R.rix0.push_back((int64_t)R.r_off.size());
+        for (auto& round : Pl.rounds[c]) {
+          R.r_off.push_back((int64_t)R.rent.size());
+          R.x_off.push_back((int64_t)R.xent.size());
+          int pi = 0;
+          for (auto& op : round) {
+            RoundEntry E;
+            E.i = op.i;
+            E.kind = op.kind;
+            E.partner = op.partner;
+            E.e_ij = find_in(Pl.il_off, Pl.il, op.i, op.partner);
+            E.e_ji = find_in(Pl.il_off, Pl.il, op.partner, op.i);
+            E.f_ij = find_in(Pl.p2_off, Pl.p2, op.i, op.partner);
+            E.f_ji = find_in(Pl.p2_off, Pl.p2, op.partner, op.i);
+            if (E.e_ij < 0 || E.e_ji < 0 || E.f_ij < 0 || E.f_ji < 0)
+              throw Error{AIFMM_ERR_STATE, "inconsistent compression schedule"};
+            E.sys = q;
+            E.tidx = (int)R.rent.size();
+            R.rent.push_back(E);
+            R.xent.push_back({op.i, op.partner, pi, 0, q});
+            if (op.kind == 0) R.xent.push_back({op.partner, op.i, pi, 1, q});
+            ++pi;
+          }
+        }
+      }
+      R.r_off.push_back((int64_t)R.rent.size());
+      R.x_off.push_back((int64_t)R.xent.size());
+      R.d_tr.alloc(R.rent.size() * 6 + 6);
+      R.d_trr.alloc(R.rent.size() * 8 + 8);
+      R.d_tr.zero(st);
+      R.d_trr.zero(st);
+      hP[q] = ptrs(s, l);
+      hP[q].trace = R.d_tr.p;
+      hP[q].trace_ratio = R.d_trr.p;
+      hP[q].flag = s.d_flag.p;
+      hP[q].tol = s.tol;
+    }
+    DBuf<LevelPtrs> dPP;
+    dPP.upload(hP, st);
+    const LevelPtrs* PP = dPP.p;
+    // the step's merged lists: per colour and round the entries of every system (an entry's
+    // pair index becomes its index in the merged round), per colour the boxes of every system
+    std::vector<RoundEntry> mrent;
+    std::vector<XformEntry> mxent;
+    std::vector<int64_t> mr_off, mx_off, mb_off;
+    std::vector<int> mnr(ncol, 0), mbox, mbsys;
+    int maxcol = 1;
+    for (int c = 0; c < ncol; ++c) {
+      for (auto& R : runs)
+        if (c < (int)R.nrounds.size()) mnr[c] = std::max(mnr[c], R.nrounds[c]);
+      for (int r = 0; r < mnr[c]; ++r) {
+        mr_off.push_back((int64_t)mrent.size());
+        mx_off.push_back((int64_t)mxent.size());
+        for (auto& R : runs) {
+          if (c >= (int)R.nrounds.size() || r >= R.nrounds[c]) continue;
+          const int64_t rix = R.rix0[c] + r;
+          const int base_pair = (int)(mrent.size() - mr_off.back());
+          for (int64_t e = R.r_off[rix]; e < R.r_off[rix + 1]; ++e) mrent.push_back(R.rent[e]);
+          for (int64_t x = R.x_off[rix]; x < R.x_off[rix + 1]; ++x) {
+            XformEntry X = R.xent[x];
+            X.pair += base_pair;
+            mxent.push_back(X);
+          }
+        }
+      }
+      mb_off.push_back((int64_t)mbox.size());
+      int nbc = 0;
+      for (int q = 0; q < na; ++q) {
+        LevelPlan& Pl = runs[q].s->plan[runs[q].l];
+        if (c + 1 >= (int)Pl.col_off.size()) continue;
+        for (int i = Pl.col_off[c]; i < Pl.col_off[c + 1]; ++i) {
+          mbox.push_back(Pl.order[i]);
+          mbsys.push_back(q);
+          ++nbc;
+        }
+      }
+      maxcol = std::max(maxcol, nbc);
+    }
+    mr_off.push_back((int64_t)mrent.size());
+    mx_off.push_back((int64_t)mxent.size());
+    mb_off.push_back((int64_t)mbox.size());
+    DBuf<RoundEntry> d_rent;
+    DBuf<XformEntry> d_xent;
+    DBuf<int> d_mbox, d_mbsys;
+    d_rent.upload(mrent, st);
+    d_xent.upload(mxent, st);
+    d_mbox.upload(mbox, st);
+    d_mbsys.upload(mbsys, st);
+    const int* bsys_all = multi ? d_mbsys.p : nullptr;
+    const int64_t wsz = 22 * (int64_t)cap * cap + 10 * cap + 16;
     const int XG = 1024;
-    int kPmax = 1;
-    if (l > 2)
-      for (int b = 0; b < lv.nb; ++b) kPmax = std::max(kPmax, s.lev[l - 1].knn[b >> s.d]);
     // basis changes: 16-wide slabs, each wave with a workspace of 16 x maxdim
     const int maxdim = std::max(cap, kPmax);
     const int nslab = cdiv(maxdim, 16);
@@ -1922,12 +2088,6 @@ static void factor_levels(aifmm_system& s) {
     // the right-hand sides of the pivot-block solves of one colour (a W-sized block per box),
     // the forward results and inverses of the pivot blocks (two m x m blocks per box), and the
     // LDS of the row permutation of each pivot-block LU
-    int64_t tstride = 2;
-    int maxmc = 1;
-    for (int b = 0; b < lv.nb; ++b) {
-      tstride = std::max(tstride, (int64_t)2 * lv.n[b] * (lv.Ccap[b] + lv.n[b]));
-      maxmc = std::max(maxmc, 2 * lv.n[b]);
-    }
     DBuf<double> tws, pws;
     tws.alloc((size_t)maxcol * tstride);
     const int64_t pstride = (int64_t)2 * maxmc * maxmc;
@@ -1951,60 +2111,9 @@ static void factor_levels(aifmm_system& s) {
     DBuf<int> d_lust;
     d_luctr.alloc(std::max(1, maxcol));
     d_lust.alloc(std::max(1, maxcol));
-    lv.d_order.upload(Pl.order, st);
-    DBuf<int>& d_order = lv.d_order;
-    // static round and transform lists of the whole level
-    std::vector<RoundEntry> rent;
-    std::vector<XformEntry> xent;
-    std::vector<int64_t> r_off, x_off;  // per (colour, round)
-    std::vector<int> nrounds;
-    int maxblk = 1;
-    for (int b = 0; b < lv.nb; ++b) maxblk = std::max(maxblk, Pl.il_off[b + 1] - Pl.il_off[b] + 1);
-    for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) {
-      nrounds.push_back((int)Pl.rounds[c].size());
-      for (auto& round : Pl.rounds[c]) {
-        r_off.push_back((int64_t)rent.size());
-        x_off.push_back((int64_t)xent.size());
-        int pi = 0;
-        for (auto& op : round) {
-          RoundEntry E;
-          E.i = op.i;
-          E.kind = op.kind;
-          E.partner = op.partner;
-          E.e_ij = find_in(Pl.il_off, Pl.il, op.i, op.partner);
-          E.e_ji = find_in(Pl.il_off, Pl.il, op.partner, op.i);
-          E.f_ij = find_in(Pl.p2_off, Pl.p2, op.i, op.partner);
-          E.f_ji = find_in(Pl.p2_off, Pl.p2, op.partner, op.i);
-          if (E.e_ij < 0 || E.e_ji < 0 || E.f_ij < 0 || E.f_ji < 0)
-            throw Error{AIFMM_ERR_STATE, "inconsistent compression schedule"};
-          rent.push_back(E);
-          xent.push_back({op.i, op.partner, pi, 0});
-          if (op.kind == 0) xent.push_back({op.partner, op.i, pi, 1});
-          ++pi;
-        }
-      }
-    }
-    r_off.push_back((int64_t)rent.size());
-    x_off.push_back((int64_t)xent.size());
-    DBuf<RoundEntry> d_rent;
-    DBuf<XformEntry> d_xent;
-    d_rent.upload(rent, st);
-    d_xent.upload(xent, st);
-    DBuf<int> d_tr;
-    DBuf<double> d_trr;
-    d_tr.alloc(rent.size() * 6 + 6);
-    d_trr.alloc(rent.size() * 8 + 8);
-    d_tr.zero(st);
-    d_trr.zero(st);
-    P.trace = d_tr.p;
-    P.trace_ratio = d_trr.p;
-    size_t rix = 0;
     // compressions of a small round are spread over teams of G workgroups each (cooperative
-    // launch, so every team is co-resident); pivot positions and a reflector live in LDS
-    // compression teams: a round with few pending compressions spreads each over a team of G
-    // co-resident workgroups (cooperative launch); when a team's share of the pivoted-QR columns
+    // launch, so every team is co-resident); when a team's share of the pivoted-QR columns
     // fits, the columns live in LDS (lds_cols per member), otherwise in the workspace
-    const bool f32 = s.prec == AIFMM_FP32;
     const size_t rs = f32 ? sizeof(float) : sizeof(double);
     const void* kcomp = f32 ? (const void*)k_compress<float> : (const void*)k_compress<double>;
     // reflector, pivot positions, own column norms
@@ -2067,14 +2176,12 @@ static void factor_levels(aifmm_system& s) {
     d_abort.alloc(1);
     d_part.zero(st);
     if (debug_abort()) {  // the abort flag raised before the first launch: every team barrier of
-      const int one = 1;  // the level falls through at once and the level reports the failure
+      const int one = 1;  // the step falls through at once and the step reports the failure
       AIFMM_HIP(hipMemcpyAsync(d_abort.p, &one, sizeof(int), hipMemcpyHostToDevice, st));
       AIFMM_HIP(hipStreamSynchronize(st));
     } else {
       d_abort.zero(st);
     }
-    hipEvent_t ev[4];
-    for (auto& e : ev) AIFMM_HIP(hipEventCreate(&e));
     std::vector<std::pair<hipEvent_t, hipEvent_t>> sch_ev, cmp_ev, trs_ev;
     auto ev_pair = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
       hipEvent_t a, b;
@@ -2083,37 +2190,36 @@ static void factor_levels(aifmm_system& s) {
       v.push_back({a, b});
       return v.back();
     };
-    for (size_t c = 0; c + 1 < Pl.col_off.size(); ++c) {
-      for (int r = 0; r < nrounds[c]; ++r, ++rix) {
-        int ne = (int)(r_off[rix + 1] - r_off[rix]);
-        int nx = (int)(x_off[rix + 1] - x_off[rix]);
-        const RoundEntry* er = d_rent.p + r_off[rix];
-        const XformEntry* ex = d_xent.p + x_off[rix];
+    size_t rix = 0;
+    for (int c = 0; c < ncol; ++c) {
+      for (int r = 0; r < mnr[c]; ++r, ++rix) {
+        int ne = (int)(mr_off[rix + 1] - mr_off[rix]);
+        int nx = (int)(mx_off[rix + 1] - mx_off[rix]);
+        if (ne == 0) continue;
+        const RoundEntry* er = d_rent.p + mr_off[rix];
+        const XformEntry* ex = d_xent.p + mx_off[rix];
         auto ce = ev_pair(cmp_ev);
         AIFMM_HIP(hipEventRecord(ce.first, st));
         int G = 1, lcols = 0;
         size_t shm = base;
         team_shape(ne, G, lcols, shm);
-        if (verbose()) {
-          ++team_hist[{G, lcols > 0 ? 1 : 0}];
-        }
+        if (verbose()) ++team_hist[{G, lcols > 0 ? 1 : 0}];
         if (G == 1) {
           if (f32)
-            hipLaunchKernelGGL(k_compress<float>, dim3(ne), dim3(CT), shm, st, P, er, ne, ws.p, wsz, cap, s.tol,
-                               r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p, lcols, d_pub.p);
+            hipLaunchKernelGGL(k_compress<float>, dim3(ne), dim3(CT), shm, st, PP, er, ne, ws.p, wsz, cap, 1, d_ctr.p,
+                               d_part.p, d_abort.p, lcols, d_pub.p);
           else
-            hipLaunchKernelGGL(k_compress<double>, dim3(ne), dim3(CT), shm, st, P, er, ne, ws.p, wsz, cap, s.tol,
-                               r_off[rix], 1, d_ctr.p, d_part.p, d_abort.p, lcols, d_pub.p);
+            hipLaunchKernelGGL(k_compress<double>, dim3(ne), dim3(CT), shm, st, PP, er, ne, ws.p, wsz, cap, 1, d_ctr.p,
+                               d_part.p, d_abort.p, lcols, d_pub.p);
         } else {
           AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * 3 * ne, st));
-          int64_t tb = r_off[rix];
-          double tol = s.tol;
           Cand* partp = d_part.p;
           unsigned* ctrp = d_ctr.p;
           int* abortp = d_abort.p;
           double* wsp = ws.p;
           double* pubp = d_pub.p;
-          void* args[] = {&P, (void*)&er, &ne, &wsp, &wsz, &cap, &tol, &tb, &G, &ctrp, &partp, &abortp, &lcols, &pubp};
+          int64_t wszv = wsz;
+          void* args[] = {(void*)&PP, (void*)&er, &ne, &wsp, &wszv, &cap, &G, &ctrp, &partp, &abortp, &lcols, &pubp};
           AIFMM_HIP(hipLaunchCooperativeKernel(kcomp, dim3(ne * G), dim3(CT), args, shm, st));
         }
         AIFMM_HIP(hipEventRecord(ce.second, st));
@@ -2121,37 +2227,38 @@ static void factor_levels(aifmm_system& s) {
           int64_t items = (int64_t)nx * maxblk * nslab;
           int g64 = (int)std::min<int64_t>(XG, std::max<int64_t>(1, cdiv(items, WG / WAVE)));
           if (f32) {
-            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
+            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
                                scratch.p, wstride);
-            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
+            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
                                scratch.p, wstride);
           } else {
-            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
+            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
                                scratch.p, wstride);
-            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, P, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
+            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
                                scratch.p, wstride);
           }
         }
-        hipLaunchKernelGGL(k_commit, dim3(cdiv(nx, WG)), dim3(WG), 0, st, P, ex, nx);
+        hipLaunchKernelGGL(k_commit, dim3(cdiv(nx, WG)), dim3(WG), 0, st, PP, ex, nx);
       }
-      int nbox = Pl.col_off[c + 1] - Pl.col_off[c];
-      const int* boxes = d_order.p + Pl.col_off[c];
-      hipLaunchKernelGGL(k_elim_gather, dim3(nbox, GS), dim3(WG), 0, st, P, boxes, tws.p, tstride);
+      int nbox = (int)(mb_off[c + 1] - mb_off[c]);
+      if (nbox == 0) continue;
+      const int* boxes = d_mbox.p + mb_off[c];
+      const int* bsys = bsys_all ? bsys_all + mb_off[c] : nullptr;
+      hipLaunchKernelGGL(k_elim_gather, dim3(nbox, GS), dim3(WG), 0, st, PP, bsys, boxes, tws.p, tstride);
       {
         // teams of up to 16 co-resident workgroups per pivot block
         const int Gl = (lu_coop > 0) ? std::max(1, std::min(16, lu_coop / std::max(1, nbox))) : 1;
         int64_t dynb = lu_panels_off() ? 0 : (int64_t)lu_shm;  // bytes the panels may use
-        int* flagp = s.d_flag.p;
         unsigned* lctr = d_luctr.p;
         int* lst = d_lust.p;
         int* abortp = d_abort.p;
         if (Gl > 1) {
           AIFMM_HIP(hipMemsetAsync(d_luctr.p, 0, sizeof(unsigned) * nbox, st));
           int Glv = Gl;
-          void* args[] = {&P, (void*)&boxes, &flagp, &dynb, &Glv, &lctr, &lst, &abortp};
+          void* args[] = {(void*)&PP, (void*)&bsys, (void*)&boxes, &dynb, &Glv, &lctr, &lst, &abortp};
           AIFMM_HIP(hipLaunchCooperativeKernel((const void*)k_elim_lu, dim3(nbox * Gl), dim3(WG), args, lu_shm, st));
         } else {
-          hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), lu_shm, st, P, boxes, flagp, dynb, 1, lctr, lst, abortp);
+          hipLaunchKernelGGL(k_elim_lu, dim3(nbox), dim3(WG), lu_shm, st, PP, bsys, boxes, dynb, 1, lctr, lst, abortp);
         }
       }
       auto te = ev_pair(trs_ev);
@@ -2162,14 +2269,13 @@ static void factor_levels(aifmm_system& s) {
         const int nblk = cdiv(maxmc, 16);
         int nw = 0, pb = 0;
         pinv_shape(maxmc, nblk * nbox, nw, pb);
-        int* flagp = s.d_flag.p;
         const dim3 pg(nblk, nbox);
 #define AIFMM_PINV(NW_, PB_)                                                                            \
-  else if (nw == NW_ && pb == PB_) hipLaunchKernelGGL((k_elim_pinv<NW_, PB_>), pg, dim3(NW_ * WAVE), 0, st, P, \
-                                                      boxes, flagp, pws.p, pstride);
+  else if (nw == NW_ && pb == PB_) hipLaunchKernelGGL((k_elim_pinv<NW_, PB_>), pg, dim3(NW_ * WAVE), 0, st, PP, \
+                                                      bsys, boxes, pws.p, pstride);
         if (nw == 0)
-          hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(maxmc, 16 * TW), nbox), dim3(TW * WAVE), 0, st, P, boxes,
-                             s.d_flag.p, pws.p, pstride);
+          hipLaunchKernelGGL(k_elim_trsm, dim3(cdiv(maxmc, 16 * TW), nbox), dim3(TW * WAVE), 0, st, PP, bsys, boxes,
+                             pws.p, pstride);
         AIFMM_PINV(1, 16) AIFMM_PINV(2, 16) AIFMM_PINV(4, 16) AIFMM_PINV(8, 16)
         AIFMM_PINV(2, 8) AIFMM_PINV(4, 8) AIFMM_PINV(8, 8)
         AIFMM_PINV(4, 4) AIFMM_PINV(8, 4) AIFMM_PINV(16, 4)
@@ -2177,124 +2283,130 @@ static void factor_levels(aifmm_system& s) {
         else throw Error{AIFMM_ERR_STATE, "no pivot-inverse kernel of the chosen shape"};
       }
       {
-        const int wt = (int)(cdiv(maxmc, ST) * (int64_t)cdiv(lv.Cmax, ST));
-        hipLaunchKernelGGL(k_elim_wgemm, dim3(8 * cdiv(wt, 8), nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, pws.p,
-                           pstride, tws.p, tstride);
+        const int wt = (int)(cdiv(maxmc, ST) * (int64_t)cdiv(Cmax, ST));
+        hipLaunchKernelGGL(k_elim_wgemm, dim3(8 * cdiv(wt, 8), nbox), dim3(WG), 0, st, PP, bsys, boxes, pws.p, pstride,
+                           tws.p, tstride);
       }
       AIFMM_HIP(hipEventRecord(te.second, st));
-      int tiles_c = cdiv(lv.Cmax, ST), tiles_r = cdiv(std::max(1, lv.Rmax), ST);
+      int tiles_c = cdiv(Cmax, ST), tiles_r = cdiv(std::max(1, Rmax), ST);
       int tiles_x = 8 * cdiv((int64_t)tiles_r * tiles_c, 8);
       auto se = ev_pair(sch_ev);
       AIFMM_HIP(hipEventRecord(se.first, st));
-      if (s.prec == AIFMM_FP32)
-        hipLaunchKernelGGL(k_elim_schur<true>, dim3(tiles_x, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
+      if (f32)
+        hipLaunchKernelGGL(k_elim_schur<true>, dim3(tiles_x, nbox), dim3(WG), 0, st, PP, bsys, boxes, tiles_c);
       else
-        hipLaunchKernelGGL(k_elim_schur<false>, dim3(tiles_x, nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p, tiles_c);
+        hipLaunchKernelGGL(k_elim_schur<false>, dim3(tiles_x, nbox), dim3(WG), 0, st, PP, bsys, boxes, tiles_c);
       AIFMM_HIP(hipEventRecord(se.second, st));
-      hipLaunchKernelGGL(k_elim_zrow, dim3(nbox), dim3(WG), 0, st, P, boxes, s.d_flag.p);
+      hipLaunchKernelGGL(k_elim_zrow, dim3(nbox), dim3(WG), 0, st, PP, bsys, boxes);
       launch_check("elimination");
     }
-    lv.kfin = lv.d_k.download(st);
+    for (auto& R : runs) R.s->lev[R.l].kfin = R.s->lev[R.l].d_k.download(st);
     AIFMM_HIP(hipStreamSynchronize(st));
-    if (d_abort.download(st)[0])
-      throw Error{AIFMM_ERR_DEVICE, "level " + std::to_string(l) + ": a team barrier timed out"};
-    double sch_before = s.stats.schur_kernel_s;
-    LevelStats& ls = s.stats.lvl[l];
-    for (auto& pr : sch_ev) {
-      float ms = 0;
-      AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-      s.stats.schur_kernel_s += ms * 1e-3;
-      ls.schur_s += ms * 1e-3;
-      s.stats.schur_launches += 1;
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
+    if (d_abort.download(st)[0]) {
+      std::string what = multi ? "level " + std::to_string(step) + " from the leaves"
+                               : "level " + std::to_string(runs[0].l);
+      throw Error{AIFMM_ERR_DEVICE, what + ": a team barrier timed out"};
     }
-    for (auto& pr : trs_ev) {
-      float ms = 0;
-      AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-      s.stats.trsm_kernel_s += ms * 1e-3;
-      ls.trsm_s += ms * 1e-3;
-      s.stats.trsm_launches += 1;
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
-    }
-    for (auto& pr : cmp_ev) {
-      float ms = 0;
-      AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-      s.stats.compress_kernel_s += ms * 1e-3;
-      ls.compress_s += ms * 1e-3;
-      s.stats.compress_launches += 1;
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    if (verbose()) {
-      fprintf(stderr, "[aifmm] level %d factored in %.3f s (%zu compressions), cap %d, coop %d/%d; rounds by team:", l,
-              since(tl), rent.size(), cap, coop_g, coop_l);
-      for (auto& kv : team_hist) fprintf(stderr, " G%d%s:%d", kv.first.first, kv.first.second ? "L" : "", kv.second);
-      fprintf(stderr, "\n");
-    }
-    const size_t trace0 = s.trace.size();
-    {
-      std::vector<int> tr = d_tr.download(st, rent.size() * 6);
-      std::vector<double> trr = d_trr.download(st, rent.size() * 8);
-      for (size_t q = 0; q < rent.size(); ++q) {
-        TraceRec t;
-        t.level = l;
-        t.i = rent[q].i;
-        t.kind = rent[q].kind;
-        t.partner = rent[q].partner;
-        for (int a = 0; a < 6; ++a) t.r[a] = tr[q * 6 + a];
-        for (int a = 0; a < 8; ++a) t.ratio[a] = trr[q * 8 + a];
-        s.trace.push_back(t);
+    // kernel times of the step's launches (shared by the systems of a merged step)
+    double t_sch = 0, t_trs = 0, t_cmp = 0;
+    auto drain = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& acc) {
+      for (auto& pr : v) {
+        float ms = 0;
+        AIFMM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        acc += ms * 1e-3;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+    };
+    drain(sch_ev, t_sch);
+    drain(trs_ev, t_trs);
+    drain(cmp_ev, t_cmp);
+    for (int q = 0; q < na; ++q) {
+      Run& R = runs[q];
+      aifmm_system& s = *R.s;
+      const int l = R.l;
+      LevelDev& lv = s.lev[l];
+      double sch_before = s.stats.schur_kernel_s;
+      LevelStats& ls = s.stats.lvl[l];
+      s.stats.schur_kernel_s += t_sch;
+      ls.schur_s += t_sch;
+      s.stats.schur_launches += (double)sch_ev.size();
+      s.stats.trsm_kernel_s += t_trs;
+      ls.trsm_s += t_trs;
+      s.stats.trsm_launches += (double)trs_ev.size();
+      s.stats.compress_kernel_s += t_cmp;
+      ls.compress_s += t_cmp;
+      s.stats.compress_launches += (double)cmp_ev.size();
+      if (verbose()) {
+        fprintf(stderr, "[aifmm] level %d factored in %.3f s (%zu compressions), cap %d, coop %d/%d; rounds by team:", l,
+                since(R.tl), R.rent.size(), cap, coop_g, coop_l);
+        for (auto& kv : team_hist) fprintf(stderr, " G%d%s:%d", kv.first.first, kv.first.second ? "L" : "", kv.second);
+        if (multi) fprintf(stderr, " (merged with %d systems)", na);
+        fprintf(stderr, "\n");
+      }
+      const size_t trace0 = s.trace.size();
+      {
+        std::vector<int> tr = R.d_tr.download(st, R.rent.size() * 6);
+        std::vector<double> trr = R.d_trr.download(st, R.rent.size() * 8);
+        for (size_t e = 0; e < R.rent.size(); ++e) {
+          TraceRec t;
+          t.level = l;
+          t.i = R.rent[e].i;
+          t.kind = R.rent[e].kind;
+          t.partner = R.rent[e].partner;
+          for (int a = 0; a < 6; ++a) t.r[a] = tr[e * 6 + a];
+          for (int a = 0; a < 8; ++a) t.ratio[a] = trr[e * 8 + a];
+          s.trace.push_back(t);
+        }
+      }
+      std::vector<int> flag = s.d_flag.download(st);
+      if (flag[0])
+        throw Error{AIFMM_ERR_SINGULAR, "singular self-block at level " + std::to_string(flag[2]) + " box " + std::to_string(flag[1])};
+      for (int b = 0; b < lv.nb; ++b)
+        if (lv.kfin[b] > lv.n[b]) throw Error{AIFMM_ERR_CAPACITY, "rank above box size"};
+      count_compress(s, l, R.r_off, trace0);
+      {
+        double f0 = s.stats.schur_flops;
+        count_flops(s, l);
+        if (verbose())
+          fprintf(stderr, "[aifmm] level %d Schur %.3e flop in %.4f s (%.2f TFLOP/s)\n", l, s.stats.schur_flops - f0,
+                  s.stats.schur_kernel_s - sch_before,
+                  (s.stats.schur_flops - f0) / std::max(1e-12, s.stats.schur_kernel_s - sch_before) * 1e-12);
+      }
+      lv.xoff.assign(lv.nb + 1, 0);
+      lv.koff.assign(lv.nb + 1, 0);
+      for (int b = 0; b < lv.nb; ++b) {
+        lv.xoff[b + 1] = lv.xoff[b] + lv.n[b];
+        lv.koff[b + 1] = lv.koff[b] + lv.kfin[b];
+      }
+      ls.factor_s = since(R.tl);
+      if (l == 2) {
+        // top-level multipole system
+        LevelDev& l2 = s.lev[2];
+        s.Ktop = (int)l2.koff[l2.nb];
+        int K = std::max(1, s.Ktop);
+        s.d_top.alloc((size_t)K * K);
+        s.d_top_piv.alloc(K);
+        std::vector<int> koff32(l2.nb);
+        for (int b = 0; b < l2.nb; ++b) koff32[b] = (int)l2.koff[b];
+        DBuf<int> d_koff;
+        d_koff.upload(koff32, st);
+        if (s.Ktop > 0) {
+          hipLaunchKernelGGL(k_gather_top, dim3(l2.nb, l2.nb), dim3(WG), 0, st, l2.nb, l2.d_k.p, l2.d_n.p, d_koff.p,
+                             l2.d_nbr_off.p, l2.d_nbr.p, l2.d_near_slot.p, l2.d_il_off.p, l2.d_il.p, l2.d_il_slot.p,
+                             l2.slab.p, s.d_top.p, s.Ktop);
+          top_lu(s.d_top.p, s.Ktop, s.d_top_piv.p, s.d_flag.p, st);
+          launch_check("top");
+        }
+        std::vector<int> tflag = s.d_flag.download(st);
+        if (verbose()) fprintf(stderr, "[aifmm] top system K=%d factored at %.3f s\n", s.Ktop, since(t0));
+        if (tflag[0]) throw Error{AIFMM_ERR_SINGULAR, "singular level-2 multipole system"};
+        l2.slab.release();
       }
     }
-    std::vector<int> flag = s.d_flag.download(st);
-    if (flag[0]) throw Error{AIFMM_ERR_SINGULAR, "singular self-block at level " + std::to_string(flag[2]) + " box " + std::to_string(flag[1])};
-    for (int b = 0; b < lv.nb; ++b)
-      if (lv.kfin[b] > lv.n[b]) throw Error{AIFMM_ERR_CAPACITY, "rank above box size"};
-    count_compress(s, l, r_off, trace0);
-    {
-      double f0 = s.stats.schur_flops;
-      count_flops(s, l);
-      if (verbose())
-        fprintf(stderr, "[aifmm] level %d Schur %.3e flop in %.4f s (%.2f TFLOP/s)\n", l, s.stats.schur_flops - f0,
-                s.stats.schur_kernel_s - sch_before,
-                (s.stats.schur_flops - f0) / std::max(1e-12, s.stats.schur_kernel_s - sch_before) * 1e-12);
-    }
-    lv.xoff.assign(lv.nb + 1, 0);
-    lv.koff.assign(lv.nb + 1, 0);
-    for (int b = 0; b < lv.nb; ++b) {
-      lv.xoff[b + 1] = lv.xoff[b] + lv.n[b];
-      lv.koff[b + 1] = lv.koff[b] + lv.kfin[b];
-    }
-    ls.factor_s = since(tl);
-  }
-  // top-level multipole system
-  {
-    LevelDev& l2 = s.lev[2];
-    s.Ktop = (int)l2.koff[l2.nb];
-    int K = std::max(1, s.Ktop);
-    s.d_top.alloc((size_t)K * K);
-    s.d_top_piv.alloc(K);
-    std::vector<int> koff32(l2.nb);
-    for (int b = 0; b < l2.nb; ++b) koff32[b] = (int)l2.koff[b];
-    DBuf<int> d_koff;
-    d_koff.upload(koff32, st);
-    if (s.Ktop > 0) {
-      hipLaunchKernelGGL(k_gather_top, dim3(l2.nb, l2.nb), dim3(WG), 0, st, l2.nb, l2.d_k.p, l2.d_n.p, d_koff.p,
-                         l2.d_nbr_off.p, l2.d_nbr.p, l2.d_near_slot.p, l2.d_il_off.p, l2.d_il.p, l2.d_il_slot.p,
-                         l2.slab.p, s.d_top.p, s.Ktop);
-      top_lu(s.d_top.p, s.Ktop, s.d_top_piv.p, s.d_flag.p, st);
-      launch_check("top");
-    }
-    std::vector<int> flag = s.d_flag.download(st);
-    if (verbose()) fprintf(stderr, "[aifmm] top system K=%d factored at %.3f s\n", s.Ktop, since(t0));
-    if (flag[0]) throw Error{AIFMM_ERR_SINGULAR, "singular level-2 multipole system"};
-    l2.slab.release();
   }
   AIFMM_HIP(hipStreamSynchronize(st));
-  s.stats.factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (aifmm_system* sp : S) sp->stats.factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 }  // namespace aifmm

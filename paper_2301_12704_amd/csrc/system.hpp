@@ -362,6 +362,8 @@ inline size_t rhs_workspace_bytes(const aifmm_system& s) {
 void build_system(aifmm_system& s, const double* pts_host_or_dev, bool on_device);
 // factor.hip
 void factor_system(aifmm_system& s);
+// several systems of one device, precision and stream, in lockstep (k_factor.hip)
+void factor_systems(const std::vector<aifmm_system*>& S);
 // solve.hip
 void solve_system(aifmm_system& s, const double* b, int64_t nrhs, int64_t ldb, double* x, int64_t ldx,
                   bool b_dev, bool x_dev);

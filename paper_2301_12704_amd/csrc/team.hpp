@@ -638,7 +638,7 @@ __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, 
 // workgroups.  Every element receives its updates a = fma(-l, u, a) one at a time in ascending
 // step order and every pivot is chosen from the fully updated column, so the factors are bit
 // for bit those of the textbook elimination.  Member 0 factors each panel (in its LDS panel
-// buffer pl, m (NB + 1) doubles, when given) and leaves the panel and its pivots in A and
+// buffer pl, m (NB + 1) doubles, when use_pl) and leaves the panel and its pivots in A and
 // ipiv; after a team barrier every member applies the panel's row swaps, in step order, to
 // its share of the other columns and solves their U12 rows with the panel's unit-lower L11;
 // after another the members take the 64 x 64 tiles of the trailing update in turn (FP64
@@ -648,7 +648,7 @@ __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, 
 // the team; the return value is the same on every member.
 template <int NB>
 __device__ inline int t_lu_blocked(Team<WG>& T, int m, double* A, int lda, int* ipiv, ValIdx* shv, double* sh,
-                                   int* ipv, double* pl, int* status) {
+                                   int* ipv, double* pl, bool use_pl, int* status) {
   constexpr int NT = WG;
   const int tid = threadIdx.x;
   double* prow = sh;
@@ -658,7 +658,7 @@ __device__ inline int t_lu_blocked(Team<WG>& T, int m, double* A, int lda, int* 
   for (int k0 = 0; k0 < m; k0 += NB) {
     const int nb = min(NB, m - k0);
     if (T.member == 0) {
-      const bool lp = pl != nullptr;
+      const bool lp = use_pl;  // a flag, not a null test of the LDS pointer
       auto el = [&](int i, int j) -> double* {
         return lp ? pl + (size_t)(i - k0) * (NB + 1) + j : A + (size_t)i * lda + k0 + j;
       };

@@ -1,5 +1,6 @@
-"""Batching form: independent systems factored concurrently on separate streams
-(aifmm_factor_batch) give exactly the factors of one-at-a-time factorization: ranks and
+"""Batching form: independent systems of different sizes and depths factored in lockstep
+(aifmm_factor_batch: every launch carries the work of all systems) give exactly the factors of
+one-at-a-time factorization: compression traces (ranks and decision ratios), rank tables and
 solutions are bit-identical, and the FP64 ones match the oracle (ranks bit-exact, solution
 within 1e-8) on a sampled system."""
 import numpy as np
@@ -30,8 +31,13 @@ def test_batch_equals_sequential(prec, tol):
     for s in seq:
         s.factor()
     bat = [A.System(p, kern, tol, 64, 0, precision=prec) for p, _ in data]
-    A.factor_batch(bat, nstreams=4)
+    A.factor_batch(bat)
+    assert len({s.L for s in bat}) > 1, "the batch should mix depths"
     for (p, b), s1, s2 in zip(data, seq, bat):
+        r1, q1 = s1.trace()
+        r2, q2 = s2.trace()
+        np.testing.assert_array_equal(r1, r2)
+        np.testing.assert_array_equal(q1, q2)
         for l in range(2, s1.L + 1):
             np.testing.assert_array_equal(s1.ranks(l), s2.ranks(l))
         np.testing.assert_array_equal(s1.solve(b), s2.solve(b))
