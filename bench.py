@@ -217,16 +217,18 @@ def serve(A, n_req=200, rate=2000.0, seed=5999):
     return out
 
 
-def batched(A, count=16):
+def batched(A, count=16, group=0):
     """Batching form: independent 2D systems with N log-uniform in [2048, 32768] (every
     (256/count)-th of the 256-system draw), A_ij = exp(-r/0.5) + 0.05 delta_ij, 64 points per
-    leaf, factored in lockstep (aifmm_factor_batch: each launch carries the work of every
-    system) in FP64 at 1e-8 and FP32 at 1e-5; the plain comparison factors the same systems one
-    at a time (aifmm_factor), and the batched rank tables must equal the sequential ones."""
+    leaf, factored in lockstep groups of `group` systems (aifmm_factor_batch: each launch
+    carries the work of every system of a group) in FP64 at 1e-8 and FP32 at 1e-5; the plain
+    comparison factors the same systems one at a time (aifmm_factor), and the batched rank
+    tables must equal the sequential ones."""
     sizes = I.batch_sizes(256)[::256 // count]
     kern = ("exp", 0.5, 0.05)
+    group = group if group > 0 else len(sizes)
     out = {"systems": len(sizes), "n_min": int(min(sizes)), "n_max": int(max(sizes)), "points": int(sum(sizes)),
-           "mode": "lockstep, one group"}
+           "mode": f"lockstep groups of up to {group} systems"}
     for prec, tol in (("fp64", 1e-8), ("fp32", 1e-5)):
         def build():
             res = []
@@ -236,7 +238,7 @@ def batched(A, count=16):
             return res
         systems = build()
         t0 = time.perf_counter()
-        A.factor_batch(systems, group=len(systems))
+        A.factor_batch(systems, group=group)
         tb = time.perf_counter() - t0
         ranks_b = [[s.ranks(l).tolist() for l in range(2, s.L + 1)] for s in systems]
         for s in systems:
@@ -267,6 +269,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching-form measurement")
+    ap.add_argument("--batch-count", type=int, default=16, choices=[16, 32, 64, 128, 256],
+                    help="systems of the batching form (every 256/count-th of the 256-system draw)")
+    ap.add_argument("--batch-group", type=int, default=0,
+                    help="systems per lockstep group of the batching form (0: all in one group)")
     ap.add_argument("--precision-config", default="c3_reduced",
                     help="workload of the precision-form comparison (c3 = the full-size 3D workload)")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form measurement")
@@ -398,7 +404,7 @@ def main():
     if not args.no_serve:
         out["served"] = serve(A)
     if not args.no_batch:
-        out["batched"] = batched(A)
+        out["batched"] = batched(A, args.batch_count, args.batch_group)
     if not args.no_precision:
         out["precision_form"] = precision_form(A, args.precision_config, args.rtol)
     if not args.no_cpu_baseline:
