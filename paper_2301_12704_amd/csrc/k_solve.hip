@@ -12,71 +12,88 @@
 
 namespace aifmm {
 
-constexpr int SOLVE_KC = 64;  // rows of B staged per wave and chunk
-
-// Y tile = A tile B over column block [cb, cb + NRB): the four waves of the workgroup split
-// K in quarters (each stages its rows of B in LDS), lane = row; the partial sums are added in
-// wave order, so the result does not depend on scheduling.
-template <int NRB, int MODE>
-__global__ void __launch_bounds__(WG) k_rows_gemm(const STask* __restrict__ tasks, const double* __restrict__ fslab,
+// Y tile = A tile B for one task (at most 64 rows of A, K columns; B is K x nr, row-major)
+// on FP64 MFMA 16x16x4: the task's rows are the A operand (row tiles of 16; for a fixed step
+// the four lanes of a row read 32 contiguous bytes of it), 16 right-hand-side columns the B
+// operand.  Row tile rt runs on the waves w with w mod RT = rt (RT row tiles), which split the
+// K range; their partial tiles are added in wave order, so the result does not depend on
+// scheduling.  The summation order differs from the oracle's (the solve is not on the
+// rank-deciding path).  NT: 16-column tiles per pass over the right-hand sides.
+typedef double sdbl4 __attribute__((ext_vector_type(4)));
+template <int NT, int MODE>
+__global__ void __launch_bounds__(WG) k_rows_mfma(const STask* __restrict__ tasks, const double* __restrict__ fslab,
                                                  const double* __restrict__ Bbuf, double* Y0buf, double* Y1buf,
                                                  const double* __restrict__ Yinit, int nr) {
-  __shared__ double sB[4 * SOLVE_KC * NRB];
-  STask T = tasks[blockIdx.x];
-  int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  int Kq = (T.K + 3) / 4;
-  int k0 = w * Kq, k1 = min(T.K, k0 + Kq);
-  bool rv = lane < T.rows;
-  const double* A = fslab + T.a + (size_t)(rv ? lane : 0) * T.lda;
+  __shared__ double red[WG / WAVE][NT][4][WAVE];
+  const STask T = tasks[blockIdx.x];
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
+  const int RT = max(1, (T.rows + 15) / 16);
+  const int KP = (WG / WAVE) / RT;
+  const int rt = w % RT, kp = w / RT;
+  const bool active = kp < KP;
+  const int ksteps = (T.K + 3) / 4;
+  const int per = (ksteps + KP - 1) / KP;
+  const int s0 = kp * per, s1 = min(ksteps, s0 + per);
+  const int row = rt * 16 + fr;
+  const bool rok = active && row < T.rows;
+  const double* Ar = fslab + T.a + (size_t)(rok ? row : 0) * T.lda;
   const double* B = Bbuf + (size_t)T.b * nr;
-  double* sw = sB + w * SOLVE_KC * NRB;
-  for (int cb = 0; cb < nr; cb += NRB) {
-    double acc[NRB];
+  constexpr int KU = 8;  // MFMA steps whose operands are loaded together
+  for (int cb = 0; cb < nr; cb += 16 * NT) {
+    sdbl4 acc[NT];
 #pragma unroll
-    for (int c = 0; c < NRB; ++c) acc[c] = 0.0;
-    for (int c0 = 0; c0 < Kq; c0 += SOLVE_KC) {
-      for (int idx = lane; idx < SOLVE_KC * NRB; idx += WAVE) {
-        int kk = idx / NRB, cc = idx - kk * NRB;
-        int k = k0 + c0 + kk, col = cb + cc;
-        sw[idx] = (k < k1 && col < nr) ? B[(size_t)k * nr + col] : 0.0;
-      }
-      __syncthreads();
-      int kn = min(SOLVE_KC, k1 - (k0 + c0));
-      if (rv) {
-        const double* Ar = A + k0 + c0;
-        for (int kk = 0; kk < kn; kk += 8) {
-          double a[8];
+    for (int t = 0; t < NT; ++t) acc[t] = sdbl4{0.0, 0.0, 0.0, 0.0};
+    if (active)
+      for (int s = s0; s < s1; s += KU) {
+        double a[KU], bb[NT][KU];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) a[u] = (kk + u < kn) ? Ar[kk + u] : 0.0;
+        for (int u = 0; u < KU; ++u) {
+          const int k = 4 * (s + u) + fk;
+          const bool kok = s + u < s1 && k < T.K;
+          a[u] = (rok && kok) ? Ar[k] : 0.0;
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int c = 0; c < NRB; ++c) acc[c] = fma(a[u], sw[(kk + u) * NRB + c], acc[c]);
+          for (int t = 0; t < NT; ++t) {
+            const int col = cb + 16 * t + fr;
+            bb[t][u] = (kok && col < nr) ? B[(size_t)k * nr + col] : 0.0;
+          }
         }
-      }
-      __syncthreads();
-    }
-    // reduction over the four waves
 #pragma unroll
-    for (int c = 0; c < NRB; ++c) sB[(w * WAVE + lane) * NRB + c] = acc[c];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < T.rows * NRB; idx += WG) {
-      int r = idx / NRB, c = idx - r * NRB;
-      int col = cb + c;
-      if (col >= nr) continue;
-      double s = sB[(0 * WAVE + r) * NRB + c] + sB[(1 * WAVE + r) * NRB + c];
-      s += sB[(2 * WAVE + r) * NRB + c];
-      s += sB[(3 * WAVE + r) * NRB + c];
-      if (MODE == 0) {  // w = Piv^{-1}[rhs(X_b); 0]; rows from sel on are also rhs(Z_b)
-        Y0buf[(size_t)(T.y + r) * nr + col] = s;
-        if (r >= T.sel) Y1buf[(size_t)(T.z + r) * nr + col] = s;
-      } else if (MODE == 1) {  // rhs(rows(p)) -= A[rows(p), x_b] w_x
-        double* Y = T.sel ? Y1buf : Y0buf;
-        Y[(size_t)(T.y + r) * nr + col] -= s;
-      } else {  // sol(x_b) = w_x - W sol(O_c)
-        Y0buf[(size_t)(T.y + r) * nr + col] = Yinit[(size_t)(T.y0 + r) * nr + col] - s;
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[t][u], acc[t], 0, 0, 0);
       }
+    if (KP > 1) {  // the row tile's partial tiles, added in wave order by its first wave
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[w][t][q][lane] = acc[t][q];
+      __syncthreads();
+      if (active && kp == 0)
+        for (int p = 1; p < KP; ++p)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[t][q] += red[rt + RT * p][t][q][lane];
     }
+    // output (lane, q) of tile t: row rt 16 + lane / 16 + 4 q, column cb + 16 t + lane % 16
+    if (active && kp == 0)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = rt * 16 + fk + 4 * q, col = cb + 16 * t + fr;
+          if (r >= T.rows || col >= nr) continue;
+          const double v = acc[t][q];
+          if (MODE == 0) {  // w = Piv^{-1}[rhs(X_b); 0]; rows from sel on are also rhs(Z_b)
+            Y0buf[(size_t)(T.y + r) * nr + col] = v;
+            if (r >= T.sel) Y1buf[(size_t)(T.z + r) * nr + col] = v;
+          } else if (MODE == 1) {  // rhs(rows(p)) -= A[rows(p), x_b] w_x
+            double* Y = T.sel ? Y1buf : Y0buf;
+            Y[(size_t)(T.y + r) * nr + col] -= v;
+          } else {  // sol(x_b) = w_x - W sol(O_c)
+            Y0buf[(size_t)(T.y + r) * nr + col] = Yinit[(size_t)(T.y0 + r) * nr + col] - v;
+          }
+        }
     __syncthreads();
   }
 }
@@ -94,7 +111,7 @@ __global__ void __launch_bounds__(WG) k_gather_seg(const STask* __restrict__ seg
 // Top (level-2 multipole) system, Sec. 3.2: y = U^{-1} L^{-1} P rhs with the dense LU of the
 // top matrix.  The solves are blocked by 64 rows: one workgroup solves the block's triangle
 // (the block and its right-hand sides staged in LDS, one column per thread), then the rows
-// beyond the block are updated by a tiled product (k_rows_gemm), block after block.
+// beyond the block are updated by a tiled product (k_rows_mfma), block after block.
 constexpr int TB = 64;
 __global__ void k_top_perm(const double* __restrict__ B, const int* __restrict__ perm, int K, int nr, double* X) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -370,11 +387,9 @@ static void launch_rows(int ntask, const STask* t, const double* fslab, const do
                         const double* Yi, int nr, hipStream_t st) {
   if (ntask <= 0) return;
   dim3 g(ntask), blk(WG);
-  if (nr == 1) hipLaunchKernelGGL((k_rows_gemm<1, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
-  else if (nr == 2) hipLaunchKernelGGL((k_rows_gemm<2, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
-  else if (nr <= 4) hipLaunchKernelGGL((k_rows_gemm<4, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
-  else if (nr <= 8) hipLaunchKernelGGL((k_rows_gemm<8, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
-  else hipLaunchKernelGGL((k_rows_gemm<16, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
+  if (nr <= 16) hipLaunchKernelGGL((k_rows_mfma<1, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
+  else if (nr <= 32) hipLaunchKernelGGL((k_rows_mfma<2, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
+  else hipLaunchKernelGGL((k_rows_mfma<4, MODE>), g, blk, 0, st, t, fslab, B, Y0, Y1, Yi, nr);
 }
 
 static SolveBufs cache_bufs(aifmm_system& s) {
