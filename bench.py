@@ -146,8 +146,91 @@ SERVE_SYSTEMS = [
 ]
 
 
+# the serving workload at its full scale: eight resident systems, two of them at N=262144 (a
+# 3D system of that size does not fit one device, so the 3D systems are at 16384, one of them in
+# the precision form); each FGMRES operator is the NNCA-based H^2 product (eps_G 1e-14 in 2D,
+# 1e-10 in 3D), certified by the exact product
+SERVE_C5 = [
+    # (d, N, kernel, tol, precision, matvec_tol)
+    (2, 262144, ("invmq", 1e-2, 1.0), 1e-8, "fp64", 1e-14),
+    (2, 262144, ("exp", 0.5, 0.05), 1e-8, "fp64", 1e-14),
+    (2, 65536, ("invmq", 1e-2, 1.0), 1e-8, "fp64", 1e-14),
+    (2, 65536, ("exp", 1.0, 0.1), 1e-8, "fp64", 1e-14),
+    (2, 16384, ("exp", 0.5, 0.05), 1e-8, "fp64", 1e-14),
+    (2, 16384, ("invmq", 1e-2, 1.0), 1e-8, "fp64", 1e-14),
+    (3, 16384, ("invmq", 16384 ** (-1.0 / 3.0), 1.0), 1e-5, "fp32", 1e-10),
+    (3, 16384, ("invmq", 16384 ** (-1.0 / 3.0), 1.0), 1e-5, "fp64", 1e-10),
+]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def serve_stream(A, specs, rates, duration=10.0, warmup=1.0, seed=6001):
+    """Serving at scale: the resident systems of specs answer Poisson streams of requests (each
+    1-64 right-hand sides N(0,1) for a uniformly drawn system, solved to relative residual 1e-10
+    by FGMRES preconditioned by its factorization) at each rate in turn; requests of the first
+    `warmup` seconds are served but not counted.  Right-hand sides are column slices of one
+    64-column draw per system.  Per rate: completed right-hand sides per second over the counted
+    window, p50 / p99 latency (submission to completion) and the largest residual."""
+    import threading
+    systems, pools = [], []
+    t0 = time.perf_counter()
+    for q, (d, n, kern, tol, prec, mtol) in enumerate(specs):
+        pts, _ = I.points_and_rhs(n, d, 1, 6100 + q)
+        s = A.System(pts, kern, tol, 64, 0, precision=prec, matvec_tol=mtol)
+        s.factor()
+        systems.append(s)
+        pools.append(np.asfortranarray(np.random.default_rng(6200 + q).standard_normal((n, 64))))
+        log(f"served system {q} ({d}D N={n} {prec}) ready at {time.perf_counter() - t0:.1f} s")
+    out = {"systems": [f"{d}D N={n} {k[0]} tol {t} {p}" for d, n, k, t, p, _ in specs],
+           "setup_s": round(time.perf_counter() - t0, 2), "duration_s": duration, "warmup_s": warmup, "rates": []}
+    for rate in rates:
+        rng = np.random.default_rng(seed + int(rate))
+        n_req = int(rate * (duration + warmup))
+        gaps = rng.exponential(1.0 / rate, n_req)
+        which = rng.integers(0, len(systems), n_req)
+        nrhs = rng.integers(1, 65, n_req)
+        srv = A.Server(systems, rtol=1e-10, max_cols=64)
+        tickets = [None] * n_req
+        results = [None] * n_req
+        sub_t = [0.0] * n_req
+
+        def waiter():
+            for q in range(n_req):
+                while tickets[q] is None:
+                    time.sleep(1e-4)
+                results[q] = srv.wait(tickets[q])
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        ts = time.perf_counter()
+        due = ts
+        for q in range(n_req):
+            due += gaps[q]
+            while time.perf_counter() < due:
+                pass
+            sub_t[q] = time.perf_counter() - ts
+            tickets[q] = srv.submit(int(which[q]), pools[which[q]][:, : nrhs[q]])
+        th.join()
+        wall = time.perf_counter() - ts
+        srv.close()
+        counted = [q for q in range(n_req) if sub_t[q] >= warmup]
+        lat = np.array([results[q][1] for q in counted])
+        done = max(sub_t[q] + results[q][1] for q in counted)
+        rhs = int(sum(nrhs[q] for q in counted))
+        worst = max(float(np.max(results[q][4])) for q in range(n_req))
+        rec = {"rate_per_s": rate, "requests": len(counted), "rhs": rhs,
+               "solves_per_s": round(rhs / max(1e-9, done - warmup), 2),
+               "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+               "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "max_relres": worst,
+               "offered_rhs_per_s": round(rate * 32.5, 1), "wall_s": round(wall, 2)}
+        out["rates"].append(rec)
+        log(f"serving at {rate}/s: {rec}")
+    for s in systems:
+        s.close()
+    return out
 
 
 def serve(A, n_req=200, rate=2000.0, seed=5999):
@@ -273,6 +356,9 @@ def main():
                     help="systems of the batching form (every 256/count-th of the 256-system draw)")
     ap.add_argument("--batch-group", type=int, default=0,
                     help="systems per lockstep group of the batching form (0: all in one group)")
+    ap.add_argument("--serve-scale", type=str, default="",
+                    help="comma-separated request rates for the full serving workload (eight systems, two at "
+                         "N=262144), e.g. 5,10,20; adds a served_full object")
     ap.add_argument("--precision-config", default="c3_reduced",
                     help="workload of the precision-form comparison (c3 = the full-size 3D workload)")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form measurement")
@@ -306,12 +392,26 @@ def main():
         t4 = time.perf_counter()
         st = s.stats()
         levels = {l: s.level_stats(l) for l in range(2, s.L + 1)}
+        # outside the timed work: the direct solve from device-resident right-hand sides in
+        # steady state (the first call above captured the solve graph), for the solve roofline
+        import torch
+        bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
+        xd = torch.empty_like(bd)
+        ts = []
+        for _ in range(4):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            s.solve(bd, out=xd)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - ta)
+        solve_dev = statistics.median(ts[1:])
         # outside the timed work: the residual of the result under the exact FP64 product (every
         # kernel entry evaluated), and that of the direct solve
         true = np.linalg.norm(s.matvec(x) - b, axis=0) / np.linalg.norm(b, axis=0)
         true_direct = np.linalg.norm(s.matvec(x_direct) - b, axis=0) / np.linalg.norm(b, axis=0)
         s.close()
         return dict(build=t1 - t0, factor=t2 - t1, direct=t3 - t2, gmres=t4 - t3, total=t4 - t0, iters=its,
+                    solve_dev=solve_dev,
                     relres=rr, stats=st, levels=levels, x_direct=x_direct, true=true, true_direct=true_direct)
 
     for _ in range(args.warmup):
@@ -374,6 +474,12 @@ def main():
         "matvec_tol": MATVEC_TOL,
         "solves_per_s_to_rtol": round(nrhs / med("gmres"), 3),
         "direct_solves_per_s": round(nrhs / med("direct"), 3),
+        "direct_solve_device_s": round(med("solve_dev"), 5),
+        "solve_roofline": {"kernel": "direct solve: sweep products k_rows_mfma + top-system blocks, device-resident RHS",
+                           "bound": "hbm", "achieved": round(st["solve_bytes"] / med("solve_dev") / 1e9, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(st["solve_bytes"] / med("solve_dev") / 1e9 / HBM_PEAK_GBS, 4),
+                           "bytes_per_solve": st["solve_bytes"], "nrhs": nrhs},
         "roofline": {"kernel": "Schur phase: k_elim_trsm (pivot-block solve) + k_elim_schur (fill-in update)",
                      "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
@@ -403,6 +509,8 @@ def main():
     }
     if not args.no_serve:
         out["served"] = serve(A)
+    if args.serve_scale:
+        out["served_full"] = serve_stream(A, SERVE_C5, [float(r) for r in args.serve_scale.split(",")])
     if not args.no_batch:
         out["batched"] = batched(A, args.batch_count, args.batch_group)
     if not args.no_precision:

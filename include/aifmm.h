@@ -161,6 +161,7 @@ enum {
   AIFMM_STAT_GMRES_S = 12,        /* wall time of the last aifmm_gmres call */
   AIFMM_STAT_TRSM_KERNEL_S = 13,  /* summed device time of the pivot-block solve launches (HIP events) */
   AIFMM_STAT_TRSM_LAUNCHES = 14,
+  AIFMM_STAT_SOLVE_BYTES = 15,    /* factor-store bytes the products of one solve read (any nrhs) */
   AIFMM_STAT_COUNT = 16
 };
 aifmm_status aifmm_get_stats(const aifmm_system* s, double* stats /* AIFMM_STAT_COUNT */);

@@ -16,7 +16,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_SINGULAR", 4: "ERR_STAT
           6: "ERR_NOCONV", 7: "ERR_CAPACITY", 8: "ERR_BUSY"}
 STAT_NAMES = ["build_s", "factor_s", "solve_s", "schur_flops", "schur_bytes", "trsm_flops", "lu_flops",
               "device_bytes", "schur_kernel_s", "schur_launches", "compress_kernel_s", "compress_launches", "gmres_s",
-              "trsm_kernel_s", "trsm_launches"]
+              "trsm_kernel_s", "trsm_launches", "solve_bytes"]
 LSTAT_NAMES = ["factor_s", "schur_flops", "schur_bytes", "trsm_flops", "trsm_flops_impl", "lu_flops", "schur_kernel_s",
                "trsm_kernel_s", "compress_kernel_s", "compress_flops", "compressions", "rounds", "crit_steps",
                "pivot_steps", "boxes"]

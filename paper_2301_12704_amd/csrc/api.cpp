@@ -313,6 +313,7 @@ aifmm_status aifmm_get_stats(const aifmm_system* s, double* stats) {
   stats[AIFMM_STAT_GMRES_S] = s->stats.gmres_s;
   stats[AIFMM_STAT_TRSM_KERNEL_S] = s->stats.trsm_kernel_s;
   stats[AIFMM_STAT_TRSM_LAUNCHES] = s->stats.trsm_launches;
+  stats[AIFMM_STAT_SOLVE_BYTES] = s->stats.solve_bytes;
   return AIFMM_OK;
 }
 

@@ -192,6 +192,7 @@ static void launch_check(const char* what) {
 static void build_solve_plan(aifmm_system& s) {
   SolveCache& sc = s.sc;
   int L = s.L;
+  double solve_bytes = 0.0;  // factor-store bytes the products of one solve read
   sc.lev.clear();
   sc.lev.resize(L + 1);
   hipStream_t st = s.stream;
@@ -285,6 +286,8 @@ static void build_solve_plan(aifmm_system& s) {
       sl.gs_off.push_back((int)gs.size());
     }
     sl.grows = gmax;
+    for (auto* v : {&fw, &fu, &bw})
+      for (const STask& t : *v) solve_bytes += 8.0 * t.rows * t.K;
     sl.fw.upload(fw, st);
     sl.fu.upload(fu, st);
     sl.bw.upload(bw, st);
@@ -332,6 +335,8 @@ static void build_solve_plan(aifmm_system& s) {
     sc.top_fw.upload(fw, st);
     sc.top_bw.upload(bw, st);
   }
+  solve_bytes += 8.0 * (double)K * K;  // the top system's LU factors, once over both sweeps
+  s.stats.solve_bytes = solve_bytes;
   sc.nr_cap = 0;
   sc.built = true;
 }

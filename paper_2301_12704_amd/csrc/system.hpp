@@ -297,6 +297,7 @@ struct Stats {
   double schur_launches = 0, compress_launches = 0;
   double trsm_kernel_s = 0, trsm_launches = 0;
   double gmres_s = 0, gmres_iters = 0;
+  double solve_bytes = 0;                 // factor-store bytes one solve's products read (any nrhs)
 };
 
 }  // namespace aifmm
