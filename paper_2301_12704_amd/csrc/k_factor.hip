@@ -89,7 +89,7 @@ constexpr int CT = 512;
 
 // R: arithmetic of the compression (double, or float in the precision form); the block store
 // stays FP64 and operands are converted on load / store.
-template <class RT>
+template <class RT, int RMAX>
 __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ PP, const RoundEntry* __restrict__ ent,
                                                  int nent, double* ws, int64_t wsz, int cap, int G, unsigned* ctr,
                                                  Cand* part, int* abort, int lds_cols, double* pubbuf) {
@@ -119,15 +119,19 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
   double* trr = P.trace_ratio + (size_t)R.tidx * 8;
   __shared__ ValIdx shv[CT / WAVE + 1];
   extern __shared__ double shm[];  // one reflector (cap), pivot positions (2 x 2cap ints), own norms (2cap)
+  // vsh: the reflector, with the register tier's rows up to 16 RMAX
+  constexpr int RROWS = 16 * RMAX;
+  const int vlen = cap > RROWS ? cap : RROWS;
   RT* vsh = (RT*)shm;
-  int* pos = (int*)(vsh + cap);
+  int* pos = (int*)(vsh + vlen);
   int* at = pos + 2 * cap;
-  // columns of the pivoted QRs and Q formations kept in LDS (lds_cols per member), the
-  // members' candidate pivot columns published in pub (2 x G x cap entries per compression)
+  // columns of the pivoted QRs and Q formations: the register tier (RMAX rows per lane), then
+  // lds_cols per member in LDS, then the workspace; the members' candidate pivot columns
+  // published in pub (2 x G x vlen entries per compression)
   RT* lnr = (RT*)(at + 2 * cap);  // the member's own columns' norms (2 cap entries)
-  RT* lcol = lds_cols > 0 ? lnr + 2 * cap : nullptr;
-  RT* pub = (RT*)pubbuf + (size_t)e * 2 * G * cap;
-  RT* pubS = pub + (split && !inA ? (size_t)2 * GA * cap : 0);  // the sub-team's publication slots
+  RT* lcol = lnr + 2 * cap;
+  RT* pub = (RT*)pubbuf + (size_t)e * 2 * G * vlen;
+  RT* pubS = pub + (split && !inA ? (size_t)2 * GA * vlen : 0);  // the sub-team's publication slots
   RT* w = (RT*)(ws + (size_t)e * wsz);
   size_t c2 = (size_t)cap * cap;
   RT* Lb_i = w;
@@ -171,13 +175,13 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
       int ld = ki + nj;
       t_copy(C, ni, ki, U_i, ni, M, ld);
       t_copy(C, ni, nj, Fij, nj, M + ki, ld);
-      r1 = t_cpqr(C, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, pubS, t1);
+      r1 = t_cpqr<CT, RMAX>(C, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, lds_cols, pubS, t1);
       // RRQR3: [V_j | L~_ij^*] with L~_ij = Q1_{r1}^* P2P_ij  (Q1_{r1} = first r1 columns of U~_i)
-      t_formq(C, ni, r1, r1, V1, cap, tau, nU, cap, vsh, 0, lcol, t1);
+      t_formq<CT, RMAX>(C, ni, r1, r1, V1, cap, tau, nU, cap, vsh, 0, lcol, lds_cols, t1);
       ld = kj + r1;
       t_copy(C, nj, kj, V_j, nj, M, ld);
       t_gemm(C, nj, r1, ni, 1.0, Fij, nj, true, nU, cap, false, 0.0, M + kj, ld);
-      r3 = t_cpqr(C, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, lnr, shv, vsh, pos, at, trr + 4, lcol, pubS, t1);
+      r3 = t_cpqr<CT, RMAX>(C, nj, ld, M, ld, tol, V3, cap, tau + 2 * cap, nrm, lnr, shv, vsh, pos, at, trr + 4, lcol, lds_cols, pubS, t1);
       if (C.gtid == 0) {
         tr[0] = r1;
         tr[2] = r3;
@@ -191,13 +195,13 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
       int ld = kj + ni;
       t_copy(C, nj, kj, U_j, nj, Mc, ld);
       t_copy(C, nj, ni, Fji, ni, Mc + kj, ld);
-      r2 = t_cpqr(C, nj, ld, Mc, ld, tol, V2, cap, tau + cap, nc, lnr, shv, vsh, pos, at, trr + 2, lcol, pubS, gc);
+      r2 = t_cpqr<CT, RMAX>(C, nj, ld, Mc, ld, tol, V2, cap, tau + cap, nc, lnr, shv, vsh, pos, at, trr + 2, lcol, lds_cols, pubS, gc);
       // RRQR4: [V_i | L~_ji^*]
-      t_formq(C, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh, 0, lcol, gc);
+      t_formq<CT, RMAX>(C, nj, r2, r2, V2, cap, tau + cap, nUj, cap, vsh, 0, lcol, lds_cols, gc);
       ld = ki + r2;
       t_copy(C, ni, ki, V_i, ni, Mc, ld);
       t_gemm(C, ni, r2, nj, 1.0, Fji, ni, true, nUj, cap, false, 0.0, Mc + ki, ld);
-      r4 = t_cpqr(C, ni, ld, Mc, ld, tol, V4, cap, tau + 3 * cap, nc, lnr, shv, vsh, pos, at, trr + 6, lcol, pubS, gc);
+      r4 = t_cpqr<CT, RMAX>(C, ni, ld, Mc, ld, tol, V4, cap, tau + 3 * cap, nc, lnr, shv, vsh, pos, at, trr + 6, lcol, lds_cols, pubS, gc);
       if (C.gtid == 0) {
         tr[1] = r2;
         tr[3] = r4;
@@ -217,15 +221,15 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
     // coefficients by projection, U_i = U~_i L_i, V_i = V~_i R_i, ...: the i side on half A,
     // the j side on half B
     if (!split || inA) {
-      t_formq(C, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1, lcol, t1);
-      t_formq(C, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh, 0, lcol, t1);
+      t_formq<CT, RMAX>(C, ni, r1, kin, V1, cap, tau, nU, cap, vsh, r1, lcol, lds_cols, t1);
+      t_formq<CT, RMAX>(C, ni, r4, kin, V4, cap, tau + 3 * cap, nV, cap, vsh, 0, lcol, lds_cols, t1);
       t_gemm(C, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
       t_gemm(C, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
     }
     if (!split || !inA) {
       RT* gc = split ? t1b : t1;
-      t_formq(C, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2, lcol, gc);
-      t_formq(C, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh, 0, lcol, gc);
+      t_formq<CT, RMAX>(C, nj, r2, kjn, V2, cap, tau + cap, nUj, cap, vsh, r2, lcol, lds_cols, gc);
+      t_formq<CT, RMAX>(C, nj, r3, kjn, V3, cap, tau + 2 * cap, nVj, cap, vsh, 0, lcol, lds_cols, gc);
       t_gemm(C, kjn, kj, nj, 1.0, nUj, cap, true, U_j, nj, false, 0.0, Lb_j, kj1);
       t_gemm(C, kjn, kj, nj, 1.0, nVj, cap, true, V_j, nj, false, 0.0, Rb_j, kj1);
     }
@@ -293,7 +297,7 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
         M[(size_t)a * ld + ki + c] = P2L[(size_t)c * ni + a];
       }
       C.sync();
-      r5 = t_cpqr(C, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, pubS, t1);
+      r5 = t_cpqr<CT, RMAX>(C, ni, ld, M, ld, tol, V1, cap, tau, nrm, lnr, shv, vsh, pos, at, trr, lcol, lds_cols, pubS, t1);
       if (C.gtid == 0) tr[0] = r5;
     }
     if (!split || !inA) {
@@ -303,8 +307,8 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
       t_copy(C, ni, kr, M2P, nr, Mc + ki, ld);
       // column storage of the chain: t1b, never t1, which holds the new A_ri below when both
       // chains run on one workgroup
-      r6 = t_cpqr(C, ni, ld, Mc, ld, tol, V2, cap, tau + cap, split ? nrmb : nrm, lnr, shv, vsh, pos, at, trr + 2,
-                  lcol, pubS, t1b);
+      r6 = t_cpqr<CT, RMAX>(C, ni, ld, Mc, ld, tol, V2, cap, tau + cap, split ? nrmb : nrm, lnr, shv, vsh, pos, at, trr + 2,
+                  lcol, lds_cols, pubS, t1b);
       if (C.gtid == 0) tr[1] = r6;
     }
     if (split) {
@@ -316,14 +320,14 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
     int kin = r5 > r6 ? r5 : r6;
     // the V side (A_ri) on half A, the U side (A_ir) on half B
     if (!split || inA) {
-      t_formq(C, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol, t1);
+      t_formq<CT, RMAX>(C, ni, r5, kin, V1, cap, tau, nV, cap, vsh, 0, lcol, lds_cols, t1);
       t_gemm(C, kin, ki, ni, 1.0, nV, cap, true, V_i, ni, false, 0.0, Rb_i, ki1);
       // A_ri := A_ri R_i^* + P2L_ri V~_i
       t_gemm(C, kr, kin, ki, 1.0, Ari, ni, false, Rb_i, ki1, true, 0.0, t1, cap);
       t_gemm(C, kr, kin, ni, 1.0, P2L, ni, false, nV, cap, false, 1.0, t1, cap);
     }
     if (!split || !inA) {
-      t_formq(C, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, t1b);  // t1 holds A_ri here
+      t_formq<CT, RMAX>(C, ni, r6, kin, V2, cap, tau + cap, nU, cap, vsh, 0, lcol, lds_cols, t1b);  // t1 holds A_ri here
       t_gemm(C, kin, ki, ni, 1.0, nU, cap, true, U_i, ni, false, 0.0, Lb_i, ki1);
       // A_ir := L_i A_ir + U~_i^* M2P_ir
       t_gemm(C, kin, kr, ki, 1.0, Lb_i, ki1, false, Air, nr, false, 0.0, t2, kr1);
@@ -1802,25 +1806,44 @@ static void count_flops(aifmm_system& s, int l) {
   }
 }
 
-// largest half-team whose pivoted-QR columns live in LDS (a whole team has at most 128 members)
-static int lds_gmax() {
-  const char* v = getenv("AIFMM_LDS_TEAM_MAX");
-  int g = v && *v ? atoi(v) : 24;
-  return std::max(1, std::min(64, g));
-}
-
-// least pivoted-QR matrix entries per member of a workspace half-team
-static int team_elems() {
-  const char* v = getenv("AIFMM_TEAM_ELEMS");
-  int e = v && *v ? atoi(v) : 49152;
-  return std::max(1024, e);
-}
-
-// largest half-team whose pivoted-QR columns live in the workspace
-static int glob_gmax() {
+// largest half-team of a compression (a whole team has at most 128 members)
+static int team_max() {
   const char* v = getenv("AIFMM_TEAM_MAX");
-  int g = v && *v ? atoi(v) : 24;
+  int g = v && *v ? atoi(v) : 64;
   return std::max(1, std::min(64, g));
+}
+
+// rows per lane of the compression's register column tier for boxes of up to cap rows: the
+// smallest compiled size holding cap rows in a 16-lane group, 0 (no register tier) beyond
+// 1024 rows or when switched off
+static int reg_rows(int cap) {
+  const char* v = getenv("AIFMM_NO_REG_COLUMNS");
+  if (v && *v && *v != '0') return 0;
+  for (int r : {16, 32, 40, 64})
+    if (16 * r >= cap) return r;
+  return 0;
+}
+
+template <class RT>
+static const void* compress_fn(int rmax) {
+  switch (rmax) {
+    case 16: return (const void*)k_compress<RT, 16>;
+    case 32: return (const void*)k_compress<RT, 32>;
+    case 40: return (const void*)k_compress<RT, 40>;
+    case 64: return (const void*)k_compress<RT, 64>;
+    default: return (const void*)k_compress<RT, 0>;
+  }
+}
+// register slots of the pivoted QR's tier for rmax rows a lane
+template <class RT>
+static int reg_slots_of(int rmax) {
+  switch (rmax) {
+    case 16: return reg_slots<16, RT>();
+    case 32: return reg_slots<32, RT>();
+    case 40: return reg_slots<40, RT>();
+    case 64: return reg_slots<64, RT>();
+    default: return 0;
+  }
 }
 
 static bool lds_off() {
@@ -2111,68 +2134,52 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
     DBuf<int> d_lust;
     d_luctr.alloc(std::max(1, maxcol));
     d_lust.alloc(std::max(1, maxcol));
-    // compressions of a small round are spread over teams of G workgroups each (cooperative
-    // launch, so every team is co-resident); when a team's share of the pivoted-QR columns
-    // fits, the columns live in LDS (lds_cols per member), otherwise in the workspace
+    // the compressions of a round are spread over teams of G workgroups each (cooperative
+    // launch, so every team is co-resident); a member keeps its share of a pivoted QR's columns
+    // in registers (rows up to 16 RMAX), then in LDS, then in the workspace
     const size_t rs = f32 ? sizeof(float) : sizeof(double);
-    const void* kcomp = f32 ? (const void*)k_compress<float> : (const void*)k_compress<double>;
-    // reflector, pivot positions, own column norms
-    const size_t base = (size_t)cap * rs + (size_t)4 * cap * sizeof(int) + (size_t)2 * cap * rs;
+    const int rmax = reg_rows(cap);
+    const void* kcomp = f32 ? compress_fn<float>(rmax) : compress_fn<double>(rmax);
+    const int nreg = (CT / 16) * (f32 ? reg_slots_of<float>(rmax) : reg_slots_of<double>(rmax));  // per member
+    // reflector (rows up to the register tier's 16 RMAX), pivot positions, own column norms
+    const int vlen = std::max(cap, 16 * rmax);
+    const size_t base = (size_t)vlen * rs + (size_t)4 * cap * sizeof(int) + (size_t)2 * cap * rs;
     const size_t lds_max = 152 * 1024;
     if (base > lds_max) throw Error{AIFMM_ERR_CAPACITY, "box size too large for the compression kernel"};
+    const size_t colb = (size_t)(cap | 1) * rs;
+    const int ldsc = lds_off() ? 0 : (int)((lds_max - base) / colb);  // LDS columns per member
     AIFMM_HIP(hipFuncSetAttribute(kcomp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
     constexpr int GMAX = 128;
-    int coop_g = 0, coop_l = 0;
+    int coop_c = 0;  // co-resident compression workgroups (0: no cooperative launch)
     {
-      int dev = 0, coop = 0, ncu = 0, per_g = 0, per_l = 0;
+      int dev = 0, coop = 0, ncu = 0, per = 0;
       AIFMM_HIP(hipGetDevice(&dev));
       AIFMM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
       AIFMM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_g, kcomp, CT, base));
-      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_l, kcomp, CT, lds_max));
-      if (coop && !team_off()) {
-        coop_g = per_g * ncu;
-        coop_l = per_l * ncu;
-      }
+      AIFMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kcomp, CT, lds_max));
+      if (coop && !team_off()) coop_c = per * ncu;
     }
+    // the smallest even team whose halves (one pivoted QR each) hold their columns on chip, at
+    // most team_max members a half and as many as the co-resident workgroups allow; columns
+    // beyond the chip's share go to the workspace
     auto team_shape = [&](int ne, int& G, int& lcols, size_t& shm) {
+      const int need = 2 * cap;  // columns of one pivoted QR
+      int h = cdiv(need, std::max(1, nreg + ldsc));
+      h = std::max(1, std::min({h, team_max(), GMAX / 2}));
       G = 1;
-      lcols = 0;
-      shm = base;
-      // LDS bytes when each member holds a 1 / per share of one pivoted QR's columns
-      auto lds_need = [&](int per) { return base + (size_t)cdiv(2 * cap, per) * (cap | 1) * rs; };
-      if (!lds_off()) {
-        // the smallest even team whose halves (one pivoted QR each) keep their columns in LDS,
-        // halves of up to lds_gmax members: a pivot step of a larger half costs more in
-        // barriers than LDS columns save over workspace columns
-        if (coop_l > 0)
-          for (int g = 2; g <= 2 * lds_gmax(); g += 2) {
-            if ((int64_t)ne * g > coop_l) break;
-            if (lds_need(g / 2) <= lds_max) {
-              G = g;
-              lcols = cdiv(2 * cap, g / 2);
-              shm = lds_need(g / 2);
-              return;
-            }
-          }
-        if (lds_need(1) <= lds_max) {  // a lone workgroup, QRs one after the other
-          lcols = 2 * cap;
-          shm = lds_need(1);
-          return;
-        }
-      }
-      // workspace columns: two halves of up to glob_gmax members each
-      if (coop_g > 0 && ne > 0)
-        G = std::max(1, std::min({2 * glob_gmax(), coop_g / ne, 2 * (int)((int64_t)2 * cap * cap / team_elems())}));
+      if (coop_c > 0 && (int64_t)ne * 2 <= coop_c) G = 2 * std::min<int64_t>(h, coop_c / (2 * (int64_t)ne));
+      const int share = G > 1 ? cdiv(need, G / 2) : need;  // a member's columns of one QR
+      lcols = std::min(ldsc, std::max(0, share - nreg));
+      shm = base + (size_t)lcols * colb;
     };
-    std::map<std::pair<int, int>, int> team_hist;  // (team size, LDS columns) -> rounds
+    std::map<std::pair<int, int>, int> team_hist;  // (team size, LDS columns a member) -> rounds
     DBuf<unsigned> d_ctr;
     DBuf<Cand> d_part;
     DBuf<int> d_abort;
     DBuf<double> d_pub;
     d_ctr.alloc((size_t)3 * std::max(1, maxcol));  // a team's counter, then two per compression for its halves
     d_part.alloc((size_t)std::max(1, maxcol) * 4 * GMAX);
-    d_pub.alloc((size_t)std::max(1, maxcol) * 2 * GMAX * cap);
+    d_pub.alloc((size_t)std::max(1, maxcol) * 2 * GMAX * vlen);
     d_abort.alloc(1);
     d_part.zero(st);
     if (debug_abort()) {  // the abort flag raised before the first launch: every team barrier of
@@ -2203,16 +2210,9 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
         int G = 1, lcols = 0;
         size_t shm = base;
         team_shape(ne, G, lcols, shm);
-        if (verbose()) ++team_hist[{G, lcols > 0 ? 1 : 0}];
-        if (G == 1) {
-          if (f32)
-            hipLaunchKernelGGL(k_compress<float>, dim3(ne), dim3(CT), shm, st, PP, er, ne, ws.p, wsz, cap, 1, d_ctr.p,
-                               d_part.p, d_abort.p, lcols, d_pub.p);
-          else
-            hipLaunchKernelGGL(k_compress<double>, dim3(ne), dim3(CT), shm, st, PP, er, ne, ws.p, wsz, cap, 1, d_ctr.p,
-                               d_part.p, d_abort.p, lcols, d_pub.p);
-        } else {
-          AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * 3 * ne, st));
+        if (verbose()) ++team_hist[{G, lcols}];
+        if (G > 1) AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * 3 * ne, st));
+        {
           Cand* partp = d_part.p;
           unsigned* ctrp = d_ctr.p;
           int* abortp = d_abort.p;
@@ -2220,7 +2220,10 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
           double* pubp = d_pub.p;
           int64_t wszv = wsz;
           void* args[] = {(void*)&PP, (void*)&er, &ne, &wsp, &wszv, &cap, &G, &ctrp, &partp, &abortp, &lcols, &pubp};
-          AIFMM_HIP(hipLaunchCooperativeKernel(kcomp, dim3(ne * G), dim3(CT), args, shm, st));
+          if (G > 1)
+            AIFMM_HIP(hipLaunchCooperativeKernel(kcomp, dim3(ne * G), dim3(CT), args, shm, st));
+          else
+            AIFMM_HIP(hipLaunchKernel(kcomp, dim3(ne), dim3(CT), args, shm, st));
         }
         AIFMM_HIP(hipEventRecord(ce.second, st));
         {
@@ -2338,9 +2341,11 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
       ls.compress_s += t_cmp;
       s.stats.compress_launches += (double)cmp_ev.size();
       if (verbose()) {
-        fprintf(stderr, "[aifmm] level %d factored in %.3f s (%zu compressions), cap %d, coop %d/%d; rounds by team:", l,
-                since(R.tl), R.rent.size(), cap, coop_g, coop_l);
-        for (auto& kv : team_hist) fprintf(stderr, " G%d%s:%d", kv.first.first, kv.first.second ? "L" : "", kv.second);
+        fprintf(stderr,
+                "[aifmm] level %d factored in %.3f s (%zu compressions), cap %d, %d register columns of %d rows a "
+                "member, coop %d; rounds by team (G, LDS columns):",
+                l, since(R.tl), R.rent.size(), cap, nreg, 16 * rmax, coop_c);
+        for (auto& kv : team_hist) fprintf(stderr, " G%d+L%d:%d", kv.first.first, kv.first.second, kv.second);
         if (multi) fprintf(stderr, " (merged with %d systems)", na);
         fprintf(stderr, "\n");
       }

@@ -289,10 +289,10 @@ __device__ inline PivState piv_merge(const PivState& a, const PivState& b, R kee
   }
   return r;
 }
-// Workgroup-wide merge of the per-thread states (the same result on every thread).  The merge
-// is commutative and associative, so any pairing gives the same state: inside each 16-lane row
-// the partners come through DPP moves (lane ^ 1, lane ^ 2, the other quad, the other half row,
-// as in lane_sum16), then across the wave's four rows through two lane exchanges.
+// Merges of candidate states.  The merge is commutative and associative, so any pairing gives
+// the same state: inside each 16-lane row the partners come through DPP moves (lane ^ 1,
+// lane ^ 2, the other quad, the other half row, as in lane_sum16), then across the wave's four
+// rows through two lane exchanges.
 template <int CTRL>
 __device__ inline PivState dpp_piv(const PivState& x) {
   PivState o;
@@ -302,8 +302,9 @@ __device__ inline PivState dpp_piv(const PivState& x) {
   o.amb = __builtin_amdgcn_mov_dpp(x.amb, CTRL, 0xF, 0xF, false);
   return o;
 }
-template <int NT, class R>
-__device__ inline PivState wg_pivmerge(PivState x, R keep, PivState* sh) {
+// Wave-wide merge (the same state on every lane of the wave).
+template <class R>
+__device__ inline PivState wave_pivmerge(PivState x, R keep) {
   x = piv_merge(x, dpp_piv<0xB1>(x), keep);
   x = piv_merge(x, dpp_piv<0x4E>(x), keep);
   x = piv_merge(x, dpp_piv<0x141>(x), keep);
@@ -316,17 +317,40 @@ __device__ inline PivState wg_pivmerge(PivState x, R keep, PivState* sh) {
     o.amb = __shfl_xor(x.amb, off, WAVE);
     x = piv_merge(x, o, keep);
   }
-  int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  return x;
+}
+// Workgroup-wide maximum of a double and minimum of an int (the same value on every thread):
+// DPP moves inside each 16-lane row, two lane exchanges across the rows, then the waves' values
+// through LDS (sh: NT / 64 entries, not read again before the next __syncthreads).  Maxima and
+// minima do not depend on the order of the operands.
+template <int NT>
+__device__ inline double wg_max(double x, double* sh) {
+  x = fmax(x, dpp_mov<0xB1>(x));
+  x = fmax(x, dpp_mov<0x4E>(x));
+  x = fmax(x, dpp_mov<0x141>(x));
+  x = fmax(x, dpp_mov<0x140>(x));
+  x = fmax(x, __shfl_xor(x, 16, WAVE));
+  x = fmax(x, __shfl_xor(x, 32, WAVE));
+  if (threadIdx.x % WAVE == 0) sh[threadIdx.x / WAVE] = x;
   __syncthreads();
-  if (lane == 0) sh[w] = x;
+  double r = sh[0];
+#pragma unroll
+  for (int q = 1; q < NT / WAVE; ++q) r = fmax(r, sh[q]);
+  return r;
+}
+template <int NT>
+__device__ inline int wg_min(int x, int* sh) {
+  x = min(x, __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false));
+  x = min(x, __shfl_xor(x, 16, WAVE));
+  x = min(x, __shfl_xor(x, 32, WAVE));
+  if (threadIdx.x % WAVE == 0) sh[threadIdx.x / WAVE] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    PivState b = sh[0];
-    for (int q = 1; q < NT / WAVE; ++q) b = piv_merge(b, sh[q], keep);
-    sh[NT / WAVE] = b;
-  }
-  __syncthreads();
-  PivState r = sh[NT / WAVE];
+  int r = sh[0];
+#pragma unroll
+  for (int q = 1; q < NT / WAVE; ++q) r = min(r, sh[q]);
   return r;
 }
 
@@ -397,6 +421,42 @@ __device__ inline R grp_axpy(R* col, const R* v, int r0, int m, int s, R w) {
   return t;
 }
 
+// Column storage of the pivoted QR and the Q formation.  A member's own columns are numbered
+// lc = 0, 1, ... (column c = member + G lc of the matrix, or c0 + member + G lc of Q); lane group
+// lc mod (NT / 16) runs column lc.  The first (NT / 16) NS own columns live in registers (slot
+// lc / (NT / 16) of that lane group; lane q holds the rows q, q + 16, ..., RMAX of them, so the
+// tier needs m <= 16 RMAX); the next lcols in the member's LDS (lcol, column at
+// lcol + (lc - (NT / 16) NS) (m | 1)); the rest in the workspace gcol.  RMAX = 0 turns the
+// register tier off.
+//
+// reflector entries read ahead by the register tier's row loops (a scheduling barrier between
+// groups keeps the compiler from issuing all RMAX loads at once)
+constexpr int REG_CHUNK = 8;
+// Register slots a lane group holds (RMAX rows each): 64 FP64 values a lane (at least one
+// slot), or up to 4 slots of FP32, the same for the pivoted QR and the Q formation.  Larger
+// tiers make the compiler spill slots in the pivot-step loop (the kernel holds 512 threads, so
+// a lane has 256 registers).
+template <int RMAX, class R>
+__host__ __device__ constexpr int reg_slots() {
+  return RMAX == 0 ? 0 : sizeof(R) == 8 ? (64 / RMAX > 1 ? 64 / RMAX : 1) : (128 / RMAX < 4 ? 128 / RMAX : 4);
+}
+
+// Each value passes through an empty asm statement, so the compiler cannot merge the slots'
+// branches into one load of ra at the runtime index k (which would keep ra in scratch memory).
+template <int RMAX, int NS, class R>
+__device__ __attribute__((always_inline)) inline void reg_put(const R (&ra)[NS][RMAX], int k, int lane, R* dst) {
+#pragma unroll
+  for (int kk = 0; kk < NS; ++kk)
+    if (kk == k) {
+#pragma unroll
+      for (int u = 0; u < RMAX; ++u) {
+        R x = ra[kk][u];
+        asm volatile("" : "+v"(x));
+        dst[lane + PL * u] = x;
+      }
+    }
+}
+
 // Householder QR with column pivoting of the m x n row-major M, truncated at the first step
 // whose pivot column norm is <= tol times the first one (RRQR with threshold eps_A of
 // Sec. 3.2.1).  Pivot: the lowest-position column whose trailing norm is within a relative
@@ -406,46 +466,79 @@ __device__ inline R grp_axpy(R* col, const R* v, int r0, int m, int s, R w) {
 // Columns stay where they are: column c is owned by member c mod G and, inside it, by the
 // lane group (c / G) mod (NT / 16); its pivot-order position is tracked in pos / at (LDS of
 // every member, n entries each), so a swap of positions s and p is the column exchange of the
-// textbook algorithm.  M is read once, into column-major storage: the member's LDS (lcol,
-// column c at lcol + (c / G) (m | 1)) or, without lcol, the workspace gcol (column c at
-// gcol + c m, m n entries).  With LDS columns in a team each member publishes its candidate
-// column in pub before the exchange.  The pivot column is read by every member to form the
-// reflector (vsh: m entries of LDS).  Reflector s is written to row s of V (ldv) with
-// V[s][s] = 1, its scale to tau[s]; nrm (device memory, n) holds each column's trailing norm
-// and lnr (LDS, n / G entries) the member's own columns' norms (column c at lnr[c / G]).
-// M is left unchanged (R is not formed).  Returns the rank; ratio (if given) receives
-// |R_kk| / (tol |R_11|) of the last kept and of the first rejected pivot.
-template <int NT, class R>
+// textbook algorithm.  M is read once, into the column storage above (registers, LDS lcol,
+// workspace gcol with column c at gcol + c m).  In a team each member publishes its candidate
+// column in pub before the exchange (2 G slots of m entries, of 16 RMAX with the register
+// tier); a lone workgroup stages a register column in vsh.  The pivot column is read by every
+// member to form the reflector (vsh: LDS of max(m, 16 RMAX) entries).
+// Reflector s is written to row s of V (ldv) with V[s][s] = 1, its scale to tau[s]; nrm
+// (device memory, n) holds each column's trailing norm and lnr (LDS, n / G entries) the
+// member's own columns' norms (column c at lnr[c / G]).  M is left unchanged (R is not
+// formed).  Returns the rank; ratio (if given) receives |R_kk| / (tol |R_11|) of the last kept
+// and of the first rejected pivot.
+template <int NT, int RMAX, class R>
 __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, double tol, R* V, int ldv, R* tau,
                              R* nrm, R* lnr, ValIdx* shv, R* vsh, int* pos, int* at, double* ratio, R* lcol,
-                             R* pub, R* gcol) {
-  __shared__ PivState psh[NT / WAVE + 1];
+                             int lcols, R* pub, R* gcol) {
+  __shared__ double shmx[NT / WAVE];
+  __shared__ int shmn[NT / WAVE];
   constexpr int NGW = NT / PL;  // lane groups per workgroup
+  constexpr int NS = reg_slots<RMAX, R>();
+  constexpr int NREG = NGW * NS;  // own columns in registers
+  // loads in flight a lane for the columns outside registers (fewer beside more register slots)
+  constexpr int GB = NS == 0 ? COL_BG : NS >= 3 ? 2 : NS == 2 ? 4 : 8;
+  const int PS = NS > 0 ? PL * RMAX : m;  // entries of a publication slot
   // pivot ties: norms within a relative band of the largest (1e-11 in FP64, 2e-6 in FP32)
   const R keep = sizeof(R) == 4 ? R(1.0 - 2e-6) : R(1.0 - 1e-11);
   const R tolr = (R)tol;
-  const bool lds = lcol != nullptr;
   const int lstride = m | 1;  // odd column stride: the groups of a wave start on distinct banks
-  auto colp = [&](int c) -> R* { return lds ? lcol + (size_t)(c / T.G) * lstride : gcol + (size_t)c * m; };
+  // a column outside the register tier: LDS, then workspace
+  auto colp = [&](int lc, int c) -> R* {
+    const int l = lc - NREG;
+    return l < lcols ? lcol + (size_t)l * lstride : gcol + (size_t)c * m;
+  };
   const int lane = (int)threadIdx.x & (PL - 1), grp = (int)threadIdx.x / PL;
   const int nloc = (n - T.member + T.G - 1) / T.G;  // own columns: c = member + G lc
   double kept = 0.0, next = 0.0;
   int smax = m < n ? m : n;
   R r11 = 0;
+  R ra[NS > 0 ? NS : 1][RMAX > 0 ? RMAX : 1];
   // own columns into column storage, with their norms
-  for (int lc = grp; lc < nloc; lc += NGW) {
-    const int c = T.member + T.G * lc;
-    R* d = colp(c);
-    R t = 0;
-    for (int i0 = lane; i0 < m; i0 += PL * COL_BG) {
-      R a[COL_BG];
+  if constexpr (NS > 0) {
 #pragma unroll
-      for (int u = 0; u < COL_BG; ++u) {
+    for (int k = 0; k < NS; ++k) {
+      const int lc = grp + NGW * k;
+      const int c = T.member + T.G * lc;
+      const bool own = lc < nloc;
+      R t = 0;
+#pragma unroll
+      for (int u = 0; u < RMAX; ++u) {
+        const int i = lane + PL * u;
+        const R a = (own && i < m) ? M[(size_t)i * ldm + c] : R(0);
+        ra[k][u] = a;
+        if (i < m) t = fma(a, a, t);
+      }
+      t = lane_sum16(t);
+      if (own && lane == 0) {
+        R v = sqrt(t);
+        nrm[c] = v;
+        lnr[lc] = v;
+      }
+    }
+  }
+  for (int lc = NREG + grp; lc < nloc; lc += NGW) {
+    const int c = T.member + T.G * lc;
+    R* d = colp(lc, c);
+    R t = 0;
+    for (int i0 = lane; i0 < m; i0 += PL * GB) {
+      R a[GB];
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
         int i = i0 + PL * u;
         a[u] = i < m ? M[(size_t)i * ldm + c] : R(0);
       }
 #pragma unroll
-      for (int u = 0; u < COL_BG; ++u) {
+      for (int u = 0; u < GB; ++u) {
         int i = i0 + PL * u;
         if (i < m) {
           d[i] = a[u];
@@ -464,32 +557,52 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     pos[c] = c;
     at[c] = c;
   }
+  // the register tier runs every row of its slots: the rows m .. 16 RMAX - 1 hold zeros in
+  // the columns and in vsh, whose entries below s are zero too, so those rows add exact zeros
+  // to the row sums and leave the column values as they are
+  for (int i = m + (int)threadIdx.x; i < PL * RMAX; i += NT) vsh[i] = R(0);
   __syncthreads();
+  // the rows s..m-1 of own column cc (lc = cc / G) into dst: by its lane group from registers
+  // (all 16 RMAX rows of the slot; the rows below s are not read), else by the whole workgroup
+  auto publish = [&](int cc, R* dst, int s) {
+    const int lc = cc / T.G;
+    if (lc < NREG) {
+      if constexpr (NS > 0)
+        if (grp == lc % NGW) reg_put<RMAX, NS>(ra, lc / NGW, lane, dst);
+    } else {
+      const R* src = colp(lc, cc);
+      for (int i = s + threadIdx.x; i < m; i += NT) dst[i] = src[i];
+    }
+  };
   int s = 0;
   for (; s < smax; ++s) {
-    // one merged pass per workgroup, then one exchange across the team: the largest live norm
-    // and the lowest position within the tie band of it; the exact two-pass selection runs
-    // only when a merge reports an ambiguity
-    PivState ps{-1.0, -1.0, INT_MAX, 0};
+    // the member's exact pivot (the largest live norm of its columns, then the lowest position
+    // within the tie band of it), then one exchange across the team that merges the members'
+    // states; the exact two-pass selection over the team runs only when the merge reports an
+    // ambiguity
+    double mxl = -1.0;
     for (int c = T.cid; c < n; c += T.GT)
-      if (pos[c] >= s) {
-        const double v = (double)lnr[c / T.G];
-        ps = piv_merge(ps, PivState{v, v, pos[c], 0}, keep);
-      }
-    ps = wg_pivmerge<NT>(ps, keep, psh);
-    // LDS columns of a team: each member publishes its candidate column (rows s..m-1) before
-    // the exchange, in a buffer alternating with the step parity
-    R* slot = pub + ((size_t)(s & 1) * T.G + T.member) * m;
-    if (lds && T.G > 1 && ps.p != INT_MAX) {
-      const R* src = colp(at[ps.p]);
-      for (int i = s + threadIdx.x; i < m; i += NT) slot[i] = src[i];
-    }
+      if (pos[c] >= s) mxl = fmax(mxl, (double)lnr[c / T.G]);
+    const double mxw = wg_max<NT>(mxl, shmx);
+    const R thrw = (R)mxw * keep;
+    int pl = INT_MAX;
+    for (int c = T.cid; c < n; c += T.GT)
+      if (pos[c] >= s && lnr[c / T.G] >= thrw && pos[c] < pl) pl = pos[c];
+    const int pw = wg_min<NT>(pl, shmn);
+    PivState ps{mxw, pw != INT_MAX ? (double)lnr[at[pw] / T.G] : -1.0, pw, 0};
+    // a team: each member publishes its candidate column (rows s..m-1) before the exchange, in
+    // a buffer alternating with the step parity
+    R* slot = pub + ((size_t)(s & 1) * T.G + T.member) * PS;
+    if (T.G > 1 && ps.p != INT_MAX) publish(at[ps.p], slot, s);
     if (T.G > 1) {
       const Cand* all = T.exchange(Cand{ps.mx, ps.nv, ps.p, ps.amb});
       if (T.bad) break;  // the members' candidates may be stale: no pivot is taken from them
+      // the members' states: lane q of every wave takes members q, q + 64, ..., then a tree
+      // across the wave (any pairing gives the same state)
       PivState g{-1.0, -1.0, INT_MAX, 0};
-      for (int q = 0; q < T.G; ++q) g = piv_merge(g, PivState{all[q].mv, all[q].nv, all[q].p, all[q].pad}, keep);
-      ps = g;
+      for (int q = (int)threadIdx.x % WAVE; q < T.G; q += WAVE)
+        g = piv_merge(g, PivState{all[q].mv, all[q].nv, all[q].p, all[q].pad}, keep);
+      ps = wave_pivmerge(g, keep);
     }
     int pp = ps.p;
     bool amb = ps.amb != 0;
@@ -521,21 +634,25 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       break;
     }
     kept = (double)bv / ((double)tolr * (double)r11);
-    // where the pivot column is read from: the owner's LDS (a lone workgroup), the owner's
-    // publication slot (a team with LDS columns) or the workspace
-    const R* pcol = colp(cp);
-    if (lds && T.G > 1) {
+    // where the pivot column is read from: the owner's publication slot (a team), the LDS
+    // staging copy in vsh (a lone workgroup's register column), or its storage
+    const R* pcol;
+    bool staged = false;
+    if (T.G > 1) {
       const int owner = cp % T.G;
-      R* oslot = pub + ((size_t)(s & 1) * T.G + owner) * m;
+      R* oslot = pub + ((size_t)(s & 1) * T.G + owner) * PS;
       if (amb) {  // the chosen column may not be its owner's candidate: publish it
-        if (T.member == owner) {
-          const R* src = colp(cp);
-          for (int i = s + threadIdx.x; i < m; i += NT) oslot[i] = src[i];
-        }
+        if (T.member == owner) publish(cp, oslot, s);
         T.sync();
         if (T.bad) break;
       }
       pcol = oslot;
+    } else if (cp / T.G < NREG) {
+      publish(cp, vsh, s);
+      staged = true;
+      pcol = vsh;
+    } else {
+      pcol = colp(cp / T.G, cp);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -545,11 +662,31 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       pos[cp] = s;
       pos[cs] = pp;
     }
+    // the thread's rows of the pivot column are read together with x0 (one memory latency)
+    constexpr int PV = 2;
+    R pv[PV];
+#pragma unroll
+    for (int k = 0; k < PV; ++k) {
+      const int i = (int)threadIdx.x + k * NT;
+      pv[k] = (i > s && i < m) ? pcol[i] : R(0);
+    }
     R x0 = pcol[s];
     R beta = x0 >= R(0) ? -bv : bv;
     R scale = x0 - beta;
     R tv = (beta - x0) / beta;
-    for (int i = threadIdx.x; i < m; i += NT) {
+    if (staged) __syncthreads();  // pcol read by every thread before vsh is overwritten in place
+#pragma unroll
+    for (int k = 0; k < PV; ++k) {
+      const int i = (int)threadIdx.x + k * NT;
+      if (i < m) {
+        R v = 0;
+        if (i == s) v = 1;
+        else if (i > s) v = pv[k] / scale;
+        vsh[i] = v;
+        if (T.member == 0 && i >= s) V[(size_t)s * ldv + i] = v;
+      }
+    }
+    for (int i = (int)threadIdx.x + PV * NT; i < m; i += NT) {
       R v = 0;
       if (i == s) v = 1;
       else if (i > s) v = pcol[i] / scale;
@@ -560,14 +697,66 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     __syncthreads();
     // apply the reflector to the own live columns: w = tau v^T a over rows s..m-1, a -= w v,
     // and the new trailing norm over rows s+1..m-1
+    if constexpr (NS > 0) {
+      // every row of every slot: a column no longer live (a pivot already taken) is not read
+      // again, so it may be updated as well; only its norm is not stored
+      R acc[NS], w[NS], t[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        acc[k] = 0;
+        t[k] = 0;
+      }
+#pragma unroll
+      for (int u = 0; u < RMAX; ++u) {
+        if (u % REG_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
+        const R vv = vsh[lane + PL * u];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) acc[k] = fma(vv, ra[k][u], acc[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < NS; ++k) w[k] = lane_sum16(acc[k]) * tv;
+      // vsh is read again rather than kept: its RMAX values would double the tier's registers
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int u = 0; u < RMAX; ++u) {
+        if (u % REG_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
+        const R vv = vsh[lane + PL * u];
+        const bool below = lane + PL * u > s;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const R x = fma(-w[k], vv, ra[k][u]);
+          ra[k][u] = x;
+          const R xs = below ? x : R(0);
+          t[k] = fma(xs, xs, t[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const R tt = lane_sum16(t[k]);
+        const int lc = grp + NGW * k;
+        if (lane == 0 && lc < nloc && pos[T.member + T.G * lc] > s) {
+          R v = sqrt(tt);
+          nrm[T.member + T.G * lc] = v;
+          lnr[lc] = v;
+        }
+      }
+    }
     const int r0 = s + ((lane - s) & (PL - 1));  // this lane's first row >= s
-    for (int lc = grp; lc < nloc; lc += NGW) {
+    for (int lc = NREG + grp; lc < nloc; lc += NGW) {
       const int c = T.member + T.G * lc;
       if (pos[c] <= s) continue;
-      R* col = colp(c);
-      const R acc = lds ? grp_dot<COL_B>(col, vsh, r0, m) : grp_dot<COL_BG>(col, vsh, r0, m);
-      const R w = lane_sum16(acc) * tv;
-      R t = lds ? grp_axpy<COL_B, true>(col, vsh, r0, m, s, w) : grp_axpy<COL_BG, true>(col, vsh, r0, m, s, w);
+      R* col = colp(lc, c);
+      R acc, t;
+      if constexpr (NS > 0) {  // one path for LDS and workspace columns, few registers
+        acc = grp_dot<GB>(col, vsh, r0, m);
+        const R w = lane_sum16(acc) * tv;
+        t = grp_axpy<GB, true>(col, vsh, r0, m, s, w);
+      } else {
+        const bool inl = lc - NREG < lcols;
+        acc = inl ? grp_dot<COL_B>(col, vsh, r0, m) : grp_dot<COL_BG>(col, vsh, r0, m);
+        const R w = lane_sum16(acc) * tv;
+        t = inl ? grp_axpy<COL_B, true>(col, vsh, r0, m, s, w) : grp_axpy<COL_BG, true>(col, vsh, r0, m, s, w);
+      }
       t = lane_sum16(t);
       if (lane == 0) {
         R v = sqrt(t);
@@ -587,48 +776,114 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
 
 // Columns c0 .. q-1 of Q = H_0 ... H_{rank-1} [I; 0] (m x q, ldq); columns below c0 are left
 // as they are (already formed).  Reflector s is row s of V (ldv), as t_cpqr writes it.  Column
-// j is owned by member (j - c0) mod G and formed by one lane group through all reflectors
-// (row sums in the fixed order of lane_sum16), in the member's LDS (lcol, column j at
-// lcol + ((j - c0) / G) (m | 1)) or, without lcol, in the workspace gcol (column j at
-// gcol + (j - c0) m); it is written to Q at the end, so members only synchronise there.
-template <int NT, class R>
+// j is owned by member (j - c0) mod G (own index lj = (j - c0) / G) and formed by one lane
+// group through all reflectors (row sums in the fixed order of lane_sum16), then written to
+// Q, so members only synchronise at the end.  With the register tier (RMAX > 0) the columns
+// are independent, so the member forms them in passes of (NT / 16) NS register columns;
+// without it a column lives in the member's LDS (lcol, lcols columns of stride m | 1) or the
+// workspace gcol (column j at gcol + (j - c0) m).
+template <int NT, int RMAX, class R>
 __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, int ldv, const R* tau, R* Q, int ldq,
-                               R* vsh, int c0, R* lcol, R* gcol) {
+                               R* vsh, int c0, R* lcol, int lcols, R* gcol) {
   if (q <= c0) return;  // nothing to form (uniform over the team)
   constexpr int NGW = NT / PL;
-  const bool lds = lcol != nullptr;
-  const int lstride = m | 1;
+  constexpr int NS = reg_slots<RMAX, R>();
   const int lane = (int)threadIdx.x & (PL - 1), grp = (int)threadIdx.x / PL;
   const int nloc = (q - c0 - T.member + T.G - 1) / T.G;  // own columns: j = c0 + member + G lj
-  auto colp = [&](int lj, int j) -> R* { return lds ? lcol + (size_t)lj * lstride : gcol + (size_t)(j - c0) * m; };
-  for (int lj = grp; lj < nloc; lj += NGW) {
-    const int j = c0 + T.member + T.G * lj;
-    R* col = colp(lj, j);
-    for (int i = lane; i < m; i += PL) col[i] = (i == j) ? R(1) : R(0);
-  }
-  for (int s = rank - 1; s >= 0; --s) {
-    R tv = tau[s];
-    __syncthreads();
-    for (int i = s + threadIdx.x; i < m; i += NT) vsh[i] = V[(size_t)s * ldv + i];
-    __syncthreads();
-    const int j0 = c0 > s ? c0 : s;
-    const int r0 = s + ((lane - s) & (PL - 1));
-    // a column is still e_j while s > j, so the reflector leaves it unchanged
+  if constexpr (NS > 0) {
+    constexpr int NREG = NGW * NS;
+    // every row of every slot, with vsh zero outside the rows s..m-1: the columns hold exact
+    // zeros beyond row m, and the rows of a column that a reflector does not reach are +0 or
+    // the 1 of e_j, which adding exact zeros leaves as they are
+    for (int i = m + (int)threadIdx.x; i < PL * RMAX; i += NT) vsh[i] = R(0);
+    for (int p0 = 0; p0 < nloc; p0 += NREG) {
+      R ra[NS][RMAX];
+      // the first own column of the pass through an empty asm statement: the compiler cannot
+      // form the pass's columns ahead of their use (above earlier loops), where they would
+      // hold registers
+      int jp = c0 + T.member + T.G * p0;
+      asm volatile("" : "+v"(jp));
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int j = jp + T.G * (grp + NGW * k);
+#pragma unroll
+        for (int u = 0; u < RMAX; ++u) ra[k][u] = (lane + PL * u == j) ? R(1) : R(0);
+      }
+      for (int s = rank - 1; s >= 0; --s) {
+        const R tv = tau[s];
+        __syncthreads();
+        for (int i = threadIdx.x; i < m; i += NT) vsh[i] = i >= s ? V[(size_t)s * ldv + i] : R(0);
+        __syncthreads();
+        R acc[NS], w[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) acc[k] = 0;
+#pragma unroll
+        for (int u = 0; u < RMAX; ++u) {
+          if (u % REG_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
+          const R vv = vsh[lane + PL * u];
+#pragma unroll
+          for (int k = 0; k < NS; ++k) acc[k] = fma(vv, ra[k][u], acc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) w[k] = lane_sum16(acc[k]) * tv;
+        // vsh is read again rather than kept: its RMAX values would double the tier's registers
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < RMAX; ++u) {
+          if (u % REG_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
+          const R vv = vsh[lane + PL * u];
+#pragma unroll
+          for (int k = 0; k < NS; ++k) ra[k][u] = fma(-w[k], vv, ra[k][u]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int lj = p0 + grp + NGW * k;
+        if (lj < nloc) {
+          const int j = c0 + T.member + T.G * lj;
+#pragma unroll
+          for (int u = 0; u < RMAX; ++u) {
+            const int i = lane + PL * u;
+            if (i < m) Q[(size_t)i * ldq + j] = ra[k][u];
+          }
+        }
+      }
+    }
+  } else {
+    const int lstride = m | 1;
+    auto colp = [&](int lj, int j) -> R* {
+      return lj < lcols ? lcol + (size_t)lj * lstride : gcol + (size_t)(j - c0) * m;
+    };
     for (int lj = grp; lj < nloc; lj += NGW) {
       const int j = c0 + T.member + T.G * lj;
-      if (j < j0) continue;
       R* col = colp(lj, j);
-      const R acc = lds ? grp_dot<COL_B>(col, vsh, r0, m) : grp_dot<COL_BG>(col, vsh, r0, m);
-      const R w = lane_sum16(acc) * tv;
-      if (lds) grp_axpy<COL_B, false>(col, vsh, r0, m, s, w);
-      else grp_axpy<COL_BG, false>(col, vsh, r0, m, s, w);
+      for (int i = lane; i < m; i += PL) col[i] = (i == j) ? R(1) : R(0);
     }
-  }
-  __syncthreads();
-  for (int lj = grp; lj < nloc; lj += NGW) {
-    const int j = c0 + T.member + T.G * lj;
-    const R* col = colp(lj, j);
-    for (int i = lane; i < m; i += PL) Q[(size_t)i * ldq + j] = col[i];
+    for (int s = rank - 1; s >= 0; --s) {
+      R tv = tau[s];
+      __syncthreads();
+      for (int i = s + threadIdx.x; i < m; i += NT) vsh[i] = V[(size_t)s * ldv + i];
+      __syncthreads();
+      const int j0 = c0 > s ? c0 : s;
+      const int r0 = s + ((lane - s) & (PL - 1));
+      // a column is still e_j while s > j, so the reflector leaves it unchanged
+      for (int lj = grp; lj < nloc; lj += NGW) {
+        const int j = c0 + T.member + T.G * lj;
+        if (j < j0) continue;
+        R* col = colp(lj, j);
+        const bool inl = lj < lcols;
+        const R acc = inl ? grp_dot<COL_B>(col, vsh, r0, m) : grp_dot<COL_BG>(col, vsh, r0, m);
+        const R w = lane_sum16(acc) * tv;
+        if (inl) grp_axpy<COL_B, false>(col, vsh, r0, m, s, w);
+        else grp_axpy<COL_BG, false>(col, vsh, r0, m, s, w);
+      }
+    }
+    __syncthreads();
+    for (int lj = grp; lj < nloc; lj += NGW) {
+      const int j = c0 + T.member + T.G * lj;
+      const R* col = colp(lj, j);
+      for (int i = lane; i < m; i += PL) Q[(size_t)i * ldq + j] = col[i];
+    }
   }
   T.sync();
 }
