@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
   int e = blockIdx.x / G;
   if (e >= nent) return;
   Team<CT> T;
-  T.init(blockIdx.x - e * G, G, ctr + e, part + (size_t)e * 4 * G, abort);
+  T.init(blockIdx.x - e * G, G, ctr + (size_t)e * CTR_STRIDE, part + (size_t)e * 4 * G, abort);
   // a team of two or more runs the independent pivoted QRs of the compression concurrently on
   // its two halves (sub-teams A: members 0 .. GA-1 and B: the rest), each with its own barrier
   // counter, exchange slots, publication slots and workspace, and joins them with a team barrier
@@ -108,10 +108,10 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
   // registers
   Team<CT> C;
   if (split)
-    C.init(inA ? T.member : T.member - GA, inA ? GA : G - GA, ctr + nent + 2 * e + (inA ? 0 : 1),
+    C.init(inA ? T.member : T.member - GA, inA ? GA : G - GA, ctr + (size_t)(nent + 2 * e + (inA ? 0 : 1)) * CTR_STRIDE,
            part + (size_t)e * 4 * G + 2 * G + (inA ? 0 : 2 * GA), abort);
   else
-    C.init(0, 1, ctr + e, part + (size_t)e * 4 * G, abort);
+    C.init(0, 1, ctr + (size_t)e * CTR_STRIDE, part + (size_t)e * 4 * G, abort);
   RoundEntry R = ent[e];
   const LevelPtrs& P = PP[R.sys];
   const double tol = P.tol;
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(WG) k_elim_lu(const LevelPtrs* __restrict__ PP
   int b = boxes[e];
   int m = P.n[b] + P.k[b];
   Team<WG> T;
-  T.init(blockIdx.x - e * G, G, ctr + e, nullptr, abort);
+  T.init(blockIdx.x - e * G, G, ctr + (size_t)e * CTR_STRIDE, nullptr, abort);
   __shared__ ValIdx shv[WG / WAVE + 1];
   __shared__ double sh[LU_NB + 64 * (LU_NB + 1) + LU_NB * 65];
   __shared__ int ipv[LU_NB];
@@ -2132,7 +2132,7 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
     }
     DBuf<unsigned> d_luctr;
     DBuf<int> d_lust;
-    d_luctr.alloc(std::max(1, maxcol));
+    d_luctr.alloc((size_t)std::max(1, maxcol) * CTR_STRIDE);
     d_lust.alloc(std::max(1, maxcol));
     // the compressions of a round are spread over teams of G workgroups each (cooperative
     // launch, so every team is co-resident); a member keeps its share of a pivoted QR's columns
@@ -2177,7 +2177,8 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
     DBuf<Cand> d_part;
     DBuf<int> d_abort;
     DBuf<double> d_pub;
-    d_ctr.alloc((size_t)3 * std::max(1, maxcol));  // a team's counter, then two per compression for its halves
+    // a team's counter, then two per compression for its halves, CTR_STRIDE apart
+    d_ctr.alloc((size_t)3 * std::max(1, maxcol) * CTR_STRIDE);
     d_part.alloc((size_t)std::max(1, maxcol) * 4 * GMAX);
     d_pub.alloc((size_t)std::max(1, maxcol) * 2 * GMAX * vlen);
     d_abort.alloc(1);
@@ -2211,7 +2212,7 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
         size_t shm = base;
         team_shape(ne, G, lcols, shm);
         if (verbose()) ++team_hist[{G, lcols}];
-        if (G > 1) AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * 3 * ne, st));
+        if (G > 1) AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * 3 * ne * CTR_STRIDE, st));
         {
           Cand* partp = d_part.p;
           unsigned* ctrp = d_ctr.p;
@@ -2256,7 +2257,7 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
         int* lst = d_lust.p;
         int* abortp = d_abort.p;
         if (Gl > 1) {
-          AIFMM_HIP(hipMemsetAsync(d_luctr.p, 0, sizeof(unsigned) * nbox, st));
+          AIFMM_HIP(hipMemsetAsync(d_luctr.p, 0, sizeof(unsigned) * nbox * CTR_STRIDE, st));
           int Glv = Gl;
           void* args[] = {(void*)&PP, (void*)&bsys, (void*)&boxes, &dynb, &Glv, &lctr, &lst, &abortp};
           AIFMM_HIP(hipLaunchCooperativeKernel((const void*)k_elim_lu, dim3(nbox * Gl), dim3(WG), args, lu_shm, st));

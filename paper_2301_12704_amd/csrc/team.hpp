@@ -19,6 +19,10 @@ struct Cand {
   int p, pad;
 };
 
+// Barrier counters of concurrent teams sit CTR_STRIDE words (256 bytes) apart, so the teams'
+// atomics and polls do not contend for one cache line.
+constexpr int CTR_STRIDE = 64;
+
 template <int NT>
 struct Team {
   int member = 0, G = 1;      // this workgroup's index in the team, team size
@@ -62,7 +66,8 @@ struct Team {
       unsigned target = epoch * (unsigned)G;
       unsigned spins = 0;
       while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        // the abort flag (one word every team polls) is read every 64th poll
+        if ((spins & 63) == 63 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         __builtin_amdgcn_s_sleep(2);
         if (++spins > max_spins) {
           atomicExch(abort, 1);
@@ -486,7 +491,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
   constexpr int NS = reg_slots<RMAX, R>();
   constexpr int NREG = NGW * NS;  // own columns in registers
   // loads in flight a lane for the columns outside registers (fewer beside more register slots)
-  constexpr int GB = NS == 0 ? COL_BG : NS >= 3 ? 2 : NS == 2 ? 4 : 8;
+  constexpr int GB = NS == 0 ? COL_BG : NS >= 3 ? 2 : 8;
   const int PS = NS > 0 ? PL * RMAX : m;  // entries of a publication slot
   // pivot ties: norms within a relative band of the largest (1e-11 in FP64, 2e-6 in FP32)
   const R keep = sizeof(R) == 4 ? R(1.0 - 2e-6) : R(1.0 - 1e-11);
