@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
   int e = blockIdx.x / G;
   if (e >= nent) return;
   Team<CT> T;
-  T.init(blockIdx.x - e * G, G, ctr + (size_t)e * CTR_STRIDE, part + (size_t)e * 4 * G, abort);
+  T.init(blockIdx.x - e * G, G, ctr + (size_t)e * CTR_STRIDE, part + (size_t)e * 4 * G * CAND_STRIDE, abort);
   // a team of two or more runs the independent pivoted QRs of the compression concurrently on
   // its two halves (sub-teams A: members 0 .. GA-1 and B: the rest), each with its own barrier
   // counter, exchange slots, publication slots and workspace, and joins them with a team barrier
@@ -109,9 +109,9 @@ __global__ void __launch_bounds__(CT) k_compress(const LevelPtrs* __restrict__ P
   Team<CT> C;
   if (split)
     C.init(inA ? T.member : T.member - GA, inA ? GA : G - GA, ctr + (size_t)(nent + 2 * e + (inA ? 0 : 1)) * CTR_STRIDE,
-           part + (size_t)e * 4 * G + 2 * G + (inA ? 0 : 2 * GA), abort);
+           part + ((size_t)e * 4 * G + 2 * G + (inA ? 0 : 2 * GA)) * CAND_STRIDE, abort);
   else
-    C.init(0, 1, ctr + (size_t)e * CTR_STRIDE, part + (size_t)e * 4 * G, abort);
+    C.init(0, 1, ctr + (size_t)e * CTR_STRIDE, part + (size_t)e * 4 * G * CAND_STRIDE, abort);
   RoundEntry R = ent[e];
   const LevelPtrs& P = PP[R.sys];
   const double tol = P.tol;
@@ -2179,7 +2179,7 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
     DBuf<double> d_pub;
     // a team's counter, then two per compression for its halves, CTR_STRIDE apart
     d_ctr.alloc((size_t)3 * std::max(1, maxcol) * CTR_STRIDE);
-    d_part.alloc((size_t)std::max(1, maxcol) * 4 * GMAX);
+    d_part.alloc((size_t)std::max(1, maxcol) * 4 * GMAX * CAND_STRIDE);
     d_pub.alloc((size_t)std::max(1, maxcol) * 2 * GMAX * vlen);
     d_abort.alloc(1);
     d_part.zero(st);

@@ -22,6 +22,8 @@ struct Cand {
 // Barrier counters of concurrent teams sit CTR_STRIDE words (256 bytes) apart, so the teams'
 // atomics and polls do not contend for one cache line.
 constexpr int CTR_STRIDE = 64;
+// The members' exchange slots sit CAND_STRIDE entries (192 bytes) apart for the same reason.
+constexpr int CAND_STRIDE = 8;
 
 template <int NT>
 struct Team {
@@ -29,7 +31,7 @@ struct Team {
   int gtid = 0, GT = NT;      // team thread index and count
   int cid = 0;                // column-interleaved team thread index: member + G * thread
   unsigned* ctr = nullptr;    // barrier counter (zero at launch)
-  Cand* part = nullptr;       // 2 x G exchange slots (double-buffered)
+  Cand* part = nullptr;       // 2 x G exchange slots, CAND_STRIDE apart (double-buffered)
   int* abort = nullptr;       // set when a barrier waited too long; every later barrier returns
   unsigned epoch = 0;
   int slot = 0;
@@ -81,10 +83,11 @@ struct Team {
     bad = s_bad != 0;
   }
 
-  // Publish one value per member and return all G of them (the same array on every thread).
+  // Publish one value per member and return all G of them (the same array on every thread;
+  // member q's value at q CAND_STRIDE).
   __device__ __attribute__((always_inline)) const Cand* exchange(const Cand& c) {
-    Cand* p = part + slot * G;
-    if (threadIdx.x == 0) p[member] = c;
+    Cand* p = part + (size_t)slot * G * CAND_STRIDE;
+    if (threadIdx.x == 0) p[member * CAND_STRIDE] = c;
     sync();
     slot ^= 1;
     return p;
@@ -97,7 +100,7 @@ struct Team {
     const Cand* all = exchange(Cand{r.v, 0.0, r.i, 0});
     ValIdx b{-1.0, INT_MAX};
     for (int q = 0; q < G; ++q) {
-      ValIdx c{all[q].mv, all[q].p};
+      ValIdx c{all[q * CAND_STRIDE].mv, all[q * CAND_STRIDE].p};
       if (vi_better(c, b)) b = c;
     }
     return b;
@@ -476,11 +479,11 @@ __device__ __attribute__((always_inline)) inline void reg_put(const R (&ra)[NS][
 // column in pub before the exchange (2 G slots of m entries, of 16 RMAX with the register
 // tier); a lone workgroup stages a register column in vsh.  The pivot column is read by every
 // member to form the reflector (vsh: LDS of max(m, 16 RMAX) entries).
-// Reflector s is written to row s of V (ldv) with V[s][s] = 1, its scale to tau[s]; nrm
-// (device memory, n) holds each column's trailing norm and lnr (LDS, n / G entries) the
-// member's own columns' norms (column c at lnr[c / G]).  M is left unchanged (R is not
-// formed).  Returns the rank; ratio (if given) receives |R_kk| / (tol |R_11|) of the last kept
-// and of the first rejected pivot.
+// Reflector s is written to row s of V (ldv) with V[s][s] = 1, its scale to tau[s]; lnr (LDS,
+// n / G entries) holds the member's own columns' trailing norms (column c at lnr[c / G]), and
+// nrm (device memory, 2 entries) passes the pivot's norm after an ambiguous merge.  M is left
+// unchanged (R is not formed).  Returns the rank; ratio (if given) receives |R_kk| / (tol |R_11|)
+// of the last kept and of the first rejected pivot.
 template <int NT, int RMAX, class R>
 __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, double tol, R* V, int ldv, R* tau,
                              R* nrm, R* lnr, ValIdx* shv, R* vsh, int* pos, int* at, double* ratio, R* lcol,
@@ -524,11 +527,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
         if (i < m) t = fma(a, a, t);
       }
       t = lane_sum16(t);
-      if (own && lane == 0) {
-        R v = sqrt(t);
-        nrm[c] = v;
-        lnr[lc] = v;
-      }
+      if (own && lane == 0) lnr[lc] = sqrt(t);
     }
   }
   for (int lc = NREG + grp; lc < nloc; lc += NGW) {
@@ -552,11 +551,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       }
     }
     t = lane_sum16(t);
-    if (lane == 0) {
-      R v = sqrt(t);
-      nrm[c] = v;
-      lnr[lc] = v;
-    }
+    if (lane == 0) lnr[lc] = sqrt(t);
   }
   for (int c = threadIdx.x; c < n; c += NT) {
     pos[c] = c;
@@ -606,7 +601,8 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       // across the wave (any pairing gives the same state)
       PivState g{-1.0, -1.0, INT_MAX, 0};
       for (int q = (int)threadIdx.x % WAVE; q < T.G; q += WAVE)
-        g = piv_merge(g, PivState{all[q].mv, all[q].nv, all[q].p, all[q].pad}, keep);
+        g = piv_merge(g, PivState{all[q * CAND_STRIDE].mv, all[q * CAND_STRIDE].nv, all[q * CAND_STRIDE].p,
+                                  all[q * CAND_STRIDE].pad}, keep);
       ps = wave_pivmerge(g, keep);
     }
     int pp = ps.p;
@@ -629,16 +625,9 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     if (pp < s || pp >= n) break;  // no live column (cannot happen while s < min(m, n))
     const int cp = at[pp];
     // the pivot's norm: carried by the merged candidate state (its nv is the norm of the column
-    // at position p); the exact fallback reads the owner's copy in device memory
-    const R bv = amb ? nrm[cp] : (R)ps.nv;
-    if (s == 0) {
-      r11 = bv;
-      if (r11 == R(0)) break;
-    } else if (bv <= tolr * r11) {
-      next = (double)bv / ((double)tolr * (double)r11);
-      break;
-    }
-    kept = (double)bv / ((double)tolr * (double)r11);
+    // at position p); after the exact fallback the owner publishes it (nrm, alternating with
+    // the step parity) with the column
+    R bv = (R)ps.nv;
     // where the pivot column is read from: the owner's publication slot (a team), the LDS
     // staging copy in vsh (a lone workgroup's register column), or its storage
     const R* pcol;
@@ -647,17 +636,35 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       const int owner = cp % T.G;
       R* oslot = pub + ((size_t)(s & 1) * T.G + owner) * PS;
       if (amb) {  // the chosen column may not be its owner's candidate: publish it
-        if (T.member == owner) publish(cp, oslot, s);
+        if (T.member == owner) {
+          publish(cp, oslot, s);
+          if (threadIdx.x == 0) nrm[s & 1] = lnr[cp / T.G];
+        }
         T.sync();
         if (T.bad) break;
+        bv = nrm[s & 1];
       }
       pcol = oslot;
-    } else if (cp / T.G < NREG) {
-      publish(cp, vsh, s);
-      staged = true;
-      pcol = vsh;
     } else {
-      pcol = colp(cp / T.G, cp);
+      if (amb) bv = lnr[cp / T.G];
+      pcol = nullptr;
+    }
+    if (s == 0) {
+      r11 = bv;
+      if (r11 == R(0)) break;
+    } else if (bv <= tolr * r11) {
+      next = (double)bv / ((double)tolr * (double)r11);
+      break;
+    }
+    kept = (double)bv / ((double)tolr * (double)r11);
+    if (T.G == 1) {
+      if (cp < NREG) {
+        publish(cp, vsh, s);
+        staged = true;
+        pcol = vsh;
+      } else {
+        pcol = colp(cp, cp);
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -739,11 +746,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       for (int k = 0; k < NS; ++k) {
         const R tt = lane_sum16(t[k]);
         const int lc = grp + NGW * k;
-        if (lane == 0 && lc < nloc && pos[T.member + T.G * lc] > s) {
-          R v = sqrt(tt);
-          nrm[T.member + T.G * lc] = v;
-          lnr[lc] = v;
-        }
+        if (lane == 0 && lc < nloc && pos[T.member + T.G * lc] > s) lnr[lc] = sqrt(tt);
       }
     }
     const int r0 = s + ((lane - s) & (PL - 1));  // this lane's first row >= s
@@ -763,11 +766,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
         t = inl ? grp_axpy<COL_B, true>(col, vsh, r0, m, s, w) : grp_axpy<COL_BG, true>(col, vsh, r0, m, s, w);
       }
       t = lane_sum16(t);
-      if (lane == 0) {
-        R v = sqrt(t);
-        nrm[c] = v;
-        lnr[lc] = v;
-      }
+      if (lane == 0) lnr[lc] = sqrt(t);
     }
     __syncthreads();
   }
