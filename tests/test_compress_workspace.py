@@ -12,7 +12,8 @@ and checks, for every capacity the workloads reach (95 to 949 at N=262144, 2D) a
   storage is placed on a region that still holds a finished block;
 - on split teams, the two halves never touch the same region between two joins;
 - the exchange slots, barrier counters and publication slots of every team size up to 128
-  members stay inside their allocations;
+  members stay inside their allocations, and the host's team shapes keep LDS within the
+  kernel's limit and teams co-resident, with the register tier covering every row;
 - the 16-lane groups of the column passes cover the rows s..m-1 of a column exactly once, for
   the batch depths used (16) and others (4, 48).
 """
@@ -155,23 +156,86 @@ def test_dataflow_check_catches_clobbered_block():
 
 
 # ---- team exchange slots, counters and publication slots
+CAND_STRIDE, CTR_STRIDE = 8, 64   # exchange slots 8 entries (192 bytes) apart, counters 64 words
+
+
+def reg_rows(cap):
+    """Rows a lane of the register column tier holds (16 lanes a column), 0 beyond 1024 rows."""
+    for r in (16, 32, 40, 64):
+        if 16 * r >= cap:
+            return r
+    return 0
+
+
+def reg_slots(rmax, rs):
+    """Register slots a 16-lane group holds: 64 FP64 values a lane, FP32 at most 4 slots."""
+    if rmax == 0:
+        return 0
+    return max(1, 64 // rmax) if rs == 8 else min(4, 128 // rmax)
+
+
 @pytest.mark.parametrize("G", list(range(1, 129)))
-def test_team_slots_inside(G):
-    GMAX, maxcol, cap = 128, 7, 949
+@pytest.mark.parametrize("cap", [95, 262, 610, 949, 958, 1024, 1500])
+def test_team_slots_inside(G, cap):
+    GMAX, maxcol = 128, 7
     GA = G // 2
+    vlen = max(cap, 16 * reg_rows(cap))    # reflector and publication-slot length
     for e in range(maxcol):
-        # whole team: 2 G exchange slots; halves: 2 GA and 2 (G - GA) after them
+        # whole team: 2 G exchange slots; halves: 2 GA and 2 (G - GA) after them; member q of
+        # slot t at (t G + q) CAND_STRIDE
         lo, hi = e * 4 * G, e * 4 * G + 2 * G
         if G > 1:
             hiA = e * 4 * G + 2 * G + 2 * GA
             hiB = hiA + 2 * (G - GA)
             hi = max(hi, hiB)
-        assert 0 <= lo and hi <= maxcol * 4 * GMAX
-        # counters: the team's at e, the halves' at nent + 2 e (+1)
-        assert max(e, maxcol + 2 * e + 1) < 3 * maxcol
-        # publication: 2 G cap per compression, half B's slots after half A's 2 GA cap
-        pub_hi = e * 2 * G * cap + 2 * GA * cap + (2 * (G - GA)) * cap
-        assert pub_hi <= maxcol * 2 * GMAX * cap
+        assert 0 <= lo and hi * CAND_STRIDE <= maxcol * 4 * GMAX * CAND_STRIDE
+        # counters: the team's at e, the halves' at nent + 2 e (+1), CTR_STRIDE words apart
+        assert (max(e, maxcol + 2 * e + 1) + 1) * CTR_STRIDE <= 3 * maxcol * CTR_STRIDE
+        # publication: 2 G vlen per compression, half B's slots after half A's 2 GA vlen; a
+        # slot of a half-team of g members written at ((s & 1) g + member) PS .. + PS - 1 with
+        # PS = 16 RMAX (register tier) or m <= cap, both <= vlen
+        for g, base in ((GA, e * 2 * G * vlen), (G - GA, e * 2 * G * vlen + 2 * GA * vlen)):
+            if g == 0:
+                continue
+            PS = 16 * reg_rows(cap) if reg_rows(cap) else cap
+            assert PS <= vlen
+            top = base + (2 * g - 1) * PS + PS  # odd step, last member
+            assert top <= e * 2 * G * vlen + 2 * G * vlen <= maxcol * 2 * GMAX * vlen
+
+
+@pytest.mark.parametrize("rs", [8, 4])
+@pytest.mark.parametrize("cap", list(range(1, 2049, 37)) + [95, 256, 257, 262, 512, 610, 640, 641, 958, 1024, 1025, 2048])
+def test_register_tier_and_team_shape(cap, rs):
+    """The host's team shape: LDS within the kernel's limit, teams co-resident, every column of
+    a pivoted QR (n <= 2 cap) held in registers, LDS or the workspace region, and the register
+    tier's rows (lane q: q, q + 16, ..) covering every row m <= cap."""
+    CT, GMAX, lds_max, coop = 512, 128, 152 * 1024, 256
+    rmax = reg_rows(cap)
+    if rmax:
+        assert 16 * rmax >= cap
+        assert sorted(q + 16 * u for q in range(16) for u in range(rmax))[:cap] == list(range(cap))
+    nreg = (CT // 16) * reg_slots(rmax, rs)
+    vlen = max(cap, 16 * rmax)
+    base = vlen * rs + 4 * cap * 4 + 2 * cap * rs
+    if base > lds_max:
+        return  # the library reports AIFMM_ERR_CAPACITY
+    colb = (cap | 1) * rs
+    ldsc = (lds_max - base) // colb
+    for ne in (1, 2, 8, 37, 157, 300):
+        need = 2 * cap
+        h = max(1, min(-(-need // max(1, nreg + ldsc)), 64, GMAX // 2))
+        G = 1
+        if ne * 2 <= coop:
+            G = 2 * min(h, coop // (2 * ne))
+        share = -(-need // (G // 2)) if G > 1 else need
+        lcols = min(ldsc, max(0, share - nreg))
+        shm = base + lcols * colb
+        assert shm <= lds_max
+        assert G == 1 or (G % 2 == 0 and 2 <= G <= GMAX and ne * G <= coop)
+        # a member's columns: registers, then LDS, then the workspace (column c at c m of a
+        # 2 cap^2 region, c < n <= 2 cap, m <= cap)
+        assert share <= nreg + lcols + max(0, share - nreg - lcols)
+        assert (2 * cap - 1) * cap + cap <= 2 * cap * cap
 
 
 # ---- the 16-lane groups of the column passes

@@ -33,14 +33,17 @@ CASES = [
 ]
 
 # Switches of the library that change which kernel path runs, never an operation's order:
-# compression columns in the workspace instead of LDS, with teams of up to 48 members (the
-# shapes the large workloads run) or of at most 4, lone workgroups only, pivot-block LU
-# panels factored in device memory instead of LDS (the path of pivot blocks above ~1050 rows),
-# and the pivot-block inverse by the left-looking kernel (the small cases otherwise take the
-# right-looking one).
+# compression columns without the register tier (LDS, then workspace); in registers with the
+# rest in the workspace on two-member teams; all in the workspace on teams of up to 128
+# members (every member's share small, some members with no column) or of at most 4; lone
+# workgroups only; pivot-block LU panels factored in device memory instead of LDS (the path of
+# pivot blocks above ~1050 rows); and the pivot-block inverse by the left-looking kernel (the
+# small cases otherwise take the right-looking one).
 SWITCHES = [
-    ("workspace_columns_large_teams", {"AIFMM_NO_LDS_COLUMNS": "1", "AIFMM_TEAM_ELEMS": "1024"}),
-    ("workspace_columns_small_teams", {"AIFMM_NO_LDS_COLUMNS": "1", "AIFMM_TEAM_ELEMS": "1024",
+    ("no_register_columns", {"AIFMM_NO_REG_COLUMNS": "1"}),
+    ("register_then_workspace_columns", {"AIFMM_NO_LDS_COLUMNS": "1", "AIFMM_TEAM_MAX": "1"}),
+    ("workspace_columns_large_teams", {"AIFMM_NO_REG_COLUMNS": "1", "AIFMM_NO_LDS_COLUMNS": "1"}),
+    ("workspace_columns_small_teams", {"AIFMM_NO_REG_COLUMNS": "1", "AIFMM_NO_LDS_COLUMNS": "1",
                                        "AIFMM_TEAM_MAX": "2"}),
     ("no_teams", {"AIFMM_NO_TEAMS": "1"}),
     ("lu_panels_in_memory", {"AIFMM_NO_LDS_PANELS": "1"}),
