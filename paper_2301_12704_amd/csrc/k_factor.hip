@@ -2170,7 +2170,8 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
       if (coop_c > 0 && (int64_t)ne * 2 <= coop_c) G = 2 * std::min<int64_t>(h, coop_c / (2 * (int64_t)ne));
       const int share = G > 1 ? cdiv(need, G / 2) : need;  // a member's columns of one QR
       lcols = std::min(ldsc, std::max(0, share - nreg));
-      shm = base + (size_t)lcols * colb;
+      // the register tier's Q formation stages FQ_RB reflectors of 16 RMAX entries there too
+      shm = base + std::max((size_t)lcols * colb, rmax > 0 ? (size_t)FQ_RB * 16 * rmax * rs : (size_t)0);
     };
     std::map<std::pair<int, int>, int> team_hist;  // (team size, LDS columns a member) -> rounds
     DBuf<unsigned> d_ctr;

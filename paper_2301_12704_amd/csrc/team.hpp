@@ -440,6 +440,8 @@ __device__ inline R grp_axpy(R* col, const R* v, int r0, int m, int s, R w) {
 // reflector entries read ahead by the register tier's row loops (a scheduling barrier between
 // groups keeps the compiler from issuing all RMAX loads at once)
 constexpr int REG_CHUNK = 8;
+// reflectors the register-tier Q formation stages in LDS at a time
+constexpr int FQ_RB = 8;
 // Register slots a lane group holds (RMAX rows each): 64 FP64 values a lane (at least one
 // slot), or up to 4 slots of FP32, the same for the pivoted QR and the Q formation.  Larger
 // tiers make the compiler spill slots in the pivot-step loop (the kernel holds 512 threads, so
@@ -783,9 +785,10 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
 // j is owned by member (j - c0) mod G (own index lj = (j - c0) / G) and formed by one lane
 // group through all reflectors (row sums in the fixed order of lane_sum16), then written to
 // Q, so members only synchronise at the end.  With the register tier (RMAX > 0) the columns
-// are independent, so the member forms them in passes of (NT / 16) NS register columns;
-// without it a column lives in the member's LDS (lcol, lcols columns of stride m | 1) or the
-// workspace gcol (column j at gcol + (j - c0) m).
+// are independent, so the member forms them in passes of (NT / 16) NS register columns, with
+// the reflectors staged in lcol (FQ_RB 16 RMAX entries, which the host reserves); without it a
+// column lives in the member's LDS (lcol, lcols columns of stride m | 1) or the workspace gcol
+// (column j at gcol + (j - c0) m).
 template <int NT, int RMAX, class R>
 __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, int ldv, const R* tau, R* Q, int ldq,
                                R* vsh, int c0, R* lcol, int lcols, R* gcol) {
@@ -796,10 +799,15 @@ __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, 
   const int nloc = (q - c0 - T.member + T.G - 1) / T.G;  // own columns: j = c0 + member + G lj
   if constexpr (NS > 0) {
     constexpr int NREG = NGW * NS;
-    // every row of every slot, with vsh zero outside the rows s..m-1: the columns hold exact
-    // zeros beyond row m, and the rows of a column that a reflector does not reach are +0 or
-    // the 1 of e_j, which adding exact zeros leaves as they are
-    for (int i = m + (int)threadIdx.x; i < PL * RMAX; i += NT) vsh[i] = R(0);
+    // every row of every slot, with the reflector zero outside the rows s..m-1: the columns
+    // hold exact zeros beyond row m, and the rows of a column that a reflector does not reach
+    // are +0 or the 1 of e_j, which adding exact zeros leaves as they are.  The reflectors are
+    // staged FQ_RB at a time in the member's LDS column region (free here: FQ_RB rows of
+    // 16 RMAX entries) and applied one after another, in descending order, without a barrier
+    // between them (the columns are independent and the staged rows read-only).
+    constexpr int RR = PL * RMAX;
+    R* vb = lcol;
+    __shared__ R tb[FQ_RB];
     for (int p0 = 0; p0 < nloc; p0 += NREG) {
       R ra[NS][RMAX];
       // the first own column of the pass through an empty asm statement: the compiler cannot
@@ -813,31 +821,40 @@ __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, 
 #pragma unroll
         for (int u = 0; u < RMAX; ++u) ra[k][u] = (lane + PL * u == j) ? R(1) : R(0);
       }
-      for (int s = rank - 1; s >= 0; --s) {
-        const R tv = tau[s];
+      for (int sb = rank - 1; sb >= 0; sb -= FQ_RB) {
+        const int nb = sb + 1 < FQ_RB ? sb + 1 : FQ_RB;  // reflectors sb, sb - 1, .., sb - nb + 1
         __syncthreads();
-        for (int i = threadIdx.x; i < m; i += NT) vsh[i] = i >= s ? V[(size_t)s * ldv + i] : R(0);
-        __syncthreads();
-        R acc[NS], w[NS];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) acc[k] = 0;
-#pragma unroll
-        for (int u = 0; u < RMAX; ++u) {
-          if (u % REG_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
-          const R vv = vsh[lane + PL * u];
-#pragma unroll
-          for (int k = 0; k < NS; ++k) acc[k] = fma(vv, ra[k][u], acc[k]);
+        for (int idx = threadIdx.x; idx < nb * RR; idx += NT) {
+          const int b = idx / RR, i = idx - b * RR, s = sb - b;
+          vb[idx] = (i >= s && i < m) ? V[(size_t)s * ldv + i] : R(0);
         }
+        if ((int)threadIdx.x < nb) tb[threadIdx.x] = tau[sb - (int)threadIdx.x];
+        __syncthreads();
+        for (int b = 0; b < nb; ++b) {
+          const R* vr = vb + b * RR;
+          const R tv = tb[b];
+          R acc[NS], w[NS];
 #pragma unroll
-        for (int k = 0; k < NS; ++k) w[k] = lane_sum16(acc[k]) * tv;
-        // vsh is read again rather than kept: its RMAX values would double the tier's registers
-        asm volatile("" ::: "memory");
+          for (int k = 0; k < NS; ++k) acc[k] = 0;
 #pragma unroll
-        for (int u = 0; u < RMAX; ++u) {
-          if (u % REG_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
-          const R vv = vsh[lane + PL * u];
+          for (int u = 0; u < RMAX; ++u) {
+            if (u % REG_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
+            const R vv = vr[lane + PL * u];
 #pragma unroll
-          for (int k = 0; k < NS; ++k) ra[k][u] = fma(-w[k], vv, ra[k][u]);
+            for (int k = 0; k < NS; ++k) acc[k] = fma(vv, ra[k][u], acc[k]);
+          }
+#pragma unroll
+          for (int k = 0; k < NS; ++k) w[k] = lane_sum16(acc[k]) * tv;
+          // the row is read again rather than kept: its RMAX values would double the tier's
+          // registers
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int u = 0; u < RMAX; ++u) {
+            if (u % REG_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
+            const R vv = vr[lane + PL * u];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) ra[k][u] = fma(-w[k], vv, ra[k][u]);
+          }
         }
       }
 #pragma unroll

@@ -229,7 +229,8 @@ def test_register_tier_and_team_shape(cap, rs):
             G = 2 * min(h, coop // (2 * ne))
         share = -(-need // (G // 2)) if G > 1 else need
         lcols = min(ldsc, max(0, share - nreg))
-        shm = base + lcols * colb
+        # the same LDS region stages the register Q formation's 8 reflectors of 16 RMAX entries
+        shm = base + max(lcols * colb, 8 * 16 * rmax * rs)
         assert shm <= lds_max
         assert G == 1 or (G % 2 == 0 and 2 <= G <= GMAX and ne * G <= coop)
         # a member's columns: registers, then LDS, then the workspace (column c at c m of a
