@@ -2213,7 +2213,11 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
         size_t shm = base;
         team_shape(ne, G, lcols, shm);
         if (verbose()) ++team_hist[{G, lcols}];
-        if (G > 1) AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * 3 * ne * CTR_STRIDE, st));
+        if (G > 1) {
+          AIFMM_HIP(hipMemsetAsync(d_ctr.p, 0, sizeof(unsigned) * 3 * ne * CTR_STRIDE, st));
+          // exchange slots and the members' exchange flags start at zero in every launch
+          AIFMM_HIP(hipMemsetAsync(d_part.p, 0, sizeof(Cand) * (size_t)ne * 4 * G * CAND_STRIDE, st));
+        }
         {
           Cand* partp = d_part.p;
           unsigned* ctrp = d_ctr.p;

@@ -19,11 +19,31 @@ struct Cand {
   int p, pad;
 };
 
+// Pivot candidate state for one pass over the live columns: the largest norm mx, the lowest
+// position p among the columns whose norm is >= keep * mx, that column's norm nv, and amb set
+// when merging lost the information needed to know p exactly (a column within the band of a
+// smaller maximum that may or may not reach the band of the larger one).  Merging is
+// associative; when amb is clear, p is exactly the pivot of the two-pass rule.
+struct PivState {
+  double mx, nv;
+  int p, amb;
+};
 // Barrier counters of concurrent teams sit CTR_STRIDE words (256 bytes) apart, so the teams'
 // atomics and polls do not contend for one cache line.
 constexpr int CTR_STRIDE = 64;
 // The members' exchange slots sit CAND_STRIDE entries (192 bytes) apart for the same reason.
 constexpr int CAND_STRIDE = 8;
+
+// Device-scope (all compute units) stores and loads: relaxed atomics at agent scope, which
+// write through to and read from the device's point of coherence.
+template <class T_>
+__device__ __attribute__((always_inline)) inline void st_dev(T_* p, T_ v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T_>
+__device__ __attribute__((always_inline)) inline T_ ld_dev(const T_* p) {
+  return __hip_atomic_load(const_cast<T_*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <int NT>
 struct Team {
@@ -34,6 +54,7 @@ struct Team {
   Cand* part = nullptr;       // 2 x G exchange slots, CAND_STRIDE apart (double-buffered)
   int* abort = nullptr;       // set when a barrier waited too long; every later barrier returns
   unsigned epoch = 0;
+  unsigned xep = 0;           // exchanges by flags so far (exchange_merge)
   int slot = 0;
   bool bad = false;           // the abort flag was seen at the last barrier: data exchanged through
                               // the team may be stale, so callers stop using it and exit
@@ -91,6 +112,71 @@ struct Team {
     sync();
     slot ^= 1;
     return p;
+  }
+
+  // Publish one candidate state per member and return the merge of all G of them (the same
+  // on every thread), without a team barrier: every thread waits for its own device-scope
+  // publication stores, the workgroup synchronises, thread 0 stores the member's state
+  // (device scope) into the exchange slot, waits for it, and then raises the member's flag
+  // (the member's count of such exchanges, in the unused part of its slot-0 entry; zero at
+  // launch).  Lane q of the first wave waits for member q's flag to reach this exchange's count
+  // and reads member q's state; the wave merges them by a tree.  Data read after a member's
+  // flag (its state, its publication slot) is read with device-scope loads.  A slot is
+  // rewritten two exchanges later, which no member reaches before every member has raised its
+  // flag for the exchange in between, so double-buffered slots suffice.  The wait is bounded
+  // like sync(); on expiry, or with the abort flag raised, bad is set.
+  template <class R, class Merge, class WaveMerge>
+  __device__ __attribute__((always_inline)) PivState exchange_merge(const Cand& c, R keep, PivState* shres,
+                                                                   Merge merge, WaveMerge wmerge,
+                                                                   unsigned max_spins = 1u << 24) {
+    __shared__ int s_bad;
+    ++xep;
+    Cand* p = part + (size_t)slot * G * CAND_STRIDE;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's publication stores are done
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Cand* q = p + member * CAND_STRIDE;
+      st_dev(&q->mv, c.mv);
+      st_dev(&q->nv, c.nv);
+      st_dev(&q->p, c.p);
+      st_dev(&q->pad, c.pad);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      st_dev((unsigned*)(part + (size_t)member * CAND_STRIDE + 1), xep);
+    }
+    if (threadIdx.x < WAVE) {
+      PivState g{-1.0, -1.0, INT_MAX, 0};
+      int ok = 1;
+      for (int q = (int)threadIdx.x; q < G && ok; q += WAVE) {
+        const unsigned* fq = (const unsigned*)(part + (size_t)q * CAND_STRIDE + 1);
+        unsigned spins = 0;
+        while (ld_dev(fq) < xep) {
+          if ((spins & 63) == 63 && ld_dev(abort)) {
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > max_spins) {
+            atomicExch(abort, 1);
+            ok = 0;
+            break;
+          }
+        }
+        if (!ok) break;
+        asm volatile("" ::: "memory");
+        const Cand* cq = p + q * CAND_STRIDE;
+        g = merge(g, PivState{ld_dev(&cq->mv), ld_dev(&cq->nv), ld_dev(&cq->p), ld_dev(&cq->pad)});
+      }
+      const int allok = __all(ok);
+      g = wmerge(g);
+      if (threadIdx.x == 0) {
+        shres[0] = g;
+        s_bad = !allok || ld_dev(abort) != 0;
+      }
+    }
+    __syncthreads();
+    bad = s_bad != 0;
+    slot ^= 1;
+    return shres[0];
   }
 
   // Team-wide argmax (ties to the lowest index); the same value on every thread of the team.
@@ -268,15 +354,6 @@ __device__ inline float dpp_mov(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-// Pivot candidate state for one pass over the live columns: the largest norm mx, the lowest
-// position p among the columns whose norm is >= keep * mx, that column's norm nv, and amb set
-// when merging lost the information needed to know p exactly (a column within the band of a
-// smaller maximum that may or may not reach the band of the larger one).  Merging is
-// associative; when amb is clear, p is exactly the pivot of the two-pass rule.
-struct PivState {
-  double mx, nv;
-  int p, amb;
-};
 template <class R>
 __device__ inline PivState piv_merge(const PivState& a, const PivState& b, R keep) {
   PivState r;
@@ -453,7 +530,8 @@ __host__ __device__ constexpr int reg_slots() {
 
 // Each value passes through an empty asm statement, so the compiler cannot merge the slots'
 // branches into one load of ra at the runtime index k (which would keep ra in scratch memory).
-template <int RMAX, int NS, class R>
+// DEV: device-scope stores (a team's publication slot), else plain stores (LDS).
+template <int RMAX, int NS, bool DEV, class R>
 __device__ __attribute__((always_inline)) inline void reg_put(const R (&ra)[NS][RMAX], int k, int lane, R* dst) {
 #pragma unroll
   for (int kk = 0; kk < NS; ++kk)
@@ -462,7 +540,8 @@ __device__ __attribute__((always_inline)) inline void reg_put(const R (&ra)[NS][
       for (int u = 0; u < RMAX; ++u) {
         R x = ra[kk][u];
         asm volatile("" : "+v"(x));
-        dst[lane + PL * u] = x;
+        if constexpr (DEV) st_dev(dst + lane + PL * u, x);
+        else dst[lane + PL * u] = x;
       }
     }
 }
@@ -492,6 +571,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
                              int lcols, R* pub, R* gcol) {
   __shared__ double shmx[NT / WAVE];
   __shared__ int shmn[NT / WAVE];
+  __shared__ PivState psres[1];
   constexpr int NGW = NT / PL;  // lane groups per workgroup
   constexpr int NS = reg_slots<RMAX, R>();
   constexpr int NREG = NGW * NS;  // own columns in registers
@@ -565,15 +645,22 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
   for (int i = m + (int)threadIdx.x; i < PL * RMAX; i += NT) vsh[i] = R(0);
   __syncthreads();
   // the rows s..m-1 of own column cc (lc = cc / G) into dst: by its lane group from registers
-  // (all 16 RMAX rows of the slot; the rows below s are not read), else by the whole workgroup
-  auto publish = [&](int cc, R* dst, int s) {
+  // (all 16 RMAX rows of the slot; the rows below s are not read), else by the whole
+  // workgroup; device-scope stores into a team's publication slot (dev), plain ones into LDS
+  auto publish = [&](int cc, R* dst, int s, bool dev) {
     const int lc = cc / T.G;
     if (lc < NREG) {
       if constexpr (NS > 0)
-        if (grp == lc % NGW) reg_put<RMAX, NS>(ra, lc / NGW, lane, dst);
+        if (grp == lc % NGW) {
+          if (dev) reg_put<RMAX, NS, true>(ra, lc / NGW, lane, dst);
+          else reg_put<RMAX, NS, false>(ra, lc / NGW, lane, dst);
+        }
     } else {
       const R* src = colp(lc, cc);
-      for (int i = s + threadIdx.x; i < m; i += NT) dst[i] = src[i];
+      if (dev)
+        for (int i = s + threadIdx.x; i < m; i += NT) st_dev(dst + i, src[i]);
+      else
+        for (int i = s + threadIdx.x; i < m; i += NT) dst[i] = src[i];
     }
   };
   int s = 0;
@@ -595,17 +682,14 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     // a team: each member publishes its candidate column (rows s..m-1) before the exchange, in
     // a buffer alternating with the step parity
     R* slot = pub + ((size_t)(s & 1) * T.G + T.member) * PS;
-    if (T.G > 1 && ps.p != INT_MAX) publish(at[ps.p], slot, s);
+    if (T.G > 1 && ps.p != INT_MAX) publish(at[ps.p], slot, s, true);
     if (T.G > 1) {
-      const Cand* all = T.exchange(Cand{ps.mx, ps.nv, ps.p, ps.amb});
+      // the members' states through their flags: lane q of the first wave takes members q,
+      // q + 64, ..., then a tree across the wave (any pairing gives the same state)
+      ps = T.exchange_merge(Cand{ps.mx, ps.nv, ps.p, ps.amb}, keep, psres,
+                            [&](const PivState& a, const PivState& b) { return piv_merge(a, b, keep); },
+                            [&](const PivState& a) { return wave_pivmerge(a, keep); });
       if (T.bad) break;  // the members' candidates may be stale: no pivot is taken from them
-      // the members' states: lane q of every wave takes members q, q + 64, ..., then a tree
-      // across the wave (any pairing gives the same state)
-      PivState g{-1.0, -1.0, INT_MAX, 0};
-      for (int q = (int)threadIdx.x % WAVE; q < T.G; q += WAVE)
-        g = piv_merge(g, PivState{all[q * CAND_STRIDE].mv, all[q * CAND_STRIDE].nv, all[q * CAND_STRIDE].p,
-                                  all[q * CAND_STRIDE].pad}, keep);
-      ps = wave_pivmerge(g, keep);
     }
     int pp = ps.p;
     bool amb = ps.amb != 0;
@@ -639,7 +723,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       R* oslot = pub + ((size_t)(s & 1) * T.G + owner) * PS;
       if (amb) {  // the chosen column may not be its owner's candidate: publish it
         if (T.member == owner) {
-          publish(cp, oslot, s);
+          publish(cp, oslot, s, true);
           if (threadIdx.x == 0) nrm[s & 1] = lnr[cp / T.G];
         }
         T.sync();
@@ -661,7 +745,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     kept = (double)bv / ((double)tolr * (double)r11);
     if (T.G == 1) {
       if (cp < NREG) {
-        publish(cp, vsh, s);
+        publish(cp, vsh, s, false);
         staged = true;
         pcol = vsh;
       } else {
@@ -676,15 +760,18 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
       pos[cp] = s;
       pos[cs] = pp;
     }
-    // the thread's rows of the pivot column are read together with x0 (one memory latency)
+    // the thread's rows of the pivot column are read together with x0 (one memory latency);
+    // a team's publication slot with device-scope loads
+    const bool pdev = T.G > 1;
+    auto pget = [&](int i) -> R { return pdev ? ld_dev(pcol + i) : pcol[i]; };
     constexpr int PV = 2;
     R pv[PV];
 #pragma unroll
     for (int k = 0; k < PV; ++k) {
       const int i = (int)threadIdx.x + k * NT;
-      pv[k] = (i > s && i < m) ? pcol[i] : R(0);
+      pv[k] = (i > s && i < m) ? pget(i) : R(0);
     }
-    R x0 = pcol[s];
+    R x0 = pget(s);
     R beta = x0 >= R(0) ? -bv : bv;
     R scale = x0 - beta;
     R tv = (beta - x0) / beta;
@@ -703,7 +790,7 @@ __device__ inline int t_cpqr(Team<NT>& T, int m, int n, const R* M, int ldm, dou
     for (int i = (int)threadIdx.x + PV * NT; i < m; i += NT) {
       R v = 0;
       if (i == s) v = 1;
-      else if (i > s) v = pcol[i] / scale;
+      else if (i > s) v = pget(i) / scale;
       vsh[i] = v;
       if (T.member == 0 && i >= s) V[(size_t)s * ldv + i] = v;
     }
