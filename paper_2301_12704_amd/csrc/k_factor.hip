@@ -1080,10 +1080,11 @@ __global__ void __launch_bounds__(NW * WAVE) k_elim_pinv(const LevelPtrs* __rest
 // operands converted to RT.  In FP64 every element is the ascending fused multiply-add chain
 // from zero over k (the slots past K add exact zeros at its end); in FP32 (the precision
 // form) the order inside an MFMA is the hardware's.  The wave computes columns 16 s .. 16 s + 15
-// (colslab) or rows 16 s .. 16 s + 15 of out into its workspace tmp (16 max(M, N) entries),
-// then writes them to dst (ldd, FP64).  dst may be the operand the slab came from: each output
-// column (colslab) or row depends only on the same column or row of that operand, and every
-// read has been consumed before the first write.
+// (colslab) or rows 16 s .. 16 s + 15 of out and writes them to dst (ldd, FP64): with up to 8
+// tiles of 16 from registers after one pass over K, else tile by tile through its workspace
+// tmp (16 max(M, N) entries).  dst may be the operand the slab came from: each output column
+// (colslab) or row depends only on the same column or row of that operand, and every read has
+// been consumed before the first write.
 template <class RT, class TA, class TB>
 __device__ inline void wave_xform_slab(int M, int N, int K, const TA* A, int64_t ai, int64_t ak, const TB* B, int64_t bk,
                                        int64_t bj, bool colslab, int s, RT* tmp, double* dst, int64_t ldd) {
@@ -1091,6 +1092,54 @@ __device__ inline void wave_xform_slab(int M, int N, int K, const TA* A, int64_t
   const int lane = threadIdx.x % WAVE, fr = lane % 16, fk = lane / 16;
   const int nt = colslab ? (M + 15) / 16 : (N + 15) / 16;
   const int nsteps = (K + 3) / 4;
+  constexpr int XT = 8;
+  if (nt <= XT) {
+    // up to 8 tiles: one pass over K for all of them (the slab's operand read once a step,
+    // each tile's accumulator in registers), then the results straight to dst.  Each tile's
+    // chain runs over the same steps in the same order as below.
+    constexpr int KQ = 4;
+    RT4 acc[XT];
+#pragma unroll
+    for (int t = 0; t < XT; ++t) acc[t] = RT4{0, 0, 0, 0};
+    const int RS = 16 * s;  // first row (or column) of the slab
+    for (int s0 = 0; s0 < nsteps; s0 += KQ) {
+      RT sl[KQ], ot[XT][KQ];
+#pragma unroll
+      for (int u = 0; u < KQ; ++u) {
+        const int k = 4 * (s0 + u) + fk;
+        const bool kin = s0 + u < nsteps && k < K;
+        // the slab's own operand: B's columns RS.. (colslab) or A's rows RS..
+        if (colslab) sl[u] = (kin && RS + fr < N) ? (RT)B[(int64_t)k * bk + (int64_t)(RS + fr) * bj] : (RT)0;
+        else sl[u] = (kin && RS + fr < M) ? (RT)A[(int64_t)(RS + fr) * ai + (int64_t)k * ak] : (RT)0;
+#pragma unroll
+        for (int t = 0; t < XT; ++t)
+          if (t < nt) {
+            const int o = 16 * t + fr;
+            if (colslab) ot[t][u] = (kin && o < M) ? (RT)A[(int64_t)o * ai + (int64_t)k * ak] : (RT)0;
+            else ot[t][u] = (kin && o < N) ? (RT)B[(int64_t)k * bk + (int64_t)o * bj] : (RT)0;
+          }
+      }
+#pragma unroll
+      for (int u = 0; u < KQ; ++u)
+        if (s0 + u < nsteps) {
+#pragma unroll
+          for (int t = 0; t < XT; ++t)
+            if (t < nt) acc[t] = colslab ? mfma16(ot[t][u], sl[u], acc[t]) : mfma16(sl[u], ot[t][u], acc[t]);
+        }
+    }
+    // every read of the slab has been consumed: write it in place
+#pragma unroll
+    for (int t = 0; t < XT; ++t)
+      if (t < nt) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = sizeof(RT) == 4 ? 4 * fk + q : fk + 4 * q;
+          const int r = (colslab ? 16 * t : RS) + rr, c = (colslab ? RS : 16 * t) + fr;
+          if (r < M && c < N) dst[(int64_t)r * ldd + c] = (double)acc[t][q];
+        }
+      }
+    return;
+  }
   constexpr int KC = 8;
   for (int t = 0; t < nt; ++t) {
     const int R0 = colslab ? 16 * t : 16 * s, C0 = colslab ? 16 * s : 16 * t;
@@ -1161,20 +1210,21 @@ __device__ inline void wave_xform_slab(int M, int N, int K, const TA* A, int64_t
 
 // The basis changes of a round (rows Z_x: L_x * block; columns y_x: block * R_x^* and the M2M
 // block R_x * block), in the precision RT of the compression, one 16-wide slab of one block
-// per wave, through wave_xform_slab.  Work items (entry, block, slab) are spread over all
-// waves of the grid; wstride is each wave's workspace (doubles).
+// per wave, through wave_xform_slab.  Work items (entry, block, slab group: the slabs g,
+// g + sgroups, ...) are spread over all waves of the grid; wstride is each wave's workspace
+// (doubles).
 template <class RT>
 __global__ void __launch_bounds__(WG) k_xform(const LevelPtrs* __restrict__ PP, const XformEntry* __restrict__ xe, int nx, const double* ws,
-                                              int64_t wsz, int cap, int maxblk, int nslab, int cols_side,
+                                              int64_t wsz, int cap, int maxblk, int sgroups, int cols_side,
                                               double* scratch, int64_t wstride) {
   const int64_t gw = (int64_t)blockIdx.x * (WG / WAVE) + threadIdx.x / WAVE;
   const int64_t nw = (int64_t)gridDim.x * (WG / WAVE);
   RT* tmp = (RT*)(scratch + gw * wstride);
   const size_t c2 = (size_t)cap * cap;
-  const int64_t total = (int64_t)nx * maxblk * nslab;
+  const int64_t total = (int64_t)nx * maxblk * sgroups;
   for (int64_t item = gw; item < total; item += nw) {
-    const int s = (int)(item % nslab);
-    const int64_t task = item / nslab;
+    const int g = (int)(item % sgroups);  // this item's slabs: g, g + sgroups, ...
+    const int64_t task = item / sgroups;
     const int t = (int)(task / maxblk), q = (int)(task - (int64_t)t * maxblk);
     const XformEntry X = xe[t];
     const LevelPtrs& P = PP[X.sys];
@@ -1198,8 +1248,8 @@ __global__ void __launch_bounds__(WG) k_xform(const LevelPtrs* __restrict__ PP, 
         cols = P.kP[x];
         ld = cols;
       }
-      if (16 * s >= cols) continue;
-      wave_xform_slab<RT>(knew, cols, kold, Lm, kold1, 1, B, ld, 1, true, s, tmp, B, ld);
+      for (int s = g; 16 * s < cols; s += sgroups)
+        wave_xform_slab<RT>(knew, cols, kold, Lm, kold1, 1, B, ld, 1, true, s, tmp, B, ld);
     } else {
       const RT* Rm = (const RT*)(ws + (size_t)X.pair * wsz) + (X.side ? 3 * c2 : c2);
       if (q < nil) {
@@ -1207,13 +1257,13 @@ __global__ void __launch_bounds__(WG) k_xform(const LevelPtrs* __restrict__ PP, 
         if (dbox == X.skip) continue;
         double* B = P.slab + P.il_slot[P.il_tr[P.il_off[x] + q]];
         int rows = P.kn[dbox], ld = P.n[x];
-        if (16 * s >= rows) continue;
-        wave_xform_slab<RT>(rows, knew, kold, B, ld, 1, Rm, 1, kold1, false, s, tmp, B, ld);
+        for (int s = g; 16 * s < rows; s += sgroups)
+          wave_xform_slab<RT>(rows, knew, kold, B, ld, 1, Rm, 1, kold1, false, s, tmp, B, ld);
       } else {
         double* B = P.slab + P.m2m_off[x];
         int cols = P.kP[x];
-        if (16 * s >= cols) continue;
-        wave_xform_slab<RT>(knew, cols, kold, Rm, kold1, 1, B, cols, 1, true, s, tmp, B, cols);
+        for (int s = g; 16 * s < cols; s += sgroups)
+          wave_xform_slab<RT>(knew, cols, kold, Rm, kold1, 1, B, cols, 1, true, s, tmp, B, cols);
       }
     }
   }
@@ -2233,17 +2283,21 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
         }
         AIFMM_HIP(hipEventRecord(ce.second, st));
         {
-          int64_t items = (int64_t)nx * maxblk * nslab;
+          // an item is a block and every sgroups-th of its slabs, with sgroups chosen so the
+          // items about fill the resident waves: each item reads its block's tables once
+          const int64_t blocks = std::max<int64_t>(1, (int64_t)nx * maxblk);
+          const int sgroups = (int)std::max<int64_t>(1, std::min<int64_t>(nslab, (int64_t)XG * (WG / WAVE) / blocks));
+          int64_t items = blocks * sgroups;
           int g64 = (int)std::min<int64_t>(XG, std::max<int64_t>(1, cdiv(items, WG / WAVE)));
           if (f32) {
-            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
+            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, sgroups, 0,
                                scratch.p, wstride);
-            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
+            hipLaunchKernelGGL(k_xform<float>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, sgroups, 1,
                                scratch.p, wstride);
           } else {
-            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, nslab, 0,
+            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, sgroups, 0,
                                scratch.p, wstride);
-            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, nslab, 1,
+            hipLaunchKernelGGL(k_xform<double>, dim3(g64), dim3(WG), 0, st, PP, ex, nx, ws.p, wsz, cap, maxblk, sgroups, 1,
                                scratch.p, wstride);
           }
         }
