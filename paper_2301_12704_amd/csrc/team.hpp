@@ -917,6 +917,9 @@ __device__ inline void t_formq(Team<NT>& T, int m, int rank, int q, const R* V, 
         }
         if ((int)threadIdx.x < nb) tb[threadIdx.x] = tau[sb - (int)threadIdx.x];
         __syncthreads();
+        // a wave whose lane groups hold none of the pass's columns (its first, p0 + its first
+        // group, is past the member's columns) skips the arithmetic; there is no barrier in it
+        if (p0 + (int)(threadIdx.x / WAVE) * (WAVE / PL) >= nloc) continue;
         for (int b = 0; b < nb; ++b) {
           const R* vr = vb + b * RR;
           const R tv = tb[b];
