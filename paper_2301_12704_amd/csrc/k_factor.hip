@@ -1863,6 +1863,13 @@ static int team_max() {
   return std::max(1, std::min(64, g));
 }
 
+// largest team of workgroups factoring one pivot block
+static int lu_team_max() {
+  const char* v = getenv("AIFMM_LU_TEAM_MAX");
+  int g = v && *v ? atoi(v) : 64;
+  return std::max(1, std::min(256, g));
+}
+
 // rows per lane of the compression's register column tier for boxes of up to cap rows: the
 // smallest compiled size holding cap rows in a 16-lane group, 0 (no register tier) beyond
 // 1024 rows or when switched off
@@ -2309,8 +2316,8 @@ static void factor_levels_multi(const std::vector<aifmm_system*>& S) {
       const int* bsys = bsys_all ? bsys_all + mb_off[c] : nullptr;
       hipLaunchKernelGGL(k_elim_gather, dim3(nbox, GS), dim3(WG), 0, st, PP, bsys, boxes, tws.p, tstride);
       {
-        // teams of up to 16 co-resident workgroups per pivot block
-        const int Gl = (lu_coop > 0) ? std::max(1, std::min(16, lu_coop / std::max(1, nbox))) : 1;
+        // teams of up to lu_team_max co-resident workgroups per pivot block
+        const int Gl = (lu_coop > 0) ? std::max(1, std::min(lu_team_max(), lu_coop / std::max(1, nbox))) : 1;
         int64_t dynb = lu_panels_off() ? 0 : (int64_t)lu_shm;  // bytes the panels may use
         unsigned* lctr = d_luctr.p;
         int* lst = d_lust.p;
